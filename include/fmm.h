@@ -1,0 +1,173 @@
+/*
+ * fmm.h -- C-ABI of the MI355X (gfx950) fast multipole library.
+ *
+ * The library evaluates, for N charged particles, the potentials and forces
+ * of the pairwise summation of Eq. (1) with the Laplace kernel of Eq. (2) of
+ * "Pipelining the Fast Multipole Method over a Runtime System" (Agullo et
+ * al.), using the black-box Chebyshev FMM of Sec. 2.1 (Eq. 3-5):
+ *
+ *     phi_i = sum_{j: r_ij > 0} q_j / r_ij
+ *     F_i   = q_i sum_{j: r_ij > 0} q_j (x_i - x_j) / r_ij^3   ( = -q_i grad phi )
+ *
+ * Pairs at zero distance, the particle itself included, contribute nothing.
+ * The octree has `height` levels 0..height-1 (leaf level height-1), cells in
+ * Morton order (Sec. 4.2); the root box is the cube anchored at the per-axis
+ * minimum of the positions whose side is the largest extent.  `order` is the
+ * number l of Chebyshev nodes per dimension (l^3 coefficients per cell; the
+ * paper's accuracy parameter Acc sets l = Acc, Sec. 2.1.2).
+ *
+ * Pointers: positions, charges, potential and forces are DEVICE pointers
+ * (for example the data of torch tensors on the current HIP device); the
+ * `host_dst` of fmm_plan_export and the `out` of fmm_plan_info are host
+ * pointers.  Layouts: positions [n][3] row-major float64; charges [n];
+ * potential [n]; forces [n][3].  Outputs are in input order and are
+ * overwritten, never accumulated.
+ *
+ * Errors: calls return FMM_OK (0) or a negative fmm_status; fmm_plan returns
+ * NULL.  fmm_last_error() gives a message for the calling thread's last
+ * failure.  No call aborts the process.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan_s* fmm_plan_t;
+
+enum fmm_status {
+  FMM_OK = 0,
+  FMM_ERR_ARG = -1,   /* invalid argument (checked before any device work) */
+  FMM_ERR_OOM = -2,   /* device allocation failed */
+  FMM_ERR_HIP = -3,   /* HIP runtime error */
+  FMM_ERR_STATE = -4  /* plan busy (evaluation still in flight elsewhere) */
+};
+
+enum fmm_precision {
+  /* every operator in FP64 (FP64 MFMA for M2L) */
+  FMM_FP64 = 0,
+  /* P2P in FP32 with leaf-local coordinates and per-source-leaf FP64 folding;
+   * M2L as FP32 MFMA contractions with FP32 accumulation folded into FP64 per
+   * far offset; P2M, M2M, L2L, L2P and the output sums stay FP64 */
+  FMM_MIXED_FP32 = 1
+};
+
+/*
+ * Build a plan (the octree, Sec. 3.2 and 4.2): root box, Morton keys, stable
+ * radix sort of the particles by (key, index), leaves, cells of every level,
+ * near lists (the up-to-27 leaves around each leaf) and far lists (children of
+ * the parent's near cells that are not adjacent, at most 189, Sec. 2.1.2),
+ * organised as MFMA tiles.  Also loads the cached per-order operators.
+ *   positions  device, [n][3] f64; read only, may be freed after return
+ *   n          1 .. 2^31-1
+ *   height     1 .. 21
+ *   order      1 .. 12
+ * Synchronous: runs on the null stream and waits for it (sizes depend on
+ * counts).  Returns NULL on error: FMM_ERR_ARG for bad sizes, a null pointer
+ * or non-finite positions; FMM_ERR_OOM; FMM_ERR_HIP.  The plan owns all its
+ * device memory; free it with fmm_release.  Precision defaults to FMM_FP64.
+ */
+fmm_plan_t fmm_plan(const double* positions, int64_t n, int height, int order);
+
+/* fmm_plan on a caller-chosen stream (still synchronous on that stream). */
+fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height,
+                           int order, hipStream_t stream);
+
+/*
+ * Evaluate potentials and forces for one set of charges (the FMM evaluation
+ * pass of Sec. 3.2: P2M, M2M upward; M2L, L2L, L2P downward; P2P near field;
+ * near and far sums combined in FP64).
+ *   charges    device [n] f64
+ *   potential  device [n] f64 (output)
+ *   forces     device [n][3] f64 (output)
+ *   stream     HIP stream all kernels are ordered on; returns immediately,
+ *              results are valid once the stream has reached this point.
+ * A plan must not be evaluated concurrently on two streams: a call while the
+ * previous evaluation on another stream is still running returns
+ * FMM_ERR_STATE.  Errors: FMM_ERR_ARG (null plan or pointer), FMM_ERR_HIP.
+ */
+int fmm_evaluate(fmm_plan_t plan, const double* charges, double* potential,
+                 double* forces, hipStream_t stream);
+
+/* Release a plan: waits for its in-flight evaluation, returns its device
+ * memory to the library's cache.  NULL-safe. */
+void fmm_release(fmm_plan_t plan);
+
+/* Message for the calling thread's most recent failure ("" if none). */
+const char* fmm_last_error(void);
+
+/* Select the arithmetic of later evaluations (enum fmm_precision). */
+int fmm_plan_set_precision(fmm_plan_t plan, int mode);
+
+/* Plan facts (host struct). */
+struct fmm_info {
+  int64_t n;
+  int32_t height, order, precision, ld;
+  int64_t n_leaf;
+  int64_t ncell[21];          /* cells per level */
+  double lo[3], L;            /* root box */
+  int64_t near_pairs;         /* directed (target, source) particle pairs in the
+                                 near field, zero-distance pairs included */
+  int64_t far_pairs;          /* (target cell, source cell) M2L pairs */
+  int64_t far_pairs_level[21];
+  int64_t m2l_tiles;          /* MFMA work tiles (64 target cells each) */
+  int64_t m2l_active_slots;   /* tile-offset pairs with at least one source */
+  int64_t device_bytes;       /* device memory held by the plan */
+};
+int fmm_plan_info(fmm_plan_t plan, struct fmm_info* out);
+
+/*
+ * Copy plan data to host memory, for checking.  `what`:
+ *   FMM_EXPORT_KEYS        uint64 [n]       sorted Morton keys
+ *   FMM_EXPORT_PERM        int64  [n]       sorted position -> input index
+ *   FMM_EXPORT_LEAF_START  int64  [n_leaf+1]
+ *   FMM_EXPORT_CELL_KEYS   uint64 [ncell[level]]
+ *   FMM_EXPORT_NEAR_OFF    int64  [n_leaf+1]  near lists as CSR, ascending
+ *   FMM_EXPORT_NEAR_IDX    int64  [near_off[n_leaf]]
+ *   FMM_EXPORT_FAR_OFF     int64  [ncell[level]+1] far lists (level >= 2) as
+ *   FMM_EXPORT_FAR_IDX     int64  [far_off[ncell]]  CSR of level-local indices,
+ *                                                   ascending
+ * `bytes` must be at least the size of the array; returns FMM_ERR_ARG
+ * otherwise.  Synchronous.
+ */
+enum fmm_export {
+  FMM_EXPORT_KEYS = 0,
+  FMM_EXPORT_PERM = 1,
+  FMM_EXPORT_LEAF_START = 2,
+  FMM_EXPORT_CELL_KEYS = 3,
+  FMM_EXPORT_NEAR_OFF = 4,
+  FMM_EXPORT_NEAR_IDX = 5,
+  FMM_EXPORT_FAR_OFF = 6,
+  FMM_EXPORT_FAR_IDX = 7
+};
+int fmm_plan_export(fmm_plan_t plan, int what, int level, void* host_dst,
+                    size_t bytes);
+
+/*
+ * Evaluate and return the near field (P2P) and far field (L2P of the local
+ * expansions) separately, in input order, for checking each operator chain.
+ * All pointers device, as in fmm_evaluate.
+ */
+int fmm_evaluate_parts(fmm_plan_t plan, const double* charges,
+                       double* phi_near, double* f_near, double* phi_far,
+                       double* f_far, hipStream_t stream);
+
+/*
+ * Time the M2L launches of subsequent evaluations on the calling thread:
+ * when ev0/ev1 are non-null, ev0 is recorded on the evaluation stream just
+ * before the M2L kernel and ev1 just after it.  Pass NULLs to stop.
+ */
+int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1);
+
+/* Return cached device memory of released plans to the HIP runtime. */
+void fmm_trim_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

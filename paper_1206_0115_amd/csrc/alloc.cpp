@@ -1,0 +1,96 @@
+// Caching device allocator.
+//
+// Plans are built and released repeatedly (one per charge-position set in a
+// serving loop), so device blocks are recycled instead of returned to the HIP
+// runtime: sizes are rounded to a size class (multiples of 256 B below 1 MiB,
+// otherwise 1/8 steps between powers of two) and kept in per-device free
+// lists.  On an allocation failure the cache is emptied and the allocation
+// retried once.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+struct Block {
+  size_t size;
+  int device;
+};
+
+std::mutex g_mu;
+std::multimap<std::pair<int, size_t>, void*> g_free;  // (device, size) -> ptr
+std::unordered_map<void*, Block> g_live;
+size_t g_cached = 0;
+
+size_t size_class(size_t b) {
+  if (b == 0) b = 1;
+  if (b < (1u << 20)) return (b + 255) & ~size_t(255);
+  size_t p = 1;
+  while ((p << 1) <= b) p <<= 1;
+  size_t step = p / 8;
+  return ((b + step - 1) / step) * step;
+}
+
+void release_all_locked() {
+  for (auto& kv : g_free) hipFree(kv.second);
+  g_free.clear();
+  g_cached = 0;
+}
+
+}  // namespace
+
+void* dev_alloc(size_t bytes) {
+  int dev = 0;
+  FMM_HIP_CHECK(hipGetDevice(&dev));
+  size_t sz = size_class(bytes);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_free.find({dev, sz});
+  if (it != g_free.end()) {
+    void* p = it->second;
+    g_free.erase(it);
+    g_cached -= sz;
+    g_live[p] = {sz, dev};
+    return p;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    release_all_locked();
+    e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw FmmError{FMM_ERR_OOM, "device allocation of " + std::to_string(sz) +
+                                      " bytes failed: " + hipGetErrorString(e)};
+    }
+  }
+  g_live[p] = {sz, dev};
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_live.find(p);
+  if (it == g_live.end()) return;
+  g_free.insert({{it->second.device, it->second.size}, p});
+  g_cached += it->second.size;
+  g_live.erase(it);
+}
+
+size_t dev_cached_bytes() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_cached;
+}
+
+void dev_trim() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  release_all_locked();
+}
+
+}  // namespace fmm

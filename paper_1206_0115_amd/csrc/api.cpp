@@ -1,0 +1,315 @@
+// C-ABI of the library: argument checks, plan lifecycle, export and errors.
+// Every argument check happens before the first HIP call, so invalid calls
+// fail the same way with or without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+thread_local std::string g_last_error;
+}
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace fmm
+
+void* fmm_plan_s::alloc(size_t b) {
+  void* p = fmm::dev_alloc(b);
+  blocks.push_back(p);
+  bytes += b;
+  return p;
+}
+
+fmm_plan_s::~fmm_plan_s() {
+  if (done) {
+    (void)hipEventSynchronize(done);
+    (void)hipEventDestroy(done);
+  }
+  for (void* p : blocks) fmm::dev_free(p);
+}
+
+namespace {
+
+int fail(int code, const std::string& msg) {
+  fmm::set_error(msg);
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const fmm::FmmError& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(FMM_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FMM_ERR_HIP, e.what());
+  }
+}
+
+// A plan is busy while an evaluation enqueued on another stream has not
+// finished.
+int check_idle(fmm_plan_s* p, hipStream_t s) {
+  (void)s;
+  if (p->in_flight && p->done) {
+    hipError_t e = hipEventQuery(p->done);
+    if (e == hipErrorNotReady) return FMM_ERR_STATE;
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return FMM_ERR_HIP;
+    }
+    p->in_flight = false;
+  }
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fmm_last_error(void) { return fmm::g_last_error.c_str(); }
+
+fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int order,
+                           hipStream_t stream) {
+  fmm::set_error("");
+  if (!positions) {
+    fail(FMM_ERR_ARG, "positions is NULL");
+    return nullptr;
+  }
+  if (n < 1 || n > int64_t(2147483646)) {
+    fail(FMM_ERR_ARG, "n must be in [1, 2^31-2], got " + std::to_string(n));
+    return nullptr;
+  }
+  if (height < 1 || height > fmm::kMaxHeight) {
+    fail(FMM_ERR_ARG, "height must be in [1, 21], got " + std::to_string(height));
+    return nullptr;
+  }
+  if (order < 1 || order > fmm::kMaxOrder) {
+    fail(FMM_ERR_ARG, "order must be in [1, 12], got " + std::to_string(order));
+    return nullptr;
+  }
+  fmm_plan_s* p = nullptr;
+  int rc = guarded([&]() -> int {
+    p = new fmm_plan_s();
+    FMM_HIP_CHECK(hipGetDevice(&p->device));
+    p->n = n;
+    p->height = height;
+    p->order = order;
+    p->ops = fmm::get_opset(order, stream);
+    fmm::build_plan(p, positions, stream);
+    const int ld = p->ops->ld;
+    const size_t rows = size_t(p->ncell_total + 1);
+    p->qs = static_cast<double*>(p->alloc(sizeof(double) * n));
+    p->phi_n = static_cast<double*>(p->alloc(sizeof(double) * n));
+    p->f_n = static_cast<double*>(p->alloc(sizeof(double) * 3 * n));
+    if (height >= 3) {
+      p->phi_f = static_cast<double*>(p->alloc(sizeof(double) * n));
+      p->f_f = static_cast<double*>(p->alloc(sizeof(double) * 3 * n));
+      p->W = static_cast<double*>(p->alloc(sizeof(double) * rows * ld));
+      p->Loc = static_cast<double*>(p->alloc(sizeof(double) * rows * ld));
+      // the row past the last cell is the zero source of absent M2L slots
+      FMM_HIP_CHECK(hipMemsetAsync(p->W + (rows - 1) * ld, 0, sizeof(double) * ld, stream));
+      FMM_HIP_CHECK(hipStreamSynchronize(stream));
+    }
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+    return FMM_OK;
+  });
+  if (rc != FMM_OK) {
+    delete p;
+    return nullptr;
+  }
+  return p;
+}
+
+fmm_plan_t fmm_plan(const double* positions, int64_t n, int height, int order) {
+  return fmm_plan_stream(positions, n, height, order, nullptr);
+}
+
+void fmm_release(fmm_plan_t plan) {
+  if (!plan) return;
+  delete plan;
+}
+
+int fmm_plan_set_precision(fmm_plan_t p, int mode) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (mode != FMM_FP64 && mode != FMM_MIXED_FP32)
+    return fail(FMM_ERR_ARG, "unknown precision mode " + std::to_string(mode));
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (mode == FMM_MIXED_FP32 && !p->W32 && p->height >= 3) {
+      if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
+      const size_t rows = size_t(p->ncell_total + 1);
+      p->W32 = static_cast<float*>(p->alloc(sizeof(float) * rows * p->ops->ld));
+    }
+    p->precision = mode;
+    return FMM_OK;
+  });
+}
+
+static int eval_common(fmm_plan_t p, const double* q, double* phi, double* f, double* pn,
+                       double* fn, double* pf, double* ff, hipStream_t s) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (!q) return fail(FMM_ERR_ARG, "charges is NULL");
+  if (phi == nullptr && pn == nullptr) return fail(FMM_ERR_ARG, "output is NULL");
+  if ((phi && !f) || (pn && (!fn || !pf || !ff))) return fail(FMM_ERR_ARG, "output is NULL");
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    int st = check_idle(p, s);
+    if (st == FMM_ERR_STATE) return fail(st, "plan is still evaluating on another stream");
+    if (st != FMM_OK) return fail(st, "event query failed");
+    int dev = 0;
+    FMM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev != p->device) return fail(FMM_ERR_ARG, "plan belongs to another device");
+    fmm::evaluate(p, q, phi, f, pn, fn, pf, ff, s);
+    FMM_HIP_CHECK(hipEventRecord(p->done, s));
+    p->in_flight = true;
+    return FMM_OK;
+  });
+}
+
+int fmm_evaluate(fmm_plan_t plan, const double* charges, double* potential, double* forces,
+                 hipStream_t stream) {
+  if (!potential || !forces) return fail(FMM_ERR_ARG, "output is NULL");
+  return eval_common(plan, charges, potential, forces, nullptr, nullptr, nullptr, nullptr,
+                     stream);
+}
+
+int fmm_evaluate_parts(fmm_plan_t plan, const double* charges, double* phi_near,
+                       double* f_near, double* phi_far, double* f_far, hipStream_t stream) {
+  if (!phi_near || !f_near || !phi_far || !f_far) return fail(FMM_ERR_ARG, "output is NULL");
+  return eval_common(plan, charges, nullptr, nullptr, phi_near, f_near, phi_far, f_far,
+                     stream);
+}
+
+int fmm_plan_info(fmm_plan_t p, struct fmm_info* out) {
+  if (!p || !out) return fail(FMM_ERR_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n = p->n;
+  out->height = p->height;
+  out->order = p->order;
+  out->precision = p->precision;
+  out->ld = p->ops ? p->ops->ld : 0;
+  out->n_leaf = p->nleaf;
+  for (int l = 0; l < p->height; ++l) out->ncell[l] = p->lev[l].ncell;
+  for (int d = 0; d < 3; ++d) out->lo[d] = p->lo[d];
+  out->L = p->L;
+  out->near_pairs = p->near_pairs;
+  out->far_pairs = p->far_pairs;
+  for (int l = 0; l < fmm::kMaxHeight; ++l) out->far_pairs_level[l] = p->far_pairs_level[l];
+  out->m2l_tiles = p->ntiles;
+  out->m2l_active_slots = p->active_slots;
+  out->device_bytes = int64_t(p->bytes);
+  return FMM_OK;
+}
+
+int fmm_plan_export(fmm_plan_t p, int what, int level, void* dst, size_t bytes) {
+  if (!p || !dst) return fail(FMM_ERR_ARG, "NULL argument");
+  auto need = [&](size_t b) { return bytes >= b; };
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int64_t n = p->n, nl = p->nleaf;
+    switch (what) {
+      case FMM_EXPORT_KEYS:
+        if (!need(sizeof(uint64_t) * n)) return fail(FMM_ERR_ARG, "buffer too small");
+        FMM_HIP_CHECK(hipMemcpy(dst, p->keys, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+        return FMM_OK;
+      case FMM_EXPORT_PERM: {
+        if (!need(sizeof(int64_t) * n)) return fail(FMM_ERR_ARG, "buffer too small");
+        std::vector<int> v(n);
+        FMM_HIP_CHECK(hipMemcpy(v.data(), p->perm, sizeof(int) * n, hipMemcpyDeviceToHost));
+        int64_t* o = static_cast<int64_t*>(dst);
+        for (int64_t i = 0; i < n; ++i) o[i] = v[i];
+        return FMM_OK;
+      }
+      case FMM_EXPORT_LEAF_START: {
+        if (!need(sizeof(int64_t) * (nl + 1))) return fail(FMM_ERR_ARG, "buffer too small");
+        std::vector<int> v(nl + 1);
+        FMM_HIP_CHECK(hipMemcpy(v.data(), p->leaf_start, sizeof(int) * (nl + 1),
+                                hipMemcpyDeviceToHost));
+        int64_t* o = static_cast<int64_t*>(dst);
+        for (int64_t i = 0; i <= nl; ++i) o[i] = v[i];
+        return FMM_OK;
+      }
+      case FMM_EXPORT_CELL_KEYS: {
+        if (level < 0 || level >= p->height) return fail(FMM_ERR_ARG, "bad level");
+        const int64_t c = p->lev[level].ncell;
+        if (!need(sizeof(uint64_t) * c)) return fail(FMM_ERR_ARG, "buffer too small");
+        FMM_HIP_CHECK(hipMemcpy(dst, p->lev[level].keys, sizeof(uint64_t) * c,
+                                hipMemcpyDeviceToHost));
+        return FMM_OK;
+      }
+      case FMM_EXPORT_NEAR_OFF:
+      case FMM_EXPORT_NEAR_IDX: {
+        std::vector<int> nr(27 * nl);
+        FMM_HIP_CHECK(hipMemcpy(nr.data(), p->near, sizeof(int) * 27 * nl,
+                                hipMemcpyDeviceToHost));
+        std::vector<int64_t> off(nl + 1, 0), idx;
+        for (int64_t a = 0; a < nl; ++a) {
+          std::vector<int64_t> row;
+          for (int s = 0; s < 27; ++s)
+            if (nr[27 * a + s] >= 0) row.push_back(nr[27 * a + s]);
+          std::sort(row.begin(), row.end());
+          idx.insert(idx.end(), row.begin(), row.end());
+          off[a + 1] = int64_t(idx.size());
+        }
+        const std::vector<int64_t>& v = what == FMM_EXPORT_NEAR_OFF ? off : idx;
+        if (!need(sizeof(int64_t) * v.size())) return fail(FMM_ERR_ARG, "buffer too small");
+        std::memcpy(dst, v.data(), sizeof(int64_t) * v.size());
+        return FMM_OK;
+      }
+      case FMM_EXPORT_FAR_OFF:
+      case FMM_EXPORT_FAR_IDX: {
+        if (level < 2 || level >= p->height) return fail(FMM_ERR_ARG, "bad level");
+        const int64_t nc = p->lev[level].ncell, off0 = p->lev[level].off;
+        std::vector<std::vector<int64_t>> rows(nc);
+        if (p->ntiles > 0) {
+          int64_t ntgt = 0;
+          for (int l = 2; l < p->height; ++l) ntgt += p->lev[l].ncell;
+          std::vector<int> tgt(ntgt), src(size_t(p->ntiles) * fmm::kSlots * fmm::kTileN);
+          FMM_HIP_CHECK(hipMemcpy(tgt.data(), p->tgt, sizeof(int) * ntgt, hipMemcpyDeviceToHost));
+          FMM_HIP_CHECK(hipMemcpy(src.data(), p->tile_src, sizeof(int) * src.size(),
+                                  hipMemcpyDeviceToHost));
+          for (int64_t t = 0; t < p->ntiles; ++t) {
+            const fmm::M2LTile& tl = p->tiles_host[t];
+            if (tl.level != level) continue;
+            for (int j = 0; j < tl.count; ++j) {
+              const int64_t c = tgt[tl.first + j] - off0;
+              for (int s = 0; s < fmm::kSlots; ++s) {
+                const int b = src[(t * fmm::kSlots + s) * fmm::kTileN + j];
+                if (b != int(p->ncell_total)) rows[c].push_back(b - off0);
+              }
+            }
+          }
+        }
+        std::vector<int64_t> off(nc + 1, 0), idx;
+        for (int64_t c = 0; c < nc; ++c) {
+          std::sort(rows[c].begin(), rows[c].end());
+          idx.insert(idx.end(), rows[c].begin(), rows[c].end());
+          off[c + 1] = int64_t(idx.size());
+        }
+        const std::vector<int64_t>& v = what == FMM_EXPORT_FAR_OFF ? off : idx;
+        if (!need(sizeof(int64_t) * v.size())) return fail(FMM_ERR_ARG, "buffer too small");
+        std::memcpy(dst, v.data(), sizeof(int64_t) * v.size());
+        return FMM_OK;
+      }
+      default:
+        return fail(FMM_ERR_ARG, "unknown export item");
+    }
+  });
+}
+
+int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1) {
+  if ((ev0 == nullptr) != (ev1 == nullptr)) return fail(FMM_ERR_ARG, "pass both events or none");
+  fmm::g_m2l_ev0 = ev0;
+  fmm::g_m2l_ev1 = ev1;
+  return FMM_OK;
+}
+
+void fmm_trim_cache(void) { fmm::dev_trim(); }
+
+}  // extern "C"

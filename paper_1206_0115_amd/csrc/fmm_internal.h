@@ -1,0 +1,150 @@
+// Internal declarations of the MI355X FMM library (not part of the C-ABI).
+//
+// Data layout in HBM (all device arrays, one plan):
+//   particles   sorted by (Morton key, input index); SoA px/py/pz (f64),
+//               prel (float4: leaf-local x,y,z + charge) for the FP32 near field
+//   cells       level-major "global cell ids": gid = lev_off[l] + i, i the
+//               Morton rank within level l; one extra all-zero row at
+//               gid = ncell_total stands in for absent M2L sources
+//   W, Loc      [ncell_total + 1][ld] f64, ld = 16 * ceil(l^3 / 16), the
+//               coefficient index (m1*l + m2)*l + m3, m1 along x
+//   near        [n_leaf][27] leaf ids (-1 if empty), fixed offset order
+//   M2L tiles   64 target cells of one level and one child parity; per tile
+//               [189][64] source gids (zero row if absent) and the list of
+//               slots with at least one source
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+constexpr int kMaxHeight = 21;
+constexpr int kMaxOrder = 12;
+constexpr int kTileN = 64;     // target cells per M2L tile
+constexpr int kSlots = 189;    // far offsets per child parity
+constexpr int kOffsets = 316;  // distinct far offsets
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+struct FmmError {
+  int code;
+  std::string msg;
+};
+#define FMM_HIP_CHECK(expr)                                                  \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      throw ::fmm::FmmError{e_ == hipErrorOutOfMemory ? FMM_ERR_OOM : FMM_ERR_HIP, \
+                            std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// ---------------------------------------------------------- device memory
+// Caching allocator: blocks are kept in per-device free lists by size class
+// and reused by later plans; hipMalloc only on a miss.
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+size_t dev_cached_bytes();
+void dev_trim();
+
+// ------------------------------------------------------ operator tables
+// Per-order tables shared by all plans on a device (built once, cached).
+struct OpSet {
+  int order = 0, l3 = 0, ld = 0, mt = 0, kc = 0;
+  double* cheb = nullptr;     // [l][l]: C[m][n] = (n==0 ? 1 : 2 T_n(xb_m)) / l
+  double* child = nullptr;    // [2][l][l]: S(xb_m; (s + xb_m')/2), s = -1, +1
+  double* kpack64 = nullptr;  // [316][mt][kc][64][4] unit M2L operators, MFMA order
+  float* kpack32 = nullptr;   // same in FP32
+  int* slot_kid = nullptr;    // [8][189] packed-operator index of each slot
+  signed char* slot_t = nullptr;  // [8][189][3] offset (tx, ty, tz) of each slot
+};
+const OpSet* get_opset(int order, hipStream_t stream);
+
+// ------------------------------------------------------------- the plan
+struct M2LTile {
+  int level;
+  int parity;
+  int first;  // index into tgt[] of the first target
+  int count;  // targets in this tile (<= kTileN)
+};
+
+struct LevelView {
+  int64_t ncell = 0;
+  int64_t off = 0;                // global id of the level's first cell
+  uint64_t* keys = nullptr;       // [ncell]
+  int* child_start = nullptr;     // [ncell+1], indices in level+1
+  int* parent = nullptr;          // [ncell], index in level-1
+  int* lookup = nullptr;          // dense table over keys (8^l entries) or null
+};
+
+}  // namespace fmm
+
+struct fmm_plan_s {
+  int device = 0;
+  int64_t n = 0;
+  int height = 0, order = 0, precision = FMM_FP64;
+  double lo[3] = {0, 0, 0}, L = 1.0;
+  const fmm::OpSet* ops = nullptr;
+
+  // particles
+  double *px = nullptr, *py = nullptr, *pz = nullptr;
+  float4* prel = nullptr;
+  int* perm = nullptr;
+  uint64_t* keys = nullptr;
+  int64_t nleaf = 0;
+  int* leaf_start = nullptr;
+  int* near = nullptr;
+
+  // cells
+  fmm::LevelView lev[fmm::kMaxHeight];
+  int64_t ncell_total = 0;
+
+  // M2L work
+  int64_t ntiles = 0;
+  fmm::M2LTile* tiles = nullptr;
+  int* tgt = nullptr;              // global ids of targets, grouped by (level, parity)
+  int* tile_src = nullptr;         // [ntiles][189][64]
+  unsigned char* tile_act = nullptr;  // [ntiles][189]
+  int* tile_nact = nullptr;        // [ntiles]
+  std::vector<fmm::M2LTile> tiles_host;
+
+  // statistics (exact counts)
+  int64_t near_pairs = 0;          // directed near interactions, self pairs included
+  int64_t far_pairs = 0;           // M2L (target, source) cell pairs
+  int64_t far_pairs_level[fmm::kMaxHeight] = {0};
+  int64_t active_slots = 0;        // sum over tiles of slots with a source
+
+  // evaluation buffers
+  double *qs = nullptr, *W = nullptr, *Loc = nullptr;
+  float* W32 = nullptr;
+  double *phi_n = nullptr, *f_n = nullptr, *phi_f = nullptr, *f_f = nullptr;
+
+  hipEvent_t done = nullptr;       // recorded after each evaluation
+  bool in_flight = false;
+  std::vector<void*> blocks;       // every device block this plan owns
+  size_t bytes = 0;
+  std::mutex mu;
+
+  void* alloc(size_t b);
+  ~fmm_plan_s();
+};
+
+namespace fmm {
+// plan construction (plan.hip)
+void build_plan(fmm_plan_s* p, const double* positions, hipStream_t stream);
+// evaluation (eval.hip)
+void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f,
+              double* phi_n, double* f_n, double* phi_f, double* f_f,
+              hipStream_t stream);
+// M2L launch (m2l.hip)
+void launch_m2l(fmm_plan_s* p, bool fp32, hipStream_t stream);
+// M2L timing hook: the last M2L launch is bracketed by these events when set
+extern thread_local hipEvent_t g_m2l_ev0, g_m2l_ev1;
+}  // namespace fmm

@@ -1,0 +1,466 @@
+// Operator tables and the M2L kernel.
+//
+// M2L (Sec. 2.1.2, Eq. 3): for a target cell C and a far source cell B at
+// level l, with centres differing by w_l t (t in [-3,3]^3, |t|_inf >= 2), the
+// local expansion gains K_{l,t} W_B where
+//     K_{l,t}[m][n] = 1 / |x_m - y_n| = 1 / |a_l (xb_m - xb_n - 2t)|,
+// a_l = L / 2^(l+1) the half-width.  1/r is homogeneous, so every level uses
+// the unit operators Kh_t[m][n] = 1 / |xb_m - xb_n - 2t| and one scalar
+// 1/a_l per level (Sec. 2.1.2: the 316 operators are computed once).
+// The 316 unit operators are signed permutations of 16 canonical ones
+// (Sec. 2.1.2): with t = G tc, (G v)_d = s_d v_{pi(d)},
+//     Kh_t[m][n] = Kh_tc[g(m)][g(n)],  g(m)_{pi(d)} = s_d > 0 ? m_d : l-1-m_d,
+// because the mirrored Chebyshev nodes satisfy xb_{l-1-k} = -xb_k.
+//
+// The contraction is organised target-stationary: a work tile holds 64
+// target cells of one level and one child parity, which share the same 189
+// offsets; for each offset the tile computes Y(l^3 x 64) += Kh_t (l^3 x l^3)
+// X(l^3 x 64) on MFMA, X the gathered source multipoles, and writes its local
+// expansions once (no atomics, deterministic).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "device_util.h"
+#include "fmm_internal.h"
+
+namespace fmm {
+
+thread_local hipEvent_t g_m2l_ev0 = nullptr, g_m2l_ev1 = nullptr;
+
+// ------------------------------------------------------------ tables
+namespace {
+
+struct OffsetInfo {
+  int t[3];
+  int canon;   // index into the 16 canonical offsets
+  int pi[3];   // t_d = s_d * tc[pi[d]]
+  int sg[3];
+};
+
+struct StaticTables {
+  std::vector<OffsetInfo> offs;        // the 316 far offsets (packed order)
+  std::vector<std::array<int, 3>> canon;  // 16 canonical offsets, tc0 >= tc1 >= tc2 >= 0
+  int id_to_kid[343];
+  std::vector<int> slot_kid;           // [8][189]
+  std::vector<signed char> slot_t;     // [8][189][3]
+};
+
+const StaticTables& tables() {
+  static StaticTables T = [] {
+    StaticTables S;
+    for (int i = 0; i < 343; ++i) S.id_to_kid[i] = -1;
+    std::map<std::array<int, 3>, int> cidx;
+    for (int tx = -3; tx <= 3; ++tx)
+      for (int ty = -3; ty <= 3; ++ty)
+        for (int tz = -3; tz <= 3; ++tz) {
+          const int t[3] = {tx, ty, tz};
+          int mx = 0;
+          for (int d = 0; d < 3; ++d) mx = std::max(mx, std::abs(t[d]));
+          if (mx < 2) continue;
+          OffsetInfo o;
+          int ord[3] = {0, 1, 2};
+          std::stable_sort(ord, ord + 3, [&](int a, int b) { return std::abs(t[a]) > std::abs(t[b]); });
+          std::array<int, 3> tc;
+          for (int j = 0; j < 3; ++j) {
+            tc[j] = std::abs(t[ord[j]]);
+            o.pi[ord[j]] = j;
+          }
+          for (int d = 0; d < 3; ++d) {
+            o.t[d] = t[d];
+            o.sg[d] = t[d] < 0 ? -1 : 1;
+          }
+          auto it = cidx.find(tc);
+          if (it == cidx.end()) {
+            it = cidx.emplace(tc, int(S.canon.size())).first;
+            S.canon.push_back(tc);
+          }
+          o.canon = it->second;
+          S.id_to_kid[(tx + 3) * 49 + (ty + 3) * 7 + (tz + 3)] = int(S.offs.size());
+          S.offs.push_back(o);
+        }
+    // per child parity p (bit d = parity of the cell coordinate along d):
+    // offsets with t_d in [-2-p_d, 3-p_d], lexicographic in (tx, ty, tz)
+    for (int p = 0; p < 8; ++p) {
+      int cnt = 0;
+      for (int tx = -3; tx <= 3; ++tx)
+        for (int ty = -3; ty <= 3; ++ty)
+          for (int tz = -3; tz <= 3; ++tz) {
+            const int t[3] = {tx, ty, tz};
+            bool ok = std::max({std::abs(tx), std::abs(ty), std::abs(tz)}) >= 2;
+            for (int d = 0; d < 3; ++d) {
+              const int pd = (p >> d) & 1;
+              ok = ok && t[d] >= -2 - pd && t[d] <= 3 - pd;
+            }
+            if (!ok) continue;
+            S.slot_kid.push_back(S.id_to_kid[(tx + 3) * 49 + (ty + 3) * 7 + (tz + 3)]);
+            for (int d = 0; d < 3; ++d) S.slot_t.push_back((signed char)t[d]);
+            ++cnt;
+          }
+      if (cnt != kSlots) throw FmmError{FMM_ERR_HIP, "internal: parity offset count"};
+    }
+    if (int(S.offs.size()) != kOffsets || S.canon.size() != 16)
+      throw FmmError{FMM_ERR_HIP, "internal: offset tables"};
+    return S;
+  }();
+  return T;
+}
+
+// Chebyshev roots of T_l, mirrored exactly (xb_{l-1-k} = -xb_k, 0 in the
+// middle for odd l).
+void cheb_nodes(int l, double* xi) {
+  for (int m = 0; m < l; ++m) xi[m] = std::cos((2.0 * m + 1.0) * M_PI / (2.0 * l));
+  for (int m = 0; m < l / 2; ++m) xi[l - 1 - m] = -xi[m];
+  if (l & 1) xi[l / 2] = 0.0;
+}
+
+void cheb_T(int l, double x, double* T) {
+  T[0] = 1.0;
+  if (l > 1) T[1] = x;
+  for (int n = 2; n < l; ++n) T[n] = 2.0 * x * T[n - 1] - T[n - 2];
+}
+
+// Canonical unit operators: Kc[c][m][n] = 1 / |xb_m - xb_n - 2 tc|
+__global__ void canon_kernel(const double* __restrict__ xi, const int* __restrict__ tc,
+                             int l, int ncanon, double* __restrict__ Kc) {
+  const int l3 = l * l * l;
+  const int64_t total = int64_t(ncanon) * l3 * l3;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int c = int(e / (int64_t(l3) * l3));
+    const int r = int(e % (int64_t(l3) * l3));
+    const int m = r / l3, n = r % l3;
+    const int m1 = m / (l * l), m2 = (m / l) % l, m3 = m % l;
+    const int n1 = n / (l * l), n2 = (n / l) % l, n3 = n % l;
+    const double dx = xi[m1] - xi[n1] - 2.0 * tc[3 * c];
+    const double dy = xi[m2] - xi[n2] - 2.0 * tc[3 * c + 1];
+    const double dz = xi[m3] - xi[n3] - 2.0 * tc[3 * c + 2];
+    Kc[e] = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+  }
+}
+
+// Pack the 316 operators in MFMA fragment order:
+//   kp[((kid*mt + i)*kc + c)*256 + lane*4 + s] = Kh_t[16 i + lane%16][16 c + 4 (lane/16) + s]
+// (zero outside l^3), gathering from the canonical operator through g.
+__global__ void pack_kernel(const double* __restrict__ Kc, const int* __restrict__ info,
+                            int l, int mt, int kc, double* __restrict__ kp64,
+                            float* __restrict__ kp32) {
+  const int l3 = l * l * l;
+  const int64_t total = int64_t(kOffsets) * mt * kc * 256;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int s = int(e & 3), lane = int((e >> 2) & 63);
+    int64_t r = e >> 8;
+    const int c = int(r % kc);
+    r /= kc;
+    const int i = int(r % mt);
+    const int kid = int(r / mt);
+    const int row = 16 * i + (lane & 15);
+    const int col = 16 * c + 4 * (lane >> 4) + s;
+    double v = 0.0;
+    if (row < l3 && col < l3) {
+      const int* in = info + 7 * kid;  // canon, pi[3], sg[3]
+      int mm[3] = {row / (l * l), (row / l) % l, row % l};
+      int nn[3] = {col / (l * l), (col / l) % l, col % l};
+      int gm[3], gn[3];
+      for (int d = 0; d < 3; ++d) {
+        gm[in[1 + d]] = in[4 + d] > 0 ? mm[d] : l - 1 - mm[d];
+        gn[in[1 + d]] = in[4 + d] > 0 ? nn[d] : l - 1 - nn[d];
+      }
+      const int gmi = (gm[0] * l + gm[1]) * l + gm[2];
+      const int gni = (gn[0] * l + gn[1]) * l + gn[2];
+      v = Kc[(int64_t(in[0]) * l3 + gmi) * l3 + gni];
+    }
+    kp64[e] = v;
+    kp32[e] = float(v);
+  }
+}
+
+std::mutex g_ops_mu;
+std::map<std::pair<int, int>, std::unique_ptr<OpSet>> g_ops;  // (device, order)
+
+}  // namespace
+
+const OpSet* get_opset(int l, hipStream_t s) {
+  int dev = 0;
+  FMM_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ops_mu);
+  auto it = g_ops.find({dev, l});
+  if (it != g_ops.end()) return it->second.get();
+  const StaticTables& T = tables();
+  auto op = std::make_unique<OpSet>();
+  op->order = l;
+  op->l3 = l * l * l;
+  op->mt = (op->l3 + 15) / 16;
+  op->kc = op->mt;
+  op->ld = 16 * op->mt;
+
+  double xi[kMaxOrder], Tm[kMaxOrder];
+  cheb_nodes(l, xi);
+  std::vector<double> cheb(l * l), child(2 * l * l);
+  for (int m = 0; m < l; ++m) {
+    cheb_T(l, xi[m], Tm);
+    for (int n = 0; n < l; ++n) cheb[m * l + n] = (n == 0 ? 1.0 : 2.0 * Tm[n]) / l;
+  }
+  // child-to-parent interpolation S(xb_m; (sigma + xb_m')/2), sigma = -1, +1
+  for (int sg = 0; sg < 2; ++sg)
+    for (int mp = 0; mp < l; ++mp) {
+      double Tu[kMaxOrder];
+      cheb_T(l, ((sg ? 1.0 : -1.0) + xi[mp]) / 2.0, Tu);
+      for (int m = 0; m < l; ++m) {
+        double v = 0.0;
+        for (int n = 0; n < l; ++n) v += cheb[m * l + n] * Tu[n];
+        child[(sg * l + m) * l + mp] = v;
+      }
+    }
+
+  std::vector<int> tc(3 * 16), info(7 * kOffsets);
+  for (int c = 0; c < 16; ++c)
+    for (int d = 0; d < 3; ++d) tc[3 * c + d] = T.canon[c][d];
+  for (int k = 0; k < kOffsets; ++k) {
+    const OffsetInfo& o = T.offs[k];
+    info[7 * k] = o.canon;
+    for (int d = 0; d < 3; ++d) {
+      info[7 * k + 1 + d] = o.pi[d];
+      info[7 * k + 4 + d] = o.sg[d];
+    }
+  }
+
+  std::vector<void*> tmp;
+  auto up = [&](const void* h, size_t b, bool keep) {
+    void* d = dev_alloc(b);
+    if (!keep) tmp.push_back(d);
+    FMM_HIP_CHECK(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, s));
+    return d;
+  };
+  try {
+    op->cheb = static_cast<double*>(up(cheb.data(), sizeof(double) * cheb.size(), true));
+    op->child = static_cast<double*>(up(child.data(), sizeof(double) * child.size(), true));
+    op->slot_kid = static_cast<int*>(up(T.slot_kid.data(), sizeof(int) * T.slot_kid.size(), true));
+    op->slot_t = static_cast<signed char*>(up(T.slot_t.data(), T.slot_t.size(), true));
+    double* xi_d = static_cast<double*>(up(xi, sizeof(double) * l, false));
+    int* tc_d = static_cast<int*>(up(tc.data(), sizeof(int) * tc.size(), false));
+    int* info_d = static_cast<int*>(up(info.data(), sizeof(int) * info.size(), false));
+    double* kc_d = static_cast<double*>(dev_alloc(sizeof(double) * 16 * size_t(op->l3) * op->l3));
+    tmp.push_back(kc_d);
+    const size_t npack = size_t(kOffsets) * op->mt * op->kc * 256;
+    op->kpack64 = static_cast<double*>(dev_alloc(sizeof(double) * npack));
+    op->kpack32 = static_cast<float*>(dev_alloc(sizeof(float) * npack));
+    canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, kc_d);
+    FMM_HIP_CHECK(hipGetLastError());
+    pack_kernel<<<4096, 256, 0, s>>>(kc_d, info_d, l, op->mt, op->kc, op->kpack64, op->kpack32);
+    FMM_HIP_CHECK(hipGetLastError());
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    for (void* q : tmp) dev_free(q);
+    throw;
+  }
+  for (void* q : tmp) dev_free(q);
+  const OpSet* r = op.get();
+  g_ops[{dev, l}] = std::move(op);
+  return r;
+}
+
+// ------------------------------------------------------------- M2L kernel
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+  typedef d4 type;
+};
+template <>
+struct Vec4<float> {
+  typedef f4 type;
+};
+
+__device__ inline d4 mfma16x16x4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+struct M2LArgs {
+  const M2LTile* tiles;
+  const int* tgt;
+  const int* tile_src;
+  const unsigned char* tile_act;
+  const int* tile_nact;
+  const int* slot_kid;
+  const void* kp;      // packed unit operators (T)
+  const void* W;       // multipoles (T), [ncell+1][ld]
+  double* Loc;         // local expansions (f64), [ncell+1][ld]
+  int mt, kc, ld, nmb, nblocks;
+  double scale[kMaxHeight];  // 1 / a_l
+};
+
+// One workgroup = 4 wavefronts = one (tile, M-block).  Wavefront w owns the
+// M-tiles [mt0, mt0 + MTW) of the output rows and all 64 target columns (four
+// 16-column N-tiles).  K-chunks of 16 coefficients = 4 MFMA k-steps; lane
+// group g = lane/16 holds k = 16c + 4g + s at step s, so both operands are
+// fetched as 4 consecutive values per lane.  FOLD: FP32 partial sums are
+// added into FP64 accumulators after every far offset.
+template <typename T, int MTW, bool FOLD>
+__global__ __launch_bounds__(256) void m2l_kernel(const M2LArgs a) {
+  typedef typename Vec4<T>::type T4;
+  // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+  // run of tiles so neighbouring tiles share source multipoles in its L2
+  int b = blockIdx.x;
+  const int n8 = (a.nblocks / 8) * 8;
+  if (b < n8) b = (b % 8) * (n8 / 8) + b / 8;
+  const int tile = b / a.nmb, mb = b % a.nmb;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int mt0 = (mb * 4 + wave) * MTW;
+  if (mt0 >= a.mt) return;
+  const int nmt = min(MTW, a.mt - mt0);
+  const M2LTile tl = a.tiles[tile];
+  const int g = lane >> 4, c16 = lane & 15;
+  const int KC = a.kc, ld = a.ld;
+  const T* __restrict__ Wp = static_cast<const T*>(a.W);
+  const T* __restrict__ Kp = static_cast<const T*>(a.kp);
+
+  T4 acc[MTW][4];
+  d4 acc64[FOLD ? MTW : 1][4];
+  for (int i = 0; i < MTW; ++i)
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = T4{0, 0, 0, 0};
+      if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
+    }
+
+  const int nact = a.tile_nact[tile];
+  const unsigned char* act = a.tile_act + int64_t(tile) * kSlots;
+  const int* srcb = a.tile_src + int64_t(tile) * kSlots * kTileN;
+  const int* kidp = a.slot_kid + tl.parity * kSlots;
+
+  for (int ia = 0; ia < nact; ++ia) {
+    const int s = act[ia];
+    const int kid = kidp[s];
+    const T* bptr[4];
+    for (int j = 0; j < 4; ++j)
+      bptr[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+    const T* aptr = Kp + (int64_t(kid) * a.mt + mt0) * KC * 256 + lane * 4;
+
+    T4 bv[4], av[MTW];
+    for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j]);
+    for (int i = 0; i < MTW; ++i)
+      av[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + int64_t(i) * KC * 256) : T4{0, 0, 0, 0};
+    for (int c = 0; c < KC; ++c) {
+      T4 bn[4], an[MTW];
+      const bool more = c + 1 < KC;
+      if (more) {
+        for (int j = 0; j < 4; ++j)
+          bn[j] = *reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1));
+        for (int i = 0; i < MTW; ++i)
+          an[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + (int64_t(i) * KC + c + 1) * 256)
+                          : T4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int i = 0; i < MTW; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
+      if (more) {
+        for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+        for (int i = 0; i < MTW; ++i) av[i] = an[i];
+      }
+    }
+    if (FOLD) {
+      for (int i = 0; i < MTW; ++i)
+        for (int j = 0; j < 4; ++j) {
+          for (int r = 0; r < 4; ++r) acc64[FOLD ? i : 0][j][r] += double(acc[i][j][r]);
+          acc[i][j] = T4{0, 0, 0, 0};
+        }
+    }
+  }
+
+  // D layout of the 16x16 outputs, column c16 in every lane group g: the
+  // FP32 instruction holds rows 4g+r in item r, the FP64 one rows 4r+g
+  // (both measured on gfx950).
+  const double sc = a.scale[tl.level];
+  const bool f64 = sizeof(T) == 8;
+  for (int j = 0; j < 4; ++j) {
+    const int col = 16 * j + c16;
+    if (col >= tl.count) continue;
+    double* out = a.Loc + int64_t(a.tgt[tl.first + col]) * ld;
+    for (int i = 0; i < nmt; ++i) {
+      const int base = 16 * (mt0 + i);
+      if (f64) {
+        for (int r = 0; r < 4; ++r)
+          out[base + 4 * r + g] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+      } else {
+        d4 v;
+        for (int r = 0; r < 4; ++r)
+          v[r] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+        *reinterpret_cast<d4*>(out + base + 4 * g) = v;
+      }
+    }
+  }
+}
+
+template <typename T, bool FOLD>
+static void launch_mtw(int mtw, const M2LArgs& a, int grid, hipStream_t s) {
+  switch (mtw) {
+    case 1: m2l_kernel<T, 1, FOLD><<<grid, 256, 0, s>>>(a); break;
+    case 2: m2l_kernel<T, 2, FOLD><<<grid, 256, 0, s>>>(a); break;
+    case 3: m2l_kernel<T, 3, FOLD><<<grid, 256, 0, s>>>(a); break;
+    default: m2l_kernel<T, 4, FOLD><<<grid, 256, 0, s>>>(a); break;
+  }
+}
+
+// M-tiles per wavefront: fewest idle M-tile slots, then the largest count
+// (fewest M-blocks, so the gathered source columns are read fewest times).
+static int pick_mtw(int mt) {
+  int best = 1, best_waste = 1 << 30;
+  for (int w = 1; w <= 4; ++w) {
+    const int per_block = 4 * w;
+    const int nmb = (mt + per_block - 1) / per_block;
+    const int waste = nmb * per_block - mt;
+    if (waste < best_waste || (waste == best_waste && w > best)) {
+      best = w;
+      best_waste = waste;
+    }
+  }
+  return best;
+}
+
+void launch_m2l(fmm_plan_s* p, bool fp32, hipStream_t s) {
+  if (p->ntiles == 0) return;
+  const OpSet* op = p->ops;
+  M2LArgs a;
+  a.tiles = p->tiles;
+  a.tgt = p->tgt;
+  a.tile_src = p->tile_src;
+  a.tile_act = p->tile_act;
+  a.tile_nact = p->tile_nact;
+  a.slot_kid = op->slot_kid;
+  a.kp = fp32 ? static_cast<const void*>(op->kpack32) : static_cast<const void*>(op->kpack64);
+  a.W = fp32 ? static_cast<const void*>(p->W32) : static_cast<const void*>(p->W);
+  a.Loc = p->Loc;
+  a.mt = op->mt;
+  a.kc = op->kc;
+  a.ld = op->ld;
+  for (int l = 0; l < kMaxHeight; ++l)
+    a.scale[l] = double(int64_t(1) << std::min(l + 1, 62)) / p->L;
+  const int mtw = pick_mtw(op->mt);
+  a.nmb = (op->mt + 4 * mtw - 1) / (4 * mtw);
+  a.nblocks = int(p->ntiles) * a.nmb;
+  if (g_m2l_ev0) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev0, s));
+  if (fp32)
+    launch_mtw<float, true>(mtw, a, a.nblocks, s);
+  else
+    launch_mtw<double, false>(mtw, a, a.nblocks, s);
+  FMM_HIP_CHECK(hipGetLastError());
+  if (g_m2l_ev1) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev1, s));
+}
+
+}  // namespace fmm

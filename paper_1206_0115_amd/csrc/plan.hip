@@ -1,0 +1,661 @@
+// Plan construction on the GPU: root box, Morton keys, stable LSD radix sort,
+// leaves and cells of every level, near lists and the M2L work tiles.
+//
+// The octree follows Sec. 3.2 (levels 0..h-1, leaf level h-1) with cells in
+// Morton order (Sec. 4.2); near and far lists follow Sec. 2.1.2 (27 near
+// cells, at most 189 far cells: children of the parent's near cells that are
+// not adjacent).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device_util.h"
+#include "fmm_internal.h"
+
+namespace fmm {
+
+// ------------------------------------------------------------------ scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T* lds_wave, T* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    T y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds_wave[wave] = x;
+  __syncthreads();
+  T base = 0, all = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) base += lds_wave[w];
+    all += lds_wave[w];
+  }
+  __syncthreads();
+  *total = all;
+  return base + x - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(
+    const T* __restrict__ in, T* __restrict__ out, T* __restrict__ sums,
+    int64_t n) {
+  __shared__ T lds[kScanThreads / 64];
+  const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+  T v[kScanItems];
+  T s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    v[k] = i < n ? in[i] : T(0);
+    s += v[k];
+  }
+  T total;
+  T run = block_exclusive_scan<T>(s, lds, &total);
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ void scan_add_kernel(T* __restrict__ out, const T* __restrict__ offs,
+                                int64_t n) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += offs[i / kScanTile];
+}
+
+// Exclusive scan of n values (in may equal out).  Temporary blocks are kept
+// in `tmp` and released by the caller after the stream has drained.
+template <typename T>
+void exclusive_scan(const T* in, T* out, int64_t n, hipStream_t s,
+                    std::vector<void*>& tmp) {
+  if (n <= 0) return;
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  T* sums = static_cast<T*>(dev_alloc(sizeof(T) * tiles));
+  tmp.push_back(sums);
+  scan_tiles_kernel<T><<<dim3(unsigned(tiles)), kScanThreads, 0, s>>>(in, out, sums, n);
+  FMM_HIP_CHECK(hipGetLastError());
+  if (tiles > 1) {
+    exclusive_scan<T>(sums, sums, tiles, s, tmp);
+    scan_add_kernel<T><<<dim3(unsigned((n + 255) / 256)), 256, 0, s>>>(out, sums, n);
+    FMM_HIP_CHECK(hipGetLastError());
+  }
+}
+
+// ------------------------------------------------------------- bounding box
+constexpr int kBoxBlocks = 512;
+
+__global__ __launch_bounds__(256) void bbox_partial_kernel(
+    const double* __restrict__ pos, int64_t n, double* __restrict__ part,
+    int* __restrict__ bad) {
+  __shared__ double smin[3][256], smax[3][256];
+  double mn[3] = {INFINITY, INFINITY, INFINITY};
+  double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int nonfinite = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * 256) {
+    for (int d = 0; d < 3; ++d) {
+      double v = pos[3 * i + d];
+      if (!isfinite(v)) nonfinite = 1;
+      mn[d] = fmin(mn[d], v);
+      mx[d] = fmax(mx[d], v);
+    }
+  }
+  if (nonfinite) atomicOr(bad, 1);
+  for (int d = 0; d < 3; ++d) {
+    smin[d][threadIdx.x] = mn[d];
+    smax[d][threadIdx.x] = mx[d];
+  }
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int d = 0; d < 3; ++d) {
+        smin[d][threadIdx.x] = fmin(smin[d][threadIdx.x], smin[d][threadIdx.x + o]);
+        smax[d][threadIdx.x] = fmax(smax[d][threadIdx.x], smax[d][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int d = 0; d < 3; ++d) {
+      part[6 * blockIdx.x + d] = smin[d][0];
+      part[6 * blockIdx.x + 3 + d] = smax[d][0];
+    }
+}
+
+__global__ void bbox_final_kernel(const double* __restrict__ part, int nb,
+                                  double* __restrict__ out) {
+  if (threadIdx.x >= 6) return;
+  const int d = threadIdx.x;
+  double v = d < 3 ? INFINITY : -INFINITY;
+  for (int b = 0; b < nb; ++b) v = d < 3 ? fmin(v, part[6 * b + d]) : fmax(v, part[6 * b + d]);
+  out[d] = v;
+}
+
+// -------------------------------------------------------------- Morton keys
+// k_d = min(floor((x_d - lo_d) / L * 2^(h-1)), 2^(h-1) - 1): IEEE divide, an
+// exact scaling by a power of two and floor -- no contraction is possible.
+__global__ void keys_kernel(const double* __restrict__ pos, int64_t n,
+                            double lo0, double lo1, double lo2, double L,
+                            int bits, uint64_t* __restrict__ keys,
+                            int* __restrict__ idx) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double side = double(int64_t(1) << bits);
+  const int64_t kmax = (int64_t(1) << bits) - 1;
+  const double lo[3] = {lo0, lo1, lo2};
+  uint32_t k3[3];
+  for (int d = 0; d < 3; ++d) {
+    double u = (pos[3 * i + d] - lo[d]) / L;
+    int64_t k = int64_t(floor(u * side));
+    k = k > kmax ? kmax : (k < 0 ? 0 : k);
+    k3[d] = uint32_t(k);
+  }
+  keys[i] = morton3(k3[0], k3[1], k3[2], bits);
+  idx[i] = int(i);
+}
+
+// ------------------------------------------------------- stable radix sort
+// LSD radix sort of (key, value) pairs, 8-bit digits.  Stability (equal keys
+// keep input order) is what makes the permutation unique: ties are ordered by
+// input index.  Per pass: tile histograms, one exclusive scan over the
+// digit-major histogram, then a scatter that ranks equal digits in input
+// order with wavefront ballots.
+constexpr int kRsThreads = 256;
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kRsThreads * kRsItems;
+
+__global__ __launch_bounds__(kRsThreads) void radix_hist_kernel(
+    const uint64_t* __restrict__ keys, int64_t n, int shift, int mask,
+    int ntiles, int* __restrict__ hist) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kRsTile;
+  for (int it = 0; it < kRsItems; ++it) {
+    int64_t i = base + int64_t(it) * kRsThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[int((keys[i] >> shift) & uint64_t(mask))], 1);
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void radix_scatter_kernel(
+    const uint64_t* __restrict__ kin, const int* __restrict__ vin,
+    uint64_t* __restrict__ kout, int* __restrict__ vout, int64_t n, int shift,
+    int mask, int ntiles, const int* __restrict__ offs) {
+  __shared__ int base_d[256];
+  __shared__ int wcnt[kRsThreads / 64][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  base_d[tid] = offs[int64_t(tid) * ntiles + blockIdx.x];
+  const uint64_t lt = (uint64_t(1) << lane) - 1;
+  const int64_t tbase = int64_t(blockIdx.x) * kRsTile;
+  for (int it = 0; it < kRsItems; ++it) {
+    for (int k = lane; k < 256; k += 64) wcnt[wave][k] = 0;
+    const int64_t i = tbase + int64_t(it) * kRsThreads + tid;
+    const bool valid = i < n;
+    uint64_t key = valid ? kin[i] : 0;
+    int val = valid ? vin[i] : 0;
+    const int d = valid ? int((key >> shift) & uint64_t(mask)) : 0;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const int rank = __popcll(peers & lt);
+    __syncthreads();
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    {
+      int run = base_d[tid];
+      for (int w = 0; w < kRsThreads / 64; ++w) {
+        int c = wcnt[w][tid];
+        wcnt[w][tid] = run;
+        run += c;
+      }
+      base_d[tid] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const int p = wcnt[wave][d] + rank;
+      kout[p] = key;
+      vout[p] = val;
+    }
+    __syncthreads();
+  }
+}
+
+// Sorts n pairs by the digits of (key >> shift) & mask over `bits` bits.
+// Returns the buffers holding the result (either the inputs or the outputs).
+static void radix_sort(uint64_t*& k, int*& v, uint64_t*& k2, int*& v2,
+                       int64_t n, int bits, hipStream_t s,
+                       std::vector<void*>& tmp) {
+  if (n <= 1 || bits <= 0) return;
+  const int ntiles = ceil_div(n, kRsTile);
+  int* hist = static_cast<int*>(dev_alloc(sizeof(int) * 256 * size_t(ntiles)));
+  tmp.push_back(hist);
+  for (int shift = 0; shift < bits; shift += 8) {
+    const int db = std::min(8, bits - shift);
+    const int mask = (1 << db) - 1;
+    radix_hist_kernel<<<ntiles, kRsThreads, 0, s>>>(k, n, shift, mask, ntiles, hist);
+    FMM_HIP_CHECK(hipGetLastError());
+    exclusive_scan<int>(hist, hist, int64_t(256) * ntiles, s, tmp);
+    radix_scatter_kernel<<<ntiles, kRsThreads, 0, s>>>(k, v, k2, v2, n, shift, mask,
+                                                       ntiles, hist);
+    FMM_HIP_CHECK(hipGetLastError());
+    std::swap(k, k2);
+    std::swap(v, v2);
+  }
+}
+
+// ------------------------------------------------------------- segments
+// Unique values of (keys >> shift) over a sorted array: segment flags, their
+// exclusive scan, then the unique keys, each segment's first index, and the
+// segment of every element.
+__global__ void seg_flags_kernel(const uint64_t* __restrict__ keys, int64_t m,
+                                 int shift, int* __restrict__ flags) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  flags[i] = (i == 0 || (keys[i] >> shift) != (keys[i - 1] >> shift)) ? 1 : 0;
+}
+
+__global__ void seg_emit_kernel(const uint64_t* __restrict__ keys, int64_t m,
+                                int shift, const int* __restrict__ flags,
+                                const int* __restrict__ pos,
+                                uint64_t* __restrict__ ukeys,
+                                int* __restrict__ first, int* __restrict__ seg) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int id = pos[i] + flags[i] - 1;
+  if (seg) seg[i] = id;
+  if (flags[i]) {
+    ukeys[id] = keys[i] >> shift;
+    first[id] = int(i);
+  }
+}
+
+__global__ void seg_count_kernel(const int* __restrict__ flags,
+                                 const int* __restrict__ pos, int64_t m,
+                                 int* __restrict__ count) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *count = pos[m - 1] + flags[m - 1];
+}
+
+__global__ void set_int_kernel(int* __restrict__ p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// ------------------------------------------------------------ gathers
+__global__ void gather_pos_kernel(const double* __restrict__ pos,
+                                  const int* __restrict__ perm, int64_t n,
+                                  double* __restrict__ px, double* __restrict__ py,
+                                  double* __restrict__ pz) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = perm[i];
+  px[i] = pos[3 * j];
+  py[i] = pos[3 * j + 1];
+  pz[i] = pos[3 * j + 2];
+}
+
+// Leaf-local FP32 coordinates for the FP32 near field: x - c_leaf.
+__global__ void rel_coords_kernel(const double* __restrict__ px,
+                                  const double* __restrict__ py,
+                                  const double* __restrict__ pz,
+                                  const int* __restrict__ leaf_start,
+                                  const uint64_t* __restrict__ leaf_keys,
+                                  int64_t nleaf, int bits, double lo0,
+                                  double lo1, double lo2, double w,
+                                  float4* __restrict__ prel) {
+  const int64_t a = blockIdx.x;
+  if (a >= nleaf) return;
+  int c[3];
+  demorton3(leaf_keys[a], bits, c);
+  const double cx = lo0 + (c[0] + 0.5) * w, cy = lo1 + (c[1] + 0.5) * w,
+               cz = lo2 + (c[2] + 0.5) * w;
+  for (int i = leaf_start[a] + threadIdx.x; i < leaf_start[a + 1]; i += blockDim.x)
+    prel[i] = make_float4(float(px[i] - cx), float(py[i] - cy), float(pz[i] - cz), 0.f);
+}
+
+// ---------------------------------------------------------- lookup tables
+__global__ void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void table_scatter_kernel(const uint64_t* __restrict__ keys,
+                                     int64_t nc, int* __restrict__ table) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < nc) table[keys[i]] = int(i);
+}
+
+// ------------------------------------------------------------ near lists
+// near[a][s], s = (dx+1)*9 + (dy+1)*3 + (dz+1): the leaf at offset (dx,dy,dz)
+// or -1.  Also counts directed particle pairs n_a * sum_b n_b.
+__global__ void near_kernel(LevelDev leaves, const int* __restrict__ leaf_start,
+                            int* __restrict__ near,
+                            unsigned long long* __restrict__ pairs) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long cnt = 0;
+  if (a < leaves.ncell) {
+    int c[3];
+    demorton3(leaves.keys[a], leaves.bits, c);
+    long long src = 0;
+    for (int s = 0; s < 27; ++s) {
+      const int b = level_find_xyz(leaves, c[0] + s / 9 - 1, c[1] + (s / 3) % 3 - 1,
+                                   c[2] + s % 3 - 1);
+      near[27 * a + s] = b;
+      if (b >= 0) src += leaf_start[b + 1] - leaf_start[b];
+    }
+    cnt = (unsigned long long)(leaf_start[a + 1] - leaf_start[a]) * (unsigned long long)src;
+  }
+  for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(pairs, cnt);
+}
+
+// ------------------------------------------------------------ M2L tiles
+__global__ void parity_count_kernel(const uint64_t* __restrict__ keys,
+                                    int64_t nc, int* __restrict__ counts) {
+  __shared__ int h[8];
+  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < nc) atomicAdd(&h[int(keys[i] & 7u)], 1);
+  __syncthreads();
+  if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void iota_kernel(int* __restrict__ p, int64_t n, int base) {
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = base + int(i);
+}
+
+// One wavefront per tile.  Lane j owns target j; for each of the parity's
+// 189 offsets it finds the source cell (zero row if absent); slots with at
+// least one source are listed in order.
+__global__ __launch_bounds__(64) void tile_src_kernel(
+    const M2LTile* __restrict__ tiles, const int* __restrict__ tgt,
+    const LevelDev* __restrict__ levels, const int64_t* __restrict__ lev_off,
+    const signed char* __restrict__ slot_t,  // [8][189][3]
+    int zero_row, int* __restrict__ tile_src, unsigned char* __restrict__ act,
+    int* __restrict__ nact, unsigned long long* __restrict__ pairs_level) {
+  const int tile = blockIdx.x, j = threadIdx.x;
+  const M2LTile T = tiles[tile];
+  const LevelDev L = levels[T.level];
+  int c[3] = {0, 0, 0};
+  const bool have = j < T.count;
+  if (have) {
+    const int local = tgt[T.first + j] - int(lev_off[T.level]);
+    demorton3(L.keys[local], L.bits, c);
+  }
+  int na = 0;
+  unsigned long long npairs = 0;
+  int* out = tile_src + int64_t(tile) * kSlots * kTileN;
+  for (int s = 0; s < kSlots; ++s) {
+    const signed char* t = slot_t + (T.parity * kSlots + s) * 3;
+    int b = -1;
+    if (have) b = level_find_xyz(L, c[0] + t[0], c[1] + t[1], c[2] + t[2]);
+    out[s * kTileN + j] = b >= 0 ? b + int(lev_off[T.level]) : zero_row;
+    const uint64_t m = __ballot(b >= 0);
+    if (m) {
+      if (j == 0) act[int64_t(tile) * kSlots + na] = (unsigned char)s;
+      ++na;
+      npairs += __popcll(m);
+    }
+  }
+  if (j == 0) {
+    nact[tile] = na;
+    atomicAdd(&pairs_level[T.level], npairs);
+  }
+}
+
+// --------------------------------------------------------------- driver
+static inline unsigned grid_for(int64_t n, int b) { return unsigned((n + b - 1) / b); }
+
+void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
+  std::vector<void*> tmp;
+  struct TmpGuard {
+    std::vector<void*>& v;
+    hipStream_t s;
+    ~TmpGuard() {
+      (void)hipStreamSynchronize(s);
+      for (void* q : v) dev_free(q);
+    }
+  } guard{tmp, s};
+  auto talloc = [&](size_t b) {
+    void* q = dev_alloc(b);
+    tmp.push_back(q);
+    return q;
+  };
+
+  const int64_t n = p->n;
+  const int h = p->height;
+  const int bits = h - 1;
+
+  // --- root box (the only input-dependent host decision) ---
+  const int nb = int(std::min<int64_t>(kBoxBlocks, (n + 255) / 256));
+  double* part = static_cast<double*>(talloc(sizeof(double) * 6 * nb + 64));
+  double* box = static_cast<double*>(talloc(sizeof(double) * 8));
+  int* bad = static_cast<int*>(talloc(sizeof(int)));
+  FMM_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
+  bbox_partial_kernel<<<nb, 256, 0, s>>>(pos, n, part, bad);
+  FMM_HIP_CHECK(hipGetLastError());
+  bbox_final_kernel<<<1, 64, 0, s>>>(part, nb, box);
+  FMM_HIP_CHECK(hipGetLastError());
+  double hb[6];
+  int hbad = 0;
+  FMM_HIP_CHECK(hipMemcpyAsync(hb, box, sizeof(hb), hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipStreamSynchronize(s));
+  if (hbad) throw FmmError{FMM_ERR_ARG, "positions contain NaN or Inf"};
+  double L = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    p->lo[d] = hb[d];
+    L = std::max(L, hb[3 + d] - hb[d]);
+  }
+  if (L == 0.0) L = 1.0;
+  p->L = L;
+
+  // --- keys and the stable sort ---
+  uint64_t* k1 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * n));
+  uint64_t* k2 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * n));
+  int* v1 = static_cast<int*>(talloc(sizeof(int) * n));
+  int* v2 = static_cast<int*>(talloc(sizeof(int) * n));
+  keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(pos, n, p->lo[0], p->lo[1], p->lo[2], L,
+                                               bits, k1, v1);
+  FMM_HIP_CHECK(hipGetLastError());
+  radix_sort(k1, v1, k2, v2, n, 3 * bits, s, tmp);
+
+  p->keys = static_cast<uint64_t*>(p->alloc(sizeof(uint64_t) * n));
+  p->perm = static_cast<int*>(p->alloc(sizeof(int) * n));
+  FMM_HIP_CHECK(hipMemcpyAsync(p->keys, k1, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+  FMM_HIP_CHECK(hipMemcpyAsync(p->perm, v1, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+  p->px = static_cast<double*>(p->alloc(sizeof(double) * n));
+  p->py = static_cast<double*>(p->alloc(sizeof(double) * n));
+  p->pz = static_cast<double*>(p->alloc(sizeof(double) * n));
+  gather_pos_kernel<<<grid_for(n, 256), 256, 0, s>>>(pos, p->perm, n, p->px, p->py, p->pz);
+  FMM_HIP_CHECK(hipGetLastError());
+
+  // --- leaves and coarser levels ---
+  int* flags = static_cast<int*>(talloc(sizeof(int) * n));
+  int* scn = static_cast<int*>(talloc(sizeof(int) * n));
+  int* cnt_d = static_cast<int*>(talloc(sizeof(int) * 4));
+  auto unique = [&](const uint64_t* keys, int64_t m, int shift, uint64_t* ukeys,
+                    int* first, int* seg) -> int64_t {
+    seg_flags_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys, m, shift, flags);
+    FMM_HIP_CHECK(hipGetLastError());
+    exclusive_scan<int>(flags, scn, m, s, tmp);
+    seg_emit_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys, m, shift, flags, scn, ukeys,
+                                                     first, seg);
+    FMM_HIP_CHECK(hipGetLastError());
+    seg_count_kernel<<<1, 64, 0, s>>>(flags, scn, m, cnt_d);
+    FMM_HIP_CHECK(hipGetLastError());
+    int c = 0;
+    FMM_HIP_CHECK(hipMemcpyAsync(&c, cnt_d, sizeof(int), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    set_int_kernel<<<1, 64, 0, s>>>(first + c, int(m));
+    FMM_HIP_CHECK(hipGetLastError());
+    return c;
+  };
+
+  uint64_t* lk = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * n));
+  int* ls = static_cast<int*>(talloc(sizeof(int) * (n + 1)));
+  p->nleaf = unique(p->keys, n, 0, lk, ls, nullptr);
+  const int64_t nl = p->nleaf;
+  p->leaf_start = static_cast<int*>(p->alloc(sizeof(int) * (nl + 1)));
+  FMM_HIP_CHECK(hipMemcpyAsync(p->leaf_start, ls, sizeof(int) * (nl + 1),
+                               hipMemcpyDeviceToDevice, s));
+  LevelView* lev = p->lev;
+  lev[h - 1].ncell = nl;
+  lev[h - 1].keys = static_cast<uint64_t*>(p->alloc(sizeof(uint64_t) * nl));
+  FMM_HIP_CHECK(hipMemcpyAsync(lev[h - 1].keys, lk, sizeof(uint64_t) * nl,
+                               hipMemcpyDeviceToDevice, s));
+  for (int l = h - 2; l >= 0; --l) {
+    const int64_t m = lev[l + 1].ncell;
+    lev[l + 1].parent = static_cast<int*>(p->alloc(sizeof(int) * m));
+    int* cs = static_cast<int*>(talloc(sizeof(int) * (m + 1)));
+    uint64_t* uk = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * m));
+    const int64_t c = unique(lev[l + 1].keys, m, 3, uk, cs, lev[l + 1].parent);
+    lev[l].ncell = c;
+    lev[l].keys = static_cast<uint64_t*>(p->alloc(sizeof(uint64_t) * c));
+    lev[l].child_start = static_cast<int*>(p->alloc(sizeof(int) * (c + 1)));
+    FMM_HIP_CHECK(hipMemcpyAsync(lev[l].keys, uk, sizeof(uint64_t) * c,
+                                 hipMemcpyDeviceToDevice, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(lev[l].child_start, cs, sizeof(int) * (c + 1),
+                                 hipMemcpyDeviceToDevice, s));
+  }
+  int64_t off = 0;
+  for (int l = 0; l < h; ++l) {
+    lev[l].off = off;
+    off += lev[l].ncell;
+  }
+  p->ncell_total = off;
+  if (off >= (int64_t(1) << 31) - 1) throw FmmError{FMM_ERR_ARG, "too many cells"};
+
+  // dense lookup tables for levels with at most 2^24 key slots
+  LevelDev ldev[kMaxHeight];
+  for (int l = 0; l < h; ++l) {
+    ldev[l] = {lev[l].keys, nullptr, int(lev[l].ncell), l};
+    if (3 * l <= 24) {
+      const int64_t slots = int64_t(1) << (3 * l);
+      lev[l].lookup = static_cast<int*>(p->alloc(sizeof(int) * slots));
+      fill_int_kernel<<<grid_for(slots, 256), 256, 0, s>>>(lev[l].lookup, slots, -1);
+      table_scatter_kernel<<<grid_for(lev[l].ncell, 256), 256, 0, s>>>(
+          lev[l].keys, lev[l].ncell, lev[l].lookup);
+      FMM_HIP_CHECK(hipGetLastError());
+      ldev[l].table = lev[l].lookup;
+    }
+  }
+
+  // --- near lists ---
+  unsigned long long* counters =
+      static_cast<unsigned long long*>(talloc(sizeof(unsigned long long) * (kMaxHeight + 2)));
+  FMM_HIP_CHECK(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * (kMaxHeight + 2), s));
+  p->near = static_cast<int*>(p->alloc(sizeof(int) * 27 * nl));
+  near_kernel<<<grid_for(nl, 256), 256, 0, s>>>(ldev[h - 1], p->leaf_start, p->near,
+                                                counters + kMaxHeight);
+  FMM_HIP_CHECK(hipGetLastError());
+
+  // --- leaf-local FP32 coordinates ---
+  p->prel = static_cast<float4*>(p->alloc(sizeof(float4) * n));
+  rel_coords_kernel<<<unsigned(nl), 64, 0, s>>>(p->px, p->py, p->pz, p->leaf_start,
+                                               lev[h - 1].keys, nl, bits, p->lo[0],
+                                               p->lo[1], p->lo[2],
+                                               L / double(int64_t(1) << bits), p->prel);
+  FMM_HIP_CHECK(hipGetLastError());
+
+  // --- M2L tiles: targets of each level >= 2 grouped by child parity ---
+  if (h >= 3) {
+    int64_t ntgt = 0;
+    for (int l = 2; l < h; ++l) ntgt += lev[l].ncell;
+    p->tgt = static_cast<int*>(p->alloc(sizeof(int) * ntgt));
+    int* pc = static_cast<int*>(talloc(sizeof(int) * 8 * kMaxHeight));
+    FMM_HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(int) * 8 * kMaxHeight, s));
+    for (int l = 2; l < h; ++l)
+      parity_count_kernel<<<grid_for(lev[l].ncell, 256), 256, 0, s>>>(
+          lev[l].keys, lev[l].ncell, pc + 8 * l);
+    FMM_HIP_CHECK(hipGetLastError());
+    int hpc[8 * kMaxHeight];
+    FMM_HIP_CHECK(hipMemcpyAsync(hpc, pc, sizeof(hpc), hipMemcpyDeviceToHost, s));
+    // stable partition by parity = one radix pass over the low 3 key bits
+    int64_t tbase = 0;
+    std::vector<M2LTile> tiles;
+    std::vector<int64_t> tgt_base(h, 0);
+    for (int l = 2; l < h; ++l) {
+      const int64_t m = lev[l].ncell;
+      uint64_t* pk1 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * m));
+      uint64_t* pk2 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * m));
+      int* pv1 = static_cast<int*>(talloc(sizeof(int) * m));
+      int* pv2 = static_cast<int*>(talloc(sizeof(int) * m));
+      FMM_HIP_CHECK(hipMemcpyAsync(pk1, lev[l].keys, sizeof(uint64_t) * m,
+                                   hipMemcpyDeviceToDevice, s));
+      iota_kernel<<<grid_for(m, 256), 256, 0, s>>>(pv1, m, int(lev[l].off));
+      FMM_HIP_CHECK(hipGetLastError());
+      radix_sort(pk1, pv1, pk2, pv2, m, 3, s, tmp);
+      FMM_HIP_CHECK(hipMemcpyAsync(p->tgt + tbase, pv1, sizeof(int) * m,
+                                   hipMemcpyDeviceToDevice, s));
+      tgt_base[l] = tbase;
+      tbase += m;
+    }
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    // finest level first: the largest tiles' work is scheduled before the
+    // coarse levels fill in the tail
+    for (int l = h - 1; l >= 2; --l) {
+      int64_t start = tgt_base[l];
+      for (int par = 0; par < 8; ++par) {
+        const int c = hpc[8 * l + par];
+        for (int k = 0; k < c; k += kTileN)
+          tiles.push_back({l, par, int(start + k), std::min(kTileN, c - k)});
+        start += c;
+      }
+    }
+    p->ntiles = int64_t(tiles.size());
+    p->tiles_host = tiles;
+    if (p->ntiles > 0) {
+      p->tiles = static_cast<M2LTile*>(p->alloc(sizeof(M2LTile) * tiles.size()));
+      FMM_HIP_CHECK(hipMemcpyAsync(p->tiles, tiles.data(), sizeof(M2LTile) * tiles.size(),
+                                   hipMemcpyHostToDevice, s));
+      p->tile_src = static_cast<int*>(p->alloc(sizeof(int) * size_t(p->ntiles) * kSlots * kTileN));
+      p->tile_act = static_cast<unsigned char*>(p->alloc(size_t(p->ntiles) * kSlots));
+      p->tile_nact = static_cast<int*>(p->alloc(sizeof(int) * p->ntiles));
+      LevelDev* ld_d = static_cast<LevelDev*>(talloc(sizeof(LevelDev) * kMaxHeight));
+      int64_t* off_d = static_cast<int64_t*>(talloc(sizeof(int64_t) * kMaxHeight));
+      int64_t offs_h[kMaxHeight];
+      for (int l = 0; l < kMaxHeight; ++l) offs_h[l] = l < h ? lev[l].off : 0;
+      FMM_HIP_CHECK(hipMemcpyAsync(ld_d, ldev, sizeof(LevelDev) * kMaxHeight,
+                                   hipMemcpyHostToDevice, s));
+      FMM_HIP_CHECK(hipMemcpyAsync(off_d, offs_h, sizeof(offs_h), hipMemcpyHostToDevice, s));
+      tile_src_kernel<<<unsigned(p->ntiles), 64, 0, s>>>(
+          p->tiles, p->tgt, ld_d, off_d, p->ops->slot_t,
+          int(p->ncell_total), p->tile_src, p->tile_act, p->tile_nact, counters);
+      FMM_HIP_CHECK(hipGetLastError());
+    }
+  }
+
+  // --- statistics ---
+  unsigned long long hc[kMaxHeight + 2];
+  FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipStreamSynchronize(s));
+  p->near_pairs = int64_t(hc[kMaxHeight]);
+  p->far_pairs = 0;
+  for (int l = 0; l < kMaxHeight; ++l) {
+    p->far_pairs_level[l] = int64_t(hc[l]);
+    p->far_pairs += int64_t(hc[l]);
+  }
+  if (p->ntiles > 0) {
+    std::vector<int> na(p->ntiles);
+    FMM_HIP_CHECK(hipMemcpy(na.data(), p->tile_nact, sizeof(int) * p->ntiles,
+                            hipMemcpyDeviceToHost));
+    p->active_slots = 0;
+    for (int v : na) p->active_slots += v;
+  }
+}
+
+}  // namespace fmm

@@ -1,0 +1,215 @@
+"""Python binding of ``libfmm.so`` (the C-ABI in ``include/fmm.h``).
+
+Argument marshalling only: tensors are checked for device, dtype and shape
+and their device pointers are passed to the library, whose HIP kernels do
+every step of the computation.  There is no fallback: if the library is not
+built the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm.so")
+
+FMM_OK, FMM_ERR_ARG, FMM_ERR_OOM, FMM_ERR_HIP, FMM_ERR_STATE = 0, -1, -2, -3, -4
+FMM_FP64, FMM_MIXED_FP32 = 0, 1
+PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED_FP32}
+
+EXPORT_KEYS, EXPORT_PERM, EXPORT_LEAF_START, EXPORT_CELL_KEYS = 0, 1, 2, 3
+EXPORT_NEAR_OFF, EXPORT_NEAR_IDX, EXPORT_FAR_OFF, EXPORT_FAR_IDX = 4, 5, 6, 7
+
+
+class FMMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class FmmInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("height", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("ld", ctypes.c_int32),
+        ("n_leaf", ctypes.c_int64),
+        ("ncell", ctypes.c_int64 * 21),
+        ("lo", ctypes.c_double * 3), ("L", ctypes.c_double),
+        ("near_pairs", ctypes.c_int64),
+        ("far_pairs", ctypes.c_int64),
+        ("far_pairs_level", ctypes.c_int64 * 21),
+        ("m2l_tiles", ctypes.c_int64),
+        ("m2l_active_slots", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1206_0115_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    L.fmm_plan.argtypes = [vp, i64, i32, i32]
+    L.fmm_plan.restype = vp
+    L.fmm_plan_stream.argtypes = [vp, i64, i32, i32, vp]
+    L.fmm_plan_stream.restype = vp
+    L.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp]
+    L.fmm_evaluate_parts.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.fmm_release.argtypes = [vp]
+    L.fmm_release.restype = None
+    L.fmm_last_error.restype = ctypes.c_char_p
+    L.fmm_plan_set_precision.argtypes = [vp, i32]
+    L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
+    L.fmm_plan_export.argtypes = [vp, i32, i32, vp, sz]
+    L.fmm_set_m2l_timing_events.argtypes = [vp, vp]
+    L.fmm_trim_cache.restype = None
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().fmm_last_error().decode()
+
+
+def _check(rc):
+    if rc != FMM_OK:
+        raise FMMError(rc, last_error())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _dev_f64(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An FMM plan over fixed particle positions (``fmm_plan``)."""
+
+    def __init__(self, positions, height: int, order: int, precision="fp64", stream=None):
+        self.n = int(positions.shape[0])
+        ptr = _dev_f64(positions, (self.n, 3), "positions")
+        if stream is None:
+            h = lib().fmm_plan(ptr, self.n, int(height), int(order))
+        else:
+            h = lib().fmm_plan_stream(ptr, self.n, int(height), int(order),
+                                      _stream_handle(stream))
+        if not h:
+            raise FMMError(FMM_ERR_ARG, last_error())
+        self._h = ctypes.c_void_p(h)
+        self.height, self.order = int(height), int(order)
+        self.set_precision(precision)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_precision(self, precision):
+        mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(lib().fmm_plan_set_precision(self._h, mode))
+        self.precision = mode
+
+    def evaluate(self, charges, potential=None, forces=None, stream=None):
+        import torch
+        q = _dev_f64(charges, (self.n,), "charges")
+        if potential is None:
+            potential = torch.empty(self.n, dtype=torch.float64, device=charges.device)
+        if forces is None:
+            forces = torch.empty(self.n, 3, dtype=torch.float64, device=charges.device)
+        _check(lib().fmm_evaluate(self._h, q, _dev_f64(potential, (self.n,), "potential"),
+                                  _dev_f64(forces, (self.n, 3), "forces"),
+                                  _stream_handle(stream)))
+        return potential, forces
+
+    def evaluate_parts(self, charges, stream=None):
+        import torch
+        q = _dev_f64(charges, (self.n,), "charges")
+        dev = charges.device
+        pn = torch.empty(self.n, dtype=torch.float64, device=dev)
+        fn = torch.empty(self.n, 3, dtype=torch.float64, device=dev)
+        pf = torch.empty(self.n, dtype=torch.float64, device=dev)
+        ff = torch.empty(self.n, 3, dtype=torch.float64, device=dev)
+        _check(lib().fmm_evaluate_parts(self._h, q, ctypes.c_void_p(pn.data_ptr()),
+                                        ctypes.c_void_p(fn.data_ptr()),
+                                        ctypes.c_void_p(pf.data_ptr()),
+                                        ctypes.c_void_p(ff.data_ptr()),
+                                        _stream_handle(stream)))
+        return pn, fn, pf, ff
+
+    def info(self) -> FmmInfo:
+        out = FmmInfo()
+        _check(lib().fmm_plan_info(self._h, ctypes.byref(out)))
+        return out
+
+    def export(self, what: int, level: int = 0) -> np.ndarray:
+        inf = self.info()
+        if what == EXPORT_KEYS:
+            out = np.empty(self.n, dtype=np.uint64)
+        elif what == EXPORT_PERM:
+            out = np.empty(self.n, dtype=np.int64)
+        elif what in (EXPORT_LEAF_START, EXPORT_NEAR_OFF):
+            out = np.empty(inf.n_leaf + 1, dtype=np.int64)
+        elif what == EXPORT_CELL_KEYS:
+            out = np.empty(inf.ncell[level], dtype=np.uint64)
+        elif what == EXPORT_NEAR_IDX:
+            off = self.export(EXPORT_NEAR_OFF)
+            out = np.empty(int(off[-1]), dtype=np.int64)
+        elif what == EXPORT_FAR_OFF:
+            out = np.empty(inf.ncell[level] + 1, dtype=np.int64)
+        elif what == EXPORT_FAR_IDX:
+            off = self.export(EXPORT_FAR_OFF, level)
+            out = np.empty(int(off[-1]), dtype=np.int64)
+        else:
+            raise ValueError("unknown export item")
+        _check(lib().fmm_plan_export(self._h, what, level,
+                                     out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    def release(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fmm_release(h)
+        self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+def set_m2l_timing_events(ev0, ev1):
+    """Bracket the M2L kernel of later evaluations on this thread with two
+    ``torch.cuda.Event`` objects (or None to stop)."""
+    if ev0 is None:
+        _check(lib().fmm_set_m2l_timing_events(None, None))
+        return
+    _check(lib().fmm_set_m2l_timing_events(ctypes.c_void_p(ev0.cuda_event),
+                                           ctypes.c_void_p(ev1.cuda_event)))
+
+
+def trim_cache():
+    lib().fmm_trim_cache()

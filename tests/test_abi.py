@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every call declared in include/fmm.h and
+rejects invalid arguments before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1206_0115_amd import fmm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(fmm_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_call():
+    lib = fmm.lib()
+    names = declared_functions()
+    assert "fmm_plan" in names and "fmm_evaluate" in names and "fmm_release" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_plan_rejects_bad_arguments_without_device():
+    lib = fmm.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: checks come first
+    assert not lib.fmm_plan(None, 10, 3, 5)
+    assert "NULL" in fmm.last_error()
+    assert not lib.fmm_plan(fake, 0, 3, 5)
+    assert "n must be" in fmm.last_error()
+    assert not lib.fmm_plan(fake, 10, 0, 5)
+    assert not lib.fmm_plan(fake, 10, 22, 5)
+    assert "height" in fmm.last_error()
+    assert not lib.fmm_plan(fake, 10, 3, 0)
+    assert not lib.fmm_plan(fake, 10, 3, 13)
+    assert "order" in fmm.last_error()
+
+
+def test_calls_reject_null_plan():
+    lib = fmm.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.fmm_evaluate(None, fake, fake, fake, None) == fmm.FMM_ERR_ARG
+    assert lib.fmm_evaluate_parts(None, fake, fake, fake, fake, fake, None) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_set_precision(None, 0) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_info(None, None) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_export(None, 0, 0, fake, 8) == fmm.FMM_ERR_ARG
+    assert lib.fmm_set_m2l_timing_events(fake, None) == fmm.FMM_ERR_ARG
+    lib.fmm_release(None)  # NULL-safe
+
+
+def test_info_struct_layout_matches_header():
+    src = open(os.path.join(ROOT, "include", "fmm.h")).read()
+    body = src[src.index("struct fmm_info {"):]
+    body = body[:body.index("};")]
+    fields = re.findall(r"(int64_t|int32_t|double)\s+([^;]+);", body)
+    names = []
+    for _, decl in fields:
+        for part in decl.split(","):
+            names.append(re.sub(r"\[.*\]", "", part).strip())
+    assert names == [f[0] for f in fmm.FmmInfo._fields_]
