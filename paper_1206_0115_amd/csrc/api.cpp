@@ -53,10 +53,9 @@ int guarded(F&& f) {
 }
 
 // A plan is busy while an evaluation enqueued on another stream has not
-// finished.
+// finished; evaluations queued on the same stream are ordered by it.
 int check_idle(fmm_plan_s* p, hipStream_t s) {
-  (void)s;
-  if (p->in_flight && p->done) {
+  if (p->in_flight && p->done && s != p->last_stream) {
     hipError_t e = hipEventQuery(p->done);
     if (e == hipErrorNotReady) return FMM_ERR_STATE;
     if (e != hipSuccess) {
@@ -168,6 +167,7 @@ static int eval_common(fmm_plan_t p, const double* q, double* phi, double* f, do
     fmm::evaluate(p, q, phi, f, pn, fn, pf, ff, s);
     FMM_HIP_CHECK(hipEventRecord(p->done, s));
     p->in_flight = true;
+    p->last_stream = s;
     return FMM_OK;
   });
 }

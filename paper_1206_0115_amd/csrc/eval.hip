@@ -326,15 +326,18 @@ __global__ __launch_bounds__(64) void p2p_f64_kernel(
   }
 }
 
-// FP32 near field: coordinates relative to each particle's own leaf centre,
-// so a pair's difference is (xr_i - o) - xr_j with o = (k_b - k_a) w the
-// exact offset between leaf centres; rsqrt is v_rsq_f32; partial sums over
-// one source leaf are kept in FP32 and folded into FP64 accumulators.
+// FP32 near field.  The pair difference is taken in FP64 (full rate on this
+// chip) and rounded once, so it carries a relative error of 2^-24 of the
+// distance itself however close the pair is; r^2, rsqrt (v_rsq_f32) and the
+// products are FP32; partial sums over one source leaf are kept in FP32 and
+// folded into FP64 accumulators.
 __global__ __launch_bounds__(64) void p2p_f32_kernel(
-    const float4* __restrict__ prel, const double* __restrict__ qs,
-    const int* __restrict__ leaf_start, const int* __restrict__ near, float w,
-    double* __restrict__ phi, double* __restrict__ f) {
-  __shared__ float4 src[64];
+    const double* __restrict__ px, const double* __restrict__ py,
+    const double* __restrict__ pz, const float4* __restrict__ prel,
+    const int* __restrict__ leaf_start, const int* __restrict__ near,
+    const double* __restrict__ qs, double* __restrict__ phi, double* __restrict__ f) {
+  __shared__ double sx[64], sy[64], sz[64];
+  __shared__ float sq[64];
   const int a = blockIdx.x, lane = threadIdx.x;
   const int t0 = leaf_start[a], nt = leaf_start[a + 1] - t0;
   const int P = p2p_groups(nt);
@@ -343,27 +346,29 @@ __global__ __launch_bounds__(64) void p2p_f32_kernel(
   for (int tb = 0; tb < nt; tb += 64) {
     const int ti = tb + (lane % P);
     const bool valid = ti < nt;
-    const float4 me = prel[t0 + (valid ? ti : 0)];
+    const int it = t0 + (valid ? ti : 0);
+    const double xi = px[it], yi = py[it], zi = pz[it];
     double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     for (int sl = 0; sl < 27; ++sl) {
       const int b = near[27 * a + sl];
       if (b < 0) continue;
-      const float ox = float(sl / 9 - 1) * w, oy = float((sl / 3) % 3 - 1) * w,
-                  oz = float(sl % 3 - 1) * w;
-      const float xi = me.x - ox, yi = me.y - oy, zi = me.z - oz;
       const int j0 = leaf_start[b], j1 = leaf_start[b + 1];
       float p32 = 0.f, x32 = 0.f, y32 = 0.f, z32 = 0.f;
       for (int jb = j0; jb < j1; jb += 64) {
         const int cnt = min(64, j1 - jb);
         __syncthreads();
-        if (lane < cnt) src[lane] = prel[jb + lane];
+        if (lane < cnt) {
+          sx[lane] = px[jb + lane];
+          sy[lane] = py[jb + lane];
+          sz[lane] = pz[jb + lane];
+          sq[lane] = prel[jb + lane].w;
+        }
         __syncthreads();
         for (int k = split; k < cnt; k += S) {
-          const float4 s = src[k];
-          const float dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+          const float dx = float(xi - sx[k]), dy = float(yi - sy[k]), dz = float(zi - sz[k]);
           const float r2 = dx * dx + dy * dy + dz * dz;
           const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-          const float qir = s.w * ir;
+          const float qir = sq[k] * ir;
           p32 += qir;
           const float s3 = qir * ir * ir;
           x32 += s3 * dx;
@@ -515,8 +520,8 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   }
 
   if (mixed)
-    p2p_f32_kernel<<<unsigned(nl), 64, 0, s>>>(p->prel, p->qs, p->leaf_start, p->near,
-                                               float(geo.w), p->phi_n, p->f_n);
+    p2p_f32_kernel<<<unsigned(nl), 64, 0, s>>>(p->px, p->py, p->pz, p->prel, p->leaf_start,
+                                               p->near, p->qs, p->phi_n, p->f_n);
   else
     p2p_f64_kernel<<<unsigned(nl), 64, 0, s>>>(p->px, p->py, p->pz, p->qs, p->leaf_start,
                                                p->near, p->phi_n, p->f_n);

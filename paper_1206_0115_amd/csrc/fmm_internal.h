@@ -128,6 +128,7 @@ struct fmm_plan_s {
 
   hipEvent_t done = nullptr;       // recorded after each evaluation
   bool in_flight = false;
+  hipStream_t last_stream = nullptr;  // stream of the last evaluation
   std::vector<void*> blocks;       // every device block this plan owns
   size_t bytes = 0;
   std::mutex mu;

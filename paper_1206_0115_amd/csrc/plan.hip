@@ -130,13 +130,24 @@ __global__ __launch_bounds__(256) void bbox_partial_kernel(
     }
 }
 
-__global__ void bbox_final_kernel(const double* __restrict__ part, int nb,
-                                  double* __restrict__ out) {
-  if (threadIdx.x >= 6) return;
-  const int d = threadIdx.x;
-  double v = d < 3 ? INFINITY : -INFINITY;
-  for (int b = 0; b < nb; ++b) v = d < 3 ? fmin(v, part[6 * b + d]) : fmax(v, part[6 * b + d]);
-  out[d] = v;
+__global__ __launch_bounds__(256) void bbox_final_kernel(const double* __restrict__ part,
+                                                         int nb, double* __restrict__ out) {
+  __shared__ double s[256];
+  for (int d = 0; d < 6; ++d) {
+    double v = d < 3 ? INFINITY : -INFINITY;
+    for (int b = threadIdx.x; b < nb; b += 256)
+      v = d < 3 ? fmin(v, part[6 * b + d]) : fmax(v, part[6 * b + d]);
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o)
+        s[threadIdx.x] = d < 3 ? fmin(s[threadIdx.x], s[threadIdx.x + o])
+                               : fmax(s[threadIdx.x], s[threadIdx.x + o]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[d] = s[0];
+    __syncthreads();
+  }
 }
 
 // -------------------------------------------------------------- Morton keys
@@ -447,7 +458,7 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   FMM_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int), s));
   bbox_partial_kernel<<<nb, 256, 0, s>>>(pos, n, part, bad);
   FMM_HIP_CHECK(hipGetLastError());
-  bbox_final_kernel<<<1, 64, 0, s>>>(part, nb, box);
+  bbox_final_kernel<<<1, 256, 0, s>>>(part, nb, box);
   FMM_HIP_CHECK(hipGetLastError());
   double hb[6];
   int hbad = 0;
