@@ -84,6 +84,92 @@ def cpu_baseline(kind, n, h, l, seed, budget_s):
                       f"plan+evaluate in {dt:.1f}s"}
 
 
+def serve_height(pos, target=64.0):
+    """Height whose non-empty leaves hold closest to `target` particles."""
+    lo = pos.min(axis=0)
+    L = float((pos.max(axis=0) - lo).max()) or 1.0
+    best, best_d = 2, None
+    for h in range(2, 9):
+        side = 2 ** (h - 1)
+        k = np.minimum(np.floor((pos - lo) / L * side), side - 1).astype(np.int64)
+        occ = len(pos) / len(np.unique((k[:, 0] * side + k[:, 1]) * side + k[:, 2]))
+        d = abs(np.log(occ) - np.log(target))
+        if best_d is None or d < best_d:
+            best, best_d = h, d
+    return best
+
+
+def run_serve(args):
+    """Serving loop under a Poisson request stream: N log-uniform in
+    [1e4, 2e6], cube or sphere 50/50, order in {3, 5, 7, 9}, height for about
+    64 particles per leaf.  Latency p50/p99 and throughput at several loads,
+    against the same requests run one at a time."""
+    import torch
+
+    from paper_1206_0115_amd import fmm, inputs
+
+    fmm.lib()
+    rng = np.random.default_rng(1004)
+    reqs = []
+    for i in range(args.requests):
+        n = int(np.exp(rng.uniform(np.log(1e4), np.log(2e6))))
+        kind = "cube" if rng.random() < 0.5 else "sphere"
+        l = int(rng.choice([3, 5, 7, 9]))
+        pos, q = inputs.make(kind, n, 10_000 + i)
+        h = serve_height(pos)
+        reqs.append((torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda(), h, l, n))
+    torch.cuda.synchronize()
+    total_n = sum(r[4] for r in reqs)
+    srv = fmm.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_active=32)
+    prec = args.serve_precision
+
+    # warm the operator caches and graphs
+    for r in reqs[:8]:
+        srv.submit(r[0], r[1], r[2], r[3], prec).wait()
+    # one at a time
+    service = []
+    for r in reqs:
+        st = srv.submit(r[0], r[1], r[2], r[3], prec).wait()
+        assert st.status == fmm.FMM_OK, fmm.last_error()
+        service.append(st.done_s - st.submit_s)
+    service = np.array(service)
+    mean_s = float(service.mean())
+    out = {"metric": "served particles/s (potential+force), p50/p99 latency",
+           "unit": "particles/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "poisson_serving", "requests": len(reqs),
+                      "N": "log-uniform [1e4, 2e6]", "orders": [3, 5, 7, 9],
+                      "kinds": "cube/sphere 50/50", "leaf_target": 64,
+                      "precision": prec, "budget_gb": args.serve_budget_gb},
+           "one_at_a_time": {"particles_per_s": round(total_n / float(service.sum()), 1),
+                             "mean_service_ms": round(1e3 * mean_s, 3),
+                             "p50_ms": round(1e3 * float(np.percentile(service, 50)), 3),
+                             "p99_ms": round(1e3 * float(np.percentile(service, 99)), 3)},
+           "loads": []}
+    for rho in (0.5, 0.8, 0.95, 2.0):
+        lam = rho / mean_s
+        gaps = rng.exponential(1.0 / lam, len(reqs))
+        t0 = srv.now()
+        arrivals = t0 + np.cumsum(gaps)
+        tickets = []
+        for r, ta in zip(reqs, arrivals):
+            while srv.now() < ta:
+                pass
+            tickets.append(srv.submit(r[0], r[1], r[2], r[3], prec))
+        sts = [t.wait() for t in tickets]
+        assert all(s.status == fmm.FMM_OK for s in sts)
+        lat = np.array([s.done_s - s.submit_s for s in sts])
+        span = max(s.done_s for s in sts) - min(s.submit_s for s in sts)
+        out["loads"].append({"rho": rho, "offered_req_per_s": round(lam, 2),
+                             "particles_per_s": round(total_n / span, 1),
+                             "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3)})
+    s = srv.stats()
+    out["server"] = {k: int(getattr(s, k)) for k, _ in fmm.ServerStats._fields_}
+    srv.close()
+    out["value"] = max(x["particles_per_s"] for x in out["loads"])
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +179,11 @@ def main():
     ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--serve", action="store_true",
+                    help="benchmark the serving loop instead (Poisson request stream)")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-precision", default="mixed", choices=["fp64", "mixed"])
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,6 +192,10 @@ def main():
             print("bench.py measures one GPU only: this FMM build has no multi-GPU path "
                   f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        run_serve(args)
+        return
 
     import torch
 

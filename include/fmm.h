@@ -167,6 +167,70 @@ int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1);
 /* Return cached device memory of released plans to the HIP runtime. */
 void fmm_trim_cache(void);
 
+/*
+ * Serving loop: a device-resident request loop that evaluates many particle
+ * sets of different size and order concurrently (continuous batching).  A
+ * worker thread plans arriving requests on its own stream, admits them while
+ * the sum of their plans' device footprints stays within `hbm_budget_bytes`
+ * and at most `max_active` are admitted, and evaluates the admitted requests
+ * in batches: each operator of the evaluation pass (Sec. 3.2's P2M, M2M, M2L,
+ * L2L, L2P, P2P) runs as one persistent launch over the work items of every
+ * request in the batch (requests of equal order share the M2L, P2M and L2P
+ * launches), and a batch's launch sequence is captured once as a hipGraph and
+ * replayed with new work tables.  Requests that arrive while batches run are
+ * planned meanwhile and join the next batch as memory frees up.  A request's
+ * results are bit-identical to fmm_evaluate on the same inputs.
+ */
+typedef struct fmm_server_s* fmm_server_t;
+
+struct fmm_request_stats {
+  int32_t status;       /* FMM_OK, or the error that ended the request */
+  int32_t done;         /* 1 once the results are in the output buffers */
+  double submit_s;      /* times in seconds on the server's monotonic clock */
+  double admit_s;
+  double done_s;
+  int64_t batch;        /* batch index the request ran in */
+  int64_t plan_bytes;   /* device footprint admitted for it */
+};
+
+struct fmm_server_stats {
+  int64_t submitted, completed, rejected, batches;
+  int64_t graph_captures, graph_replays;
+  int64_t max_batch_jobs, max_active_seen;
+  int64_t peak_admitted_bytes;
+};
+
+/* Create a server on the current device.  hbm_budget_bytes > 0, 1 <= max_active
+ * <= 64.  Returns NULL on error (FMM_ERR_ARG / FMM_ERR_HIP). */
+fmm_server_t fmm_server_create(size_t hbm_budget_bytes, int max_active);
+
+/*
+ * Queue one evaluation.  positions [n][3], charges [n], potential [n] and
+ * forces [n][3] are device pointers that the caller keeps valid and untouched
+ * until the request is done.  height, order as for fmm_plan; precision an
+ * fmm_precision.  Returns a ticket >= 0, or a negative fmm_status for invalid
+ * arguments (checked before anything is queued).  A request whose plan alone
+ * exceeds the budget finishes with status FMM_ERR_OOM.
+ */
+int64_t fmm_server_submit(fmm_server_t srv, const double* positions, const double* charges,
+                          int64_t n, int height, int order, int precision,
+                          double* potential, double* forces);
+
+/* Non-blocking: 1 if the request is done (its status in st->status), 0 if not,
+ * FMM_ERR_ARG for an unknown ticket.  `st` may be NULL. */
+int fmm_server_poll(fmm_server_t srv, int64_t ticket, struct fmm_request_stats* st);
+
+/* Block until the request is done; returns its status. */
+int fmm_server_wait(fmm_server_t srv, int64_t ticket, struct fmm_request_stats* st);
+
+/* Seconds on the server's clock (the clock of the request times). */
+double fmm_server_now(fmm_server_t srv);
+
+int fmm_server_get_stats(fmm_server_t srv, struct fmm_server_stats* out);
+
+/* Finish every queued request, then stop the worker and free the server. */
+void fmm_server_destroy(fmm_server_t srv);
+
 #ifdef __cplusplus
 }
 #endif

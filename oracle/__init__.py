@@ -75,6 +75,8 @@ def _load():
     lib.oracle_tree_far.argtypes = [ctypes.c_void_p, ctypes.c_int, _pi64, _pi64]
     lib.oracle_fmm.argtypes = [ctypes.c_void_p, ctypes.c_int, _pd, _pi64, _i64,
                                _pd, _pd, _pd, _pd, _pd, _pd]
+    lib.oracle_fmm_ops.argtypes = [ctypes.c_void_p, ctypes.c_int, _pd, _pi64, _i64, _pd,
+                                   _pd, _pd, _pd, _pd, _pd, _pd]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
     _lib = lib
@@ -260,9 +262,15 @@ class Tree:
         lib.oracle_tree_far(self._h, level, _ptr(off, _pi64), _ptr(idx, _pi64))
         return off, idx
 
-    def fmm(self, l, q, targets=None, parts=False):
-        """FMM potentials and forces; near + far, or the four parts."""
+    def fmm(self, l, q, targets=None, parts=False, unit_ops=None):
+        """FMM potentials and forces; near + far, or the four parts.  With
+        ``unit_ops`` (from :func:`compressed_unit_ops`) M2L uses those
+        operators instead of the exact kernel matrices."""
         q = _f64(q, (self.n,))
+        if unit_ops is not None:
+            unit_ops = np.ascontiguousarray(unit_ops, dtype=np.float64)
+            if unit_ops.shape != (343, l ** 3, l ** 3):
+                raise ValueError("unit_ops must be (343, l^3, l^3)")
         if targets is None:
             nt = self.n
             tptr = None
@@ -276,8 +284,9 @@ class Tree:
         fn = np.empty((nt, 3)) if parts else None
         pf = np.empty(nt) if parts else None
         ff = np.empty((nt, 3)) if parts else None
-        rc = _load().oracle_fmm(self._h, int(l), _ptr(q), tptr, nt, _ptr(phi),
-                                _ptr(f), _ptr(pn), _ptr(fn), _ptr(pf), _ptr(ff))
+        rc = _load().oracle_fmm_ops(self._h, int(l), _ptr(q), tptr, nt, _ptr(unit_ops),
+                                    _ptr(phi), _ptr(f), _ptr(pn), _ptr(fn), _ptr(pf),
+                                    _ptr(ff))
         if rc != 0:
             raise ValueError(f"oracle_fmm failed ({rc})")
         if parts:
@@ -288,3 +297,39 @@ class Tree:
 def fmm(pos, q, h, l, targets=None):
     """Convenience: build the tree and evaluate."""
     return Tree(pos, h).fmm(l, q, targets=targets)
+
+
+def far_offsets():
+    """The 316 far-field offsets t (|t|_inf in {2, 3}) and their ids."""
+    out = []
+    for tx in range(-3, 4):
+        for ty in range(-3, 4):
+            for tz in range(-3, 4):
+                if max(abs(tx), abs(ty), abs(tz)) >= 2:
+                    out.append(((tx, ty, tz), (tx + 3) * 49 + (ty + 3) * 7 + (tz + 3)))
+    return out
+
+
+_ops_cache = {}
+
+
+def compressed_unit_ops(l, eps):
+    """Compressed M2L of Sec. 2.1.2: for every far offset t, the unit
+    operator (cells of half-width 1) replaced by its truncated SVD, keeping
+    the singular values s_k >= eps * s_1 (eps = 0 keeps all).  Each offset's
+    operator is decomposed on its own (numpy's LAPACK SVD; no symmetry is
+    used).  Returns (ops[343][l^3][l^3], {offset: rank})."""
+    key = (l, float(eps))
+    if key in _ops_cache:
+        return _ops_cache[key]
+    l3 = l ** 3
+    ops = np.zeros((343, l3, l3))
+    ranks = {}
+    for t, i in far_offsets():
+        K = m2l_matrix(l, 1.0, 2.0, t)
+        U, s, Vt = np.linalg.svd(K)
+        r = int(np.sum(s >= eps * s[0]))
+        ops[i] = (U[:, :r] * s[:r]) @ Vt[:r]
+        ranks[t] = r
+    _ops_cache[key] = (ops, ranks)
+    return ops, ranks

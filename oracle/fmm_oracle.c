@@ -687,6 +687,14 @@ int oracle_fmm(const oracle_tree* t, int l, const double* q,
                const int64_t* targets, int64_t nt, double* phi, double* f,
                double* phi_near, double* f_near, double* phi_far,
                double* f_far) {
+  return oracle_fmm_ops(t, l, q, targets, nt, NULL, phi, f, phi_near, f_near,
+                        phi_far, f_far);
+}
+
+int oracle_fmm_ops(const oracle_tree* t, int l, const double* q,
+                   const int64_t* targets, int64_t nt, const double* unit_ops,
+                   double* phi, double* f, double* phi_near, double* f_near,
+                   double* phi_far, double* f_far) {
   if (!t || !q || l < 1 || l > MAXO) return -1;
   const int64_t n = t->n;
   const int h = t->h;
@@ -795,7 +803,13 @@ int oracle_fmm(const oracle_tree* t, int l, const double* q,
       for (int k = 0; k < nid; ++k) {
         int id = ids[k];
         int tt[3] = {id / 49 - 3, (id / 7) % 7 - 3, id % 7 - 3};
-        m2l_matrix(&B, a, w, tt, K[id]);
+        if (unit_ops) {
+          /* given operator between half-width-1 cells, scaled to this level */
+          const double* src = unit_ops + (size_t)id * l3 * l3;
+          for (size_t e = 0; e < (size_t)l3 * l3; ++e) K[id][e] = src[e] / a;
+        } else {
+          m2l_matrix(&B, a, w, tt, K[id]);
+        }
       }
 
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nth)

@@ -91,6 +91,17 @@ int oracle_fmm(const oracle_tree* t, int l, const double* q,
                double* phi_near, double* f_near, double* phi_far,
                double* f_far);
 
+/* As oracle_fmm, but M2L uses given unit operators instead of evaluating the
+ * kernel: unit_ops[id][l^3][l^3] for the offset t with
+ * id = (tx+3)*49 + (ty+3)*7 + (tz+3) is the operator between cells of width
+ * 2 (half-width 1); level lv uses it scaled by 1/a_lv (1/r is homogeneous of
+ * degree -1).  Used for the compressed M2L of Sec. 2.1.2, whose truncated
+ * operators the caller computes. */
+int oracle_fmm_ops(const oracle_tree* t, int l, const double* q,
+                   const int64_t* targets, int64_t nt, const double* unit_ops,
+                   double* phi, double* f, double* phi_near, double* f_near,
+                   double* phi_far, double* f_far);
+
 /* number of OpenMP threads the oracle uses (0 = library default) */
 void oracle_set_threads(int nthreads);
 int oracle_get_threads(void);

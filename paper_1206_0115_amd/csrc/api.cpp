@@ -13,8 +13,89 @@
 namespace fmm {
 namespace {
 thread_local std::string g_last_error;
+
+StepTab one_job(int items, int level = 0) {
+  StepTab t;
+  std::memset(&t, 0, sizeof(t));
+  t.njobs = 1;
+  t.job[0] = 0;
+  t.level[0] = level;
+  t.start[0] = 0;
+  t.start[1] = items;
+  return t;
 }
+}  // namespace
+
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+void upload_job(fmm_plan_s* p, hipStream_t s) {
+  const int h = p->height;
+  const OpSet* op = p->ops;
+  JobDev& J = p->job_h;
+  std::memset(&J, 0, sizeof(J));
+  J.px = p->px;
+  J.py = p->py;
+  J.pz = p->pz;
+  J.prel = p->prel;
+  J.qs = p->qs;
+  J.perm = p->perm;
+  J.leaf_start = p->leaf_start;
+  J.leaf_keys = p->lev[h - 1].keys;
+  J.near = p->near;
+  J.n = int(p->n);
+  J.nleaf = int(p->nleaf);
+  J.height = h;
+  J.order = p->order;
+  J.ld = op->ld;
+  J.mt = op->mt;
+  J.kc = op->kc;
+  J.nmb = m2l_nmb(op->mt);
+  J.ntiles = int(p->ntiles);
+  J.has_far = h >= 3;
+  J.geo = {p->lo[0], p->lo[1], p->lo[2], p->L / double(int64_t(1) << (h - 1)), h - 1};
+  J.W = p->W;
+  J.W32 = p->W32;
+  J.Loc = p->Loc;
+  for (int l = 0; l < h; ++l) {
+    J.lev_off[l] = p->lev[l].off;
+    J.ncell[l] = int(p->lev[l].ncell);
+    J.child_start[l] = p->lev[l].child_start;
+    J.parent[l] = p->lev[l].parent;
+    J.keys[l] = p->lev[l].keys;
+  }
+  for (int l = 0; l < kMaxHeight; ++l)
+    J.scale[l] = double(int64_t(1) << std::min(l + 1, 62)) / p->L;
+  J.tiles = p->tiles;
+  J.tgt = p->tgt;
+  J.tile_src = p->tile_src;
+  J.tile_act = p->tile_act;
+  J.tile_nact = p->tile_nact;
+  J.kp64 = op->kpack64;
+  J.kp32 = op->kpack32;
+  J.slot_kid = op->slot_kid;
+  J.cheb = op->cheb;
+  J.child = op->child;
+  J.phi_n = p->phi_n;
+  J.f_n = p->f_n;
+  J.phi_f = p->phi_f;
+  J.f_f = p->f_f;
+
+  std::memset(p->tab_h, 0, sizeof(p->tab_h));
+  p->tab_h[kTabLeaf] = one_job(int(p->nleaf));
+  if (h >= 3) {
+    p->tab_h[kTabCast] = one_job(int(p->ncell_total + 1 - p->lev[2].off));
+    p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb);
+    for (int st = 0; st + 4 <= h; ++st) {
+      p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
+      p->tab_h[kTabL2L + st] = one_job(int(p->lev[3 + st].ncell), 3 + st);
+    }
+  }
+  if (!p->job_d) p->job_d = static_cast<JobDev*>(p->alloc(sizeof(JobDev)));
+  if (!p->tab_d) p->tab_d = static_cast<StepTab*>(p->alloc(sizeof(StepTab) * kTabCount));
+  FMM_HIP_CHECK(hipMemcpyAsync(p->job_d, &p->job_h, sizeof(JobDev), hipMemcpyHostToDevice, s));
+  FMM_HIP_CHECK(hipMemcpyAsync(p->tab_d, p->tab_h, sizeof(p->tab_h), hipMemcpyHostToDevice, s));
+  FMM_HIP_CHECK(hipStreamSynchronize(s));
+}
 }  // namespace fmm
 
 void* fmm_plan_s::alloc(size_t b) {
@@ -113,8 +194,8 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
       p->Loc = static_cast<double*>(p->alloc(sizeof(double) * rows * ld));
       // the row past the last cell is the zero source of absent M2L slots
       FMM_HIP_CHECK(hipMemsetAsync(p->W + (rows - 1) * ld, 0, sizeof(double) * ld, stream));
-      FMM_HIP_CHECK(hipStreamSynchronize(stream));
     }
+    fmm::upload_job(p, stream);
     FMM_HIP_CHECK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
     return FMM_OK;
   });
@@ -144,6 +225,7 @@ int fmm_plan_set_precision(fmm_plan_t p, int mode) {
       if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
       const size_t rows = size_t(p->ncell_total + 1);
       p->W32 = static_cast<float*>(p->alloc(sizeof(float) * rows * p->ops->ld));
+      fmm::upload_job(p, p->last_stream);
     }
     p->precision = mode;
     return FMM_OK;

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/fmm.h"
+#include "jobs.h"
 
 namespace fmm {
 
@@ -84,6 +85,18 @@ struct LevelView {
   int* lookup = nullptr;          // dense table over keys (8^l entries) or null
 };
 
+// Step tables a plan keeps for its own evaluations (one job each).
+enum {
+  kTabLeaf = 0,  // P2M, L2L, L2P, P2P: one item per leaf
+  kTabCast = 1,  // FP32 copy of the multipoles: one item per row of levels >= 2
+  kTabM2L = 2,   // one item per (M2L tile, M-block)
+  kTabM2M = 3,   // + step s: parents at level h-2-s
+  kTabL2L = 3 + kMaxHeight,  // + step s: children at level 3+s
+  kTabCount = 3 + 2 * kMaxHeight
+};
+
+int m2l_nmb(int mt);  // M-blocks per M2L tile for mt 16-row tiles
+
 }  // namespace fmm
 
 struct fmm_plan_s {
@@ -126,6 +139,12 @@ struct fmm_plan_s {
   float* W32 = nullptr;
   double *phi_n = nullptr, *f_n = nullptr, *phi_f = nullptr, *f_f = nullptr;
 
+  // kernel-side description of this plan and its step tables
+  fmm::JobDev job_h{};
+  fmm::JobDev* job_d = nullptr;
+  fmm::StepTab tab_h[fmm::kTabCount];
+  fmm::StepTab* tab_d = nullptr;
+
   hipEvent_t done = nullptr;       // recorded after each evaluation
   bool in_flight = false;
   hipStream_t last_stream = nullptr;  // stream of the last evaluation
@@ -144,8 +163,8 @@ void build_plan(fmm_plan_s* p, const double* positions, hipStream_t stream);
 void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f,
               double* phi_n, double* f_n, double* phi_f, double* f_f,
               hipStream_t stream);
-// M2L launch (m2l.hip)
-void launch_m2l(fmm_plan_s* p, bool fp32, hipStream_t stream);
+// fill the plan's JobDev and step tables and copy them to the device (api.cpp)
+void upload_job(fmm_plan_s* p, hipStream_t stream);
 // M2L timing hook: the last M2L launch is bracketed by these events when set
 extern thread_local hipEvent_t g_m2l_ev0, g_m2l_ev1;
 }  // namespace fmm

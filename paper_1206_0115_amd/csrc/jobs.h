@@ -1,0 +1,106 @@
+// Job tables: how one kernel launch covers the work of one or many plans.
+//
+// Every evaluation kernel walks a flat item range (leaves, cells of a level,
+// M2L tile blocks, particle chunks).  A StepTab lists the plans (jobs) taking
+// part in one launch and the prefix sums of their item counts; a block finds
+// its job by binary search and works on that job's item with that job's
+// arrays.  A single evaluation is a one-job table built at plan time; the
+// serving loop builds many-job tables per batch.  The per-item code is the
+// same in both cases, so a plan's results do not depend on what else shares
+// the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fmm {
+
+constexpr int kMaxJobs = 64;
+constexpr int kMaxHeightJ = 21;
+
+struct LeafGeom {
+  double lo0, lo1, lo2, w;  // leaf width w, centre lo + (k + 1/2) w
+  int bits;
+};
+
+struct M2LTile;
+
+// Everything a kernel needs to know about one plan (device-resident copy).
+struct JobDev {
+  const double* px;
+  const double* py;
+  const double* pz;
+  float4* prel;
+  double* qs;
+  const int* perm;
+  const int* leaf_start;
+  const uint64_t* leaf_keys;
+  const int* near;
+  int n, nleaf, height, order, ld, mt, kc, nmb, ntiles, has_far;
+  LeafGeom geo;
+  double* W;
+  float* W32;
+  double* Loc;
+  int64_t lev_off[kMaxHeightJ];
+  int ncell[kMaxHeightJ];
+  const int* child_start[kMaxHeightJ];
+  const int* parent[kMaxHeightJ];
+  const uint64_t* keys[kMaxHeightJ];
+  const M2LTile* tiles;
+  const int* tgt;
+  const int* tile_src;
+  const unsigned char* tile_act;
+  const int* tile_nact;
+  double scale[kMaxHeightJ];  // 1 / a_l, the M2L level factor
+  const double* kp64;
+  const float* kp32;
+  const int* slot_kid;
+  const double* cheb;
+  const double* child;
+  double* phi_n;  // near/far partial results in sorted order
+  double* f_n;
+  double* phi_f;
+  double* f_f;
+};
+
+// Per-evaluation pointers (input order), for the gather and combine steps.
+struct CallDev {
+  const double* q;
+  double* phi;
+  double* f;
+  double* pn;
+  double* fn;
+  double* pf;
+  double* ff;
+};
+
+struct StepTab {
+  int njobs;
+  int job[kMaxJobs];    // index into the job array
+  int level[kMaxJobs];  // per-job level argument (M2M: parent level; L2L: child level)
+  int start[kMaxJobs + 1];
+};
+
+__device__ inline int step_total(const StepTab& t) { return t.start[t.njobs]; }
+
+// k with t.start[k] <= item < t.start[k+1]
+__device__ inline int step_find(const StepTab& t, int item) {
+  int lo = 0, hi = t.njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t.start[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Host-side launchers (eval.hip / m2l.hip).  `grid` <= 0 means one block per
+// item (the total must then be given); a positive grid makes every block loop
+// over items with that stride (persistent launch).
+enum StepKind { kStepGather, kStepP2M, kStepM2M, kStepCast, kStepM2L, kStepL2L, kStepL2P,
+                kStepP2P, kStepCombine };
+void launch_step(StepKind kind, int order, bool fp32, const JobDev* jobs, const StepTab* tab,
+                 const CallDev* calls, int grid, hipStream_t s);
+
+}  // namespace fmm

@@ -28,6 +28,7 @@
 
 #include "device_util.h"
 #include "fmm_internal.h"
+#include "jobs.h"
 
 namespace fmm {
 
@@ -289,137 +290,136 @@ __device__ inline f4 mfma16x16x4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-struct M2LArgs {
-  const M2LTile* tiles;
-  const int* tgt;
-  const int* tile_src;
-  const unsigned char* tile_act;
-  const int* tile_nact;
-  const int* slot_kid;
-  const void* kp;      // packed unit operators (T)
-  const void* W;       // multipoles (T), [ncell+1][ld]
-  double* Loc;         // local expansions (f64), [ncell+1][ld]
-  int mt, kc, ld, nmb, nblocks;
-  double scale[kMaxHeight];  // 1 / a_l
-};
-
-// One workgroup = 4 wavefronts = one (tile, M-block).  Wavefront w owns the
-// M-tiles [mt0, mt0 + MTW) of the output rows and all 64 target columns (four
-// 16-column N-tiles).  K-chunks of 16 coefficients = 4 MFMA k-steps; lane
-// group g = lane/16 holds k = 16c + 4g + s at step s, so both operands are
-// fetched as 4 consecutive values per lane.  FOLD: FP32 partial sums are
+// One workgroup = 4 wavefronts = one (tile, M-block) item.  Wavefront w owns
+// the M-tiles [mt0, mt0 + MTW) of the output rows and all 64 target columns
+// (four 16-column N-tiles).  K-chunks of 16 coefficients = 4 MFMA k-steps;
+// lane group g = lane/16 holds k = 16c + 4g + s at step s, so both operands
+// are fetched as 4 consecutive values per lane.  FOLD: FP32 partial sums are
 // added into FP64 accumulators after every far offset.
 template <typename T, int MTW, bool FOLD>
-__global__ __launch_bounds__(256) void m2l_kernel(const M2LArgs a) {
+__global__ __launch_bounds__(256) void m2l_kernel(const JobDev* __restrict__ jobs,
+                                                  const StepTab* __restrict__ tab) {
   typedef typename Vec4<T>::type T4;
-  // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-  // run of tiles so neighbouring tiles share source multipoles in its L2
-  int b = blockIdx.x;
-  const int n8 = (a.nblocks / 8) * 8;
-  if (b < n8) b = (b % 8) * (n8 / 8) + b / 8;
-  const int tile = b / a.nmb, mb = b % a.nmb;
+  const int total = step_total(*tab);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int mt0 = (mb * 4 + wave) * MTW;
-  if (mt0 >= a.mt) return;
-  const int nmt = min(MTW, a.mt - mt0);
-  const M2LTile tl = a.tiles[tile];
   const int g = lane >> 4, c16 = lane & 15;
-  const int KC = a.kc, ld = a.ld;
-  const T* __restrict__ Wp = static_cast<const T*>(a.W);
-  const T* __restrict__ Kp = static_cast<const T*>(a.kp);
-
-  T4 acc[MTW][4];
-  d4 acc64[FOLD ? MTW : 1][4];
-  for (int i = 0; i < MTW; ++i)
-    for (int j = 0; j < 4; ++j) {
-      acc[i][j] = T4{0, 0, 0, 0};
-      if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    // with one block per item, blocks are dealt round-robin to the 8 XCDs:
+    // give each XCD a contiguous run of tiles so neighbouring tiles share
+    // source multipoles in its L2
+    int b = it;
+    if (int(gridDim.x) == total) {
+      const int n8 = (total / 8) * 8;
+      if (b < n8) b = (b % 8) * (n8 / 8) + b / 8;
     }
+    const int k = step_find(*tab, b);
+    const JobDev& J = jobs[tab->job[k]];
+    const int local = b - tab->start[k];
+    const int tile = local / J.nmb, mb = local % J.nmb;
+    const int MT = J.mt, KC = J.kc, ld = J.ld;
+    const int mt0 = (mb * 4 + wave) * MTW;
+    if (mt0 >= MT) continue;
+    const int nmt = min(MTW, MT - mt0);
+    const M2LTile tl = J.tiles[tile];
+    const T* __restrict__ Wp = FOLD ? reinterpret_cast<const T*>(J.W32)
+                                    : reinterpret_cast<const T*>(J.W);
+    const T* __restrict__ Kp = FOLD ? reinterpret_cast<const T*>(J.kp32)
+                                    : reinterpret_cast<const T*>(J.kp64);
 
-  const int nact = a.tile_nact[tile];
-  const unsigned char* act = a.tile_act + int64_t(tile) * kSlots;
-  const int* srcb = a.tile_src + int64_t(tile) * kSlots * kTileN;
-  const int* kidp = a.slot_kid + tl.parity * kSlots;
-
-  for (int ia = 0; ia < nact; ++ia) {
-    const int s = act[ia];
-    const int kid = kidp[s];
-    const T* bptr[4];
-    for (int j = 0; j < 4; ++j)
-      bptr[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
-    const T* aptr = Kp + (int64_t(kid) * a.mt + mt0) * KC * 256 + lane * 4;
-
-    T4 bv[4], av[MTW];
-    for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j]);
+    T4 acc[MTW][4];
+    d4 acc64[FOLD ? MTW : 1][4];
     for (int i = 0; i < MTW; ++i)
-      av[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + int64_t(i) * KC * 256) : T4{0, 0, 0, 0};
-    for (int c = 0; c < KC; ++c) {
-      T4 bn[4], an[MTW];
-      const bool more = c + 1 < KC;
-      if (more) {
-        for (int j = 0; j < 4; ++j)
-          bn[j] = *reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1));
-        for (int i = 0; i < MTW; ++i)
-          an[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + (int64_t(i) * KC + c + 1) * 256)
-                          : T4{0, 0, 0, 0};
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = T4{0, 0, 0, 0};
+        if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
       }
-#pragma unroll
-      for (int st = 0; st < 4; ++st)
-#pragma unroll
-        for (int i = 0; i < MTW; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
-      if (more) {
-        for (int j = 0; j < 4; ++j) bv[j] = bn[j];
-        for (int i = 0; i < MTW; ++i) av[i] = an[i];
-      }
-    }
-    if (FOLD) {
-      for (int i = 0; i < MTW; ++i)
-        for (int j = 0; j < 4; ++j) {
-          for (int r = 0; r < 4; ++r) acc64[FOLD ? i : 0][j][r] += double(acc[i][j][r]);
-          acc[i][j] = T4{0, 0, 0, 0};
-        }
-    }
-  }
 
-  // D layout of the 16x16 outputs, column c16 in every lane group g: the
-  // FP32 instruction holds rows 4g+r in item r, the FP64 one rows 4r+g
-  // (both measured on gfx950).
-  const double sc = a.scale[tl.level];
-  const bool f64 = sizeof(T) == 8;
-  for (int j = 0; j < 4; ++j) {
-    const int col = 16 * j + c16;
-    if (col >= tl.count) continue;
-    double* out = a.Loc + int64_t(a.tgt[tl.first + col]) * ld;
-    for (int i = 0; i < nmt; ++i) {
-      const int base = 16 * (mt0 + i);
-      if (f64) {
-        for (int r = 0; r < 4; ++r)
-          out[base + 4 * r + g] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
-      } else {
-        d4 v;
-        for (int r = 0; r < 4; ++r)
-          v[r] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
-        *reinterpret_cast<d4*>(out + base + 4 * g) = v;
+    const int nact = J.tile_nact[tile];
+    const unsigned char* act = J.tile_act + int64_t(tile) * kSlots;
+    const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN;
+    const int* kidp = J.slot_kid + tl.parity * kSlots;
+
+    for (int ia = 0; ia < nact; ++ia) {
+      const int s = act[ia];
+      const int kid = kidp[s];
+      const T* bptr[4];
+      for (int j = 0; j < 4; ++j)
+        bptr[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+      const T* aptr = Kp + (int64_t(kid) * MT + mt0) * KC * 256 + lane * 4;
+
+      T4 bv[4], av[MTW];
+      for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j]);
+      for (int i = 0; i < MTW; ++i)
+        av[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + int64_t(i) * KC * 256)
+                        : T4{0, 0, 0, 0};
+      for (int c = 0; c < KC; ++c) {
+        T4 bn[4], an[MTW];
+        const bool more = c + 1 < KC;
+        if (more) {
+          for (int j = 0; j < 4; ++j)
+            bn[j] = *reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1));
+          for (int i = 0; i < MTW; ++i)
+            an[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + (int64_t(i) * KC + c + 1) * 256)
+                            : T4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int i = 0; i < MTW; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
+        if (more) {
+          for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+          for (int i = 0; i < MTW; ++i) av[i] = an[i];
+        }
+      }
+      if (FOLD) {
+        for (int i = 0; i < MTW; ++i)
+          for (int j = 0; j < 4; ++j) {
+            for (int r = 0; r < 4; ++r) acc64[FOLD ? i : 0][j][r] += double(acc[i][j][r]);
+            acc[i][j] = T4{0, 0, 0, 0};
+          }
+      }
+    }
+
+    // D layout of the 16x16 outputs, column c16 in every lane group g: the
+    // FP32 instruction holds rows 4g+r in item r, the FP64 one rows 4r+g
+    // (both measured on gfx950).
+    const double sc = J.scale[tl.level];
+    const bool f64 = sizeof(T) == 8;
+    for (int j = 0; j < 4; ++j) {
+      const int col = 16 * j + c16;
+      if (col >= tl.count) continue;
+      double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+      for (int i = 0; i < nmt; ++i) {
+        const int base = 16 * (mt0 + i);
+        if (f64) {
+          for (int r = 0; r < 4; ++r)
+            out[base + 4 * r + g] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+        } else {
+          d4 v;
+          for (int r = 0; r < 4; ++r)
+            v[r] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+          *reinterpret_cast<d4*>(out + base + 4 * g) = v;
+        }
       }
     }
   }
 }
 
 template <typename T, bool FOLD>
-static void launch_mtw(int mtw, const M2LArgs& a, int grid, hipStream_t s) {
+static void launch_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid, hipStream_t s) {
   switch (mtw) {
-    case 1: m2l_kernel<T, 1, FOLD><<<grid, 256, 0, s>>>(a); break;
-    case 2: m2l_kernel<T, 2, FOLD><<<grid, 256, 0, s>>>(a); break;
-    case 3: m2l_kernel<T, 3, FOLD><<<grid, 256, 0, s>>>(a); break;
-    default: m2l_kernel<T, 4, FOLD><<<grid, 256, 0, s>>>(a); break;
+    case 1: m2l_kernel<T, 1, FOLD><<<grid, 256, 0, s>>>(jobs, tab); break;
+    case 2: m2l_kernel<T, 2, FOLD><<<grid, 256, 0, s>>>(jobs, tab); break;
+    case 3: m2l_kernel<T, 3, FOLD><<<grid, 256, 0, s>>>(jobs, tab); break;
+    default: m2l_kernel<T, 4, FOLD><<<grid, 256, 0, s>>>(jobs, tab); break;
   }
 }
 
 // M-tiles per wavefront: fewest idle M-tile slots, then the largest count
 // (fewest M-blocks, so the gathered source columns are read fewest times).
-static int pick_mtw(int mt) {
+int m2l_mtw(int mt) {
   int best = 1, best_waste = 1 << 30;
   for (int w = 1; w <= 4; ++w) {
     const int per_block = 4 * w;
@@ -433,34 +433,21 @@ static int pick_mtw(int mt) {
   return best;
 }
 
-void launch_m2l(fmm_plan_s* p, bool fp32, hipStream_t s) {
-  if (p->ntiles == 0) return;
-  const OpSet* op = p->ops;
-  M2LArgs a;
-  a.tiles = p->tiles;
-  a.tgt = p->tgt;
-  a.tile_src = p->tile_src;
-  a.tile_act = p->tile_act;
-  a.tile_nact = p->tile_nact;
-  a.slot_kid = op->slot_kid;
-  a.kp = fp32 ? static_cast<const void*>(op->kpack32) : static_cast<const void*>(op->kpack64);
-  a.W = fp32 ? static_cast<const void*>(p->W32) : static_cast<const void*>(p->W);
-  a.Loc = p->Loc;
-  a.mt = op->mt;
-  a.kc = op->kc;
-  a.ld = op->ld;
-  for (int l = 0; l < kMaxHeight; ++l)
-    a.scale[l] = double(int64_t(1) << std::min(l + 1, 62)) / p->L;
-  const int mtw = pick_mtw(op->mt);
-  a.nmb = (op->mt + 4 * mtw - 1) / (4 * mtw);
-  a.nblocks = int(p->ntiles) * a.nmb;
-  if (g_m2l_ev0) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev0, s));
+int m2l_nmb(int mt) {
+  const int w = m2l_mtw(mt);
+  return (mt + 4 * w - 1) / (4 * w);
+}
+
+// Every job in `tab` must have the same order (same packed operator shape).
+void launch_m2l_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
+                     hipStream_t s) {
+  const int l3 = order * order * order;
+  const int mtw = m2l_mtw((l3 + 15) / 16);
   if (fp32)
-    launch_mtw<float, true>(mtw, a, a.nblocks, s);
+    launch_mtw<float, true>(mtw, jobs, tab, grid, s);
   else
-    launch_mtw<double, false>(mtw, a, a.nblocks, s);
+    launch_mtw<double, false>(mtw, jobs, tab, grid, s);
   FMM_HIP_CHECK(hipGetLastError());
-  if (g_m2l_ev1) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev1, s));
 }
 
 }  // namespace fmm

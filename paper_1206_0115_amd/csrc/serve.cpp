@@ -1,0 +1,538 @@
+// Serving loop: continuous batching of FMM evaluations on one GPU.
+//
+// A worker thread owns two streams.  On the plan stream it builds the plans
+// of arriving requests (root box, sort, lists: the synchronous part) and
+// admits them while the admitted plans' device bytes stay within the budget.
+// On the execution stream it evaluates batches: all admitted requests that
+// are not yet running form one batch whose operators run as persistent
+// launches over one shared work table (jobs.h), the whole launch sequence
+// captured once per shape as a hipGraph and replayed with new tables.  The
+// table travels inside the graph as a copy from a pinned host buffer; two
+// buffers let the next batch be prepared while one runs.  Planning on the
+// plan stream overlaps the running batch on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "fmm_internal.h"
+#include "jobs.h"
+
+namespace fmm {
+namespace {
+
+constexpr int kMaxSteps = 160;
+constexpr int kBuffers = 2;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Blocks per persistent launch, by kernel (sized to keep every CU busy; a
+// block loops over the items of the batch with this stride).
+int persistent_grid(StepKind k) {
+  switch (k) {
+    case kStepM2L: return 512;
+    case kStepP2P:
+    case kStepP2M:
+    case kStepL2P: return 4096;
+    default: return 1024;
+  }
+}
+
+struct Request {
+  int64_t id = 0;
+  const double* pos = nullptr;
+  const double* q = nullptr;
+  int64_t n = 0;
+  int h = 0, order = 0, prec = 0;
+  double* phi = nullptr;
+  double* f = nullptr;
+  fmm_plan_s* plan = nullptr;
+  int status = FMM_OK;
+  bool done = false;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int64_t batch = -1;
+  int64_t bytes = 0;        // admitted footprint (known after the first plan)
+};
+
+struct Launch {
+  StepKind kind;
+  int order;
+  bool fp32;
+};
+
+struct TableBuf {
+  void* pinned = nullptr;
+  void* dev = nullptr;
+  hipEvent_t last = nullptr;  // completion of the batch that last read it
+  bool busy = false;
+};
+
+struct Batch {
+  std::vector<Request*> reqs;
+  hipEvent_t ev = nullptr;
+  int buf = 0;
+  int64_t index = 0;
+};
+
+const size_t kJobsOff = 0;
+const size_t kCallsOff = align256(sizeof(JobDev) * kMaxJobs);
+const size_t kTabsOff = kCallsOff + align256(sizeof(CallDev) * kMaxJobs);
+const size_t kTableBytes = kTabsOff + sizeof(StepTab) * kMaxSteps;
+
+}  // namespace
+}  // namespace fmm
+
+struct fmm_server_s {
+  int device = 0;
+  size_t budget = 0;
+  int max_active = 0;
+  hipStream_t plan_stream = nullptr, exec_stream = nullptr;
+  fmm::TableBuf buf[fmm::kBuffers];
+  std::map<std::pair<int, std::string>, hipGraphExec_t> graphs;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<fmm::Request*> pending;          // submitted, not yet admitted
+  std::vector<fmm::Request*> ready;           // admitted, not yet launched
+  std::deque<fmm::Batch> inflight;
+  std::unordered_map<int64_t, fmm::Request*> all;
+  int64_t next_id = 0;
+  size_t used = 0;
+  int active = 0;
+  bool stop = false;
+  struct fmm_server_stats st{};
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  std::thread worker;
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void run();
+  void retire();
+  bool admit();
+  bool launch_batch();
+  void finish(fmm::Request* r, int status);
+};
+
+using namespace fmm;
+
+void fmm_server_s::finish(Request* r, int status) {
+  // called with mu held
+  r->status = status;
+  r->done = true;
+  r->t_done = now();
+  if (status == FMM_OK) ++st.completed;
+  else ++st.rejected;
+  cv_done.notify_all();
+}
+
+void fmm_server_s::retire() {
+  while (true) {
+    Batch b;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (inflight.empty()) return;
+      hipError_t e = hipEventQuery(inflight.front().ev);
+      if (e == hipErrorNotReady) return;
+      b = inflight.front();
+      inflight.pop_front();
+      const int status = e == hipSuccess ? FMM_OK : FMM_ERR_HIP;
+      if (e != hipSuccess) (void)hipGetLastError();
+      for (Request* r : b.reqs) {
+        used -= size_t(r->bytes);
+        --active;
+        finish(r, status);
+      }
+    }
+    buf[b.buf].busy = false;
+    (void)hipEventDestroy(b.ev);
+    for (Request* r : b.reqs) {
+      fmm_release(r->plan);
+      r->plan = nullptr;
+    }
+    cv_work.notify_all();
+  }
+}
+
+// Plan pending requests in arrival order while slots and memory allow.
+bool fmm_server_s::admit() {
+  bool any = false;
+  while (true) {
+    Request* r = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (pending.empty() || active >= max_active) return any;
+      r = pending.front();
+      // footprint known from an earlier attempt and still too large for now
+      if (r->bytes > 0 && used + size_t(r->bytes) > budget) return any;
+      pending.pop_front();
+    }
+    fmm_plan_s* p = fmm_plan_stream(r->pos, r->n, r->h, r->order, plan_stream);
+    int rc = p ? fmm_plan_set_precision(p, r->prec) : FMM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!p || rc != FMM_OK) {
+      if (p) fmm_release(p);
+      finish(r, rc != FMM_OK ? rc : FMM_ERR_ARG);
+      any = true;
+      continue;
+    }
+    r->bytes = int64_t(p->bytes);
+    if (size_t(r->bytes) > budget) {
+      fmm_release(p);
+      finish(r, FMM_ERR_OOM);
+      any = true;
+      continue;
+    }
+    if (used + size_t(r->bytes) > budget) {
+      // wait for running batches to free memory; re-plan then
+      fmm_release(p);
+      pending.push_front(r);
+      return any;
+    }
+    r->plan = p;
+    r->t_admit = now();
+    used += size_t(r->bytes);
+    ++active;
+    st.max_active_seen = std::max<int64_t>(st.max_active_seen, active);
+    st.peak_admitted_bytes = std::max<int64_t>(st.peak_admitted_bytes, int64_t(used));
+    ready.push_back(r);
+    any = true;
+  }
+}
+
+// Build the batch's work table and launch sequence, then run it as a graph.
+bool fmm_server_s::launch_batch() {
+  int bi = -1;
+  for (int i = 0; i < kBuffers; ++i)
+    if (!buf[i].busy) {
+      bi = i;
+      break;
+    }
+  std::vector<Request*> reqs;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (ready.empty() || bi < 0) return false;
+    const size_t take = std::min<size_t>(ready.size(), kMaxJobs);
+    reqs.assign(ready.begin(), ready.begin() + take);
+    ready.erase(ready.begin(), ready.begin() + take);
+  }
+  TableBuf& B = buf[bi];
+  if (B.last) FMM_HIP_CHECK(hipEventSynchronize(B.last));  // its copy has been consumed
+  char* host = static_cast<char*>(B.pinned);
+  JobDev* jobs = reinterpret_cast<JobDev*>(host + kJobsOff);
+  CallDev* calls = reinterpret_cast<CallDev*>(host + kCallsOff);
+  StepTab* tabs = reinterpret_cast<StepTab*>(host + kTabsOff);
+  const int nj = int(reqs.size());
+  for (int j = 0; j < nj; ++j) {
+    jobs[j] = reqs[j]->plan->job_h;
+    calls[j] = CallDev{reqs[j]->q, reqs[j]->phi, reqs[j]->f, nullptr, nullptr, nullptr, nullptr};
+  }
+
+  std::vector<Launch> seq;
+  std::string key;
+  auto add = [&](StepKind kind, int order, bool fp32, auto want, auto items, auto level) {
+    StepTab& t = tabs[seq.size()];
+    std::memset(&t, 0, sizeof(t));
+    int tot = 0;
+    for (int j = 0; j < nj; ++j) {
+      if (!want(reqs[j])) continue;
+      const int it = items(reqs[j]);
+      if (it <= 0) continue;
+      t.job[t.njobs] = j;
+      t.level[t.njobs] = level(reqs[j]);
+      t.start[t.njobs] = tot;
+      tot += it;
+      ++t.njobs;
+    }
+    t.start[t.njobs] = tot;
+    if (t.njobs == 0) return;
+    if (seq.size() + 1 >= size_t(kMaxSteps)) throw FmmError{FMM_ERR_HIP, "batch step table full"};
+    seq.push_back({kind, order, fp32});
+    key += std::to_string(int(kind)) + ":" + std::to_string(order) + (fp32 ? "f" : "d") + ";";
+  };
+  auto all_ = [](Request*) { return true; };
+  auto lvl0 = [](Request*) { return 0; };
+  auto chunks = [](Request* r) { return int((r->n + 255) / 256); };
+  auto far = [](Request* r) { return r->h >= 3; };
+  auto mixed = [](Request* r) { return r->prec == FMM_MIXED_FP32; };
+
+  std::vector<int> orders;
+  for (Request* r : reqs)
+    if (r->h >= 3 && std::find(orders.begin(), orders.end(), r->order) == orders.end())
+      orders.push_back(r->order);
+  std::sort(orders.begin(), orders.end());
+  int steps = 0;
+  for (Request* r : reqs) steps = std::max(steps, r->h - 3);
+
+  add(kStepGather, 0, false, all_, chunks, lvl0);
+  for (int L : orders)
+    add(kStepP2M, L, false, [&](Request* r) { return far(r) && r->order == L; },
+        [](Request* r) { return int(r->plan->nleaf); }, lvl0);
+  for (int s = 0; s < steps; ++s)
+    add(kStepM2M, 0, false, [&](Request* r) { return r->h - 4 >= s; },
+        [&](Request* r) { return int(r->plan->lev[r->h - 2 - s].ncell); },
+        [&](Request* r) { return r->h - 2 - s; });
+  add(kStepCast, 0, true, [&](Request* r) { return far(r) && mixed(r); },
+      [](Request* r) { return int(r->plan->ncell_total + 1 - r->plan->lev[2].off); }, lvl0);
+  for (int L : orders)
+    for (int f32 = 0; f32 < 2; ++f32)
+      add(kStepM2L, L, f32 != 0,
+          [&](Request* r) { return far(r) && r->order == L && mixed(r) == (f32 != 0); },
+          [](Request* r) { return int(r->plan->ntiles) * r->plan->job_h.nmb; }, lvl0);
+  for (int s = 0; s < steps; ++s)
+    add(kStepL2L, 0, false, [&](Request* r) { return r->h - 4 >= s; },
+        [&](Request* r) { return int(r->plan->lev[3 + s].ncell); },
+        [&](Request*) { return 3 + s; });
+  for (int L : orders)
+    add(kStepL2P, L, false, [&](Request* r) { return far(r) && r->order == L; },
+        [](Request* r) { return int(r->plan->nleaf); }, lvl0);
+  for (int f32 = 0; f32 < 2; ++f32)
+    add(kStepP2P, 0, f32 != 0, [&](Request* r) { return mixed(r) == (f32 != 0); },
+        [](Request* r) { return int(r->plan->nleaf); }, lvl0);
+  add(kStepCombine, 0, false, all_, chunks, lvl0);
+
+  // the graph for this launch sequence and buffer, captured on first use
+  const JobDev* jobs_d = reinterpret_cast<const JobDev*>(static_cast<char*>(B.dev) + kJobsOff);
+  const CallDev* calls_d = reinterpret_cast<const CallDev*>(static_cast<char*>(B.dev) + kCallsOff);
+  const StepTab* tabs_d = reinterpret_cast<const StepTab*>(static_cast<char*>(B.dev) + kTabsOff);
+  auto gk = std::make_pair(bi, key);
+  auto it = graphs.find(gk);
+  if (it == graphs.end()) {
+    hipGraph_t g = nullptr;
+    FMM_HIP_CHECK(hipStreamBeginCapture(exec_stream, hipStreamCaptureModeThreadLocal));
+    FMM_HIP_CHECK(hipMemcpyAsync(B.dev, B.pinned, kTableBytes, hipMemcpyHostToDevice, exec_stream));
+    for (size_t i = 0; i < seq.size(); ++i)
+      launch_step(seq[i].kind, seq[i].order, seq[i].fp32, jobs_d, tabs_d + i, calls_d,
+                  persistent_grid(seq[i].kind), exec_stream);
+    FMM_HIP_CHECK(hipStreamEndCapture(exec_stream, &g));
+    hipGraphExec_t ge = nullptr;
+    FMM_HIP_CHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    FMM_HIP_CHECK(hipGraphDestroy(g));
+    it = graphs.emplace(gk, ge).first;
+    ++st.graph_captures;
+  }
+  FMM_HIP_CHECK(hipGraphLaunch(it->second, exec_stream));
+  Batch b;
+  b.reqs = reqs;
+  b.buf = bi;
+  FMM_HIP_CHECK(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+  FMM_HIP_CHECK(hipEventRecord(b.ev, exec_stream));
+  if (B.last) FMM_HIP_CHECK(hipEventDestroy(B.last));
+  FMM_HIP_CHECK(hipEventCreateWithFlags(&B.last, hipEventDisableTiming));
+  FMM_HIP_CHECK(hipEventRecord(B.last, exec_stream));
+  B.busy = true;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    b.index = st.batches++;
+    ++st.graph_replays;
+    st.max_batch_jobs = std::max<int64_t>(st.max_batch_jobs, nj);
+    for (Request* r : reqs) r->batch = b.index;
+    inflight.push_back(b);
+  }
+  return true;
+}
+
+void fmm_server_s::run() {
+  (void)hipSetDevice(device);
+  while (true) {
+    bool progress = false;
+    try {
+      retire();
+      progress |= admit();
+      progress |= launch_batch();
+    } catch (...) {
+      // a runtime failure ends every request that is not running
+      int code = FMM_ERR_HIP;
+      std::string msg = "serving loop failure";
+      try {
+        throw;
+      } catch (const FmmError& e) {
+        code = e.code;
+        msg = e.msg;
+      } catch (const std::bad_alloc&) {
+        code = FMM_ERR_OOM;
+        msg = "host allocation failed";
+      } catch (...) {
+      }
+      std::lock_guard<std::mutex> lk(mu);
+      set_error(msg);
+      for (Request* r : ready) {
+        if (r->plan) {
+          used -= size_t(r->bytes);
+          --active;
+          fmm_release(r->plan);
+          r->plan = nullptr;
+        }
+        finish(r, code);
+      }
+      ready.clear();
+      for (Request* r : pending) finish(r, code);
+      pending.clear();
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    if (stop && pending.empty() && ready.empty() && inflight.empty()) break;
+    if (progress) continue;
+    if (!inflight.empty()) {
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    } else {
+      cv_work.wait_for(lk, std::chrono::milliseconds(5));
+    }
+  }
+  // release the graphs and the plans of anything left
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+}
+
+extern "C" {
+
+fmm_server_t fmm_server_create(size_t hbm_budget_bytes, int max_active) {
+  set_error("");
+  if (hbm_budget_bytes == 0) {
+    set_error("hbm_budget_bytes must be > 0");
+    return nullptr;
+  }
+  if (max_active < 1 || max_active > kMaxJobs) {
+    set_error("max_active must be in [1, 64]");
+    return nullptr;
+  }
+  fmm_server_s* s = new fmm_server_s();
+  try {
+    FMM_HIP_CHECK(hipGetDevice(&s->device));
+    s->budget = hbm_budget_bytes;
+    s->max_active = max_active;
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&s->plan_stream, hipStreamNonBlocking));
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&s->exec_stream, hipStreamNonBlocking));
+    for (int i = 0; i < kBuffers; ++i) {
+      FMM_HIP_CHECK(hipHostMalloc(&s->buf[i].pinned, kTableBytes, hipHostMallocDefault));
+      std::memset(s->buf[i].pinned, 0, kTableBytes);
+      FMM_HIP_CHECK(hipMalloc(&s->buf[i].dev, kTableBytes));
+    }
+  } catch (const FmmError& e) {
+    set_error(e.msg);
+    for (int i = 0; i < kBuffers; ++i) {
+      if (s->buf[i].pinned) (void)hipHostFree(s->buf[i].pinned);
+      if (s->buf[i].dev) (void)hipFree(s->buf[i].dev);
+    }
+    if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
+    if (s->exec_stream) (void)hipStreamDestroy(s->exec_stream);
+    delete s;
+    return nullptr;
+  }
+  s->worker = std::thread([s] { s->run(); });
+  return s;
+}
+
+int64_t fmm_server_submit(fmm_server_t s, const double* positions, const double* charges,
+                          int64_t n, int height, int order, int precision, double* potential,
+                          double* forces) {
+  if (!s) {
+    set_error("server is NULL");
+    return FMM_ERR_ARG;
+  }
+  if (!positions || !charges || !potential || !forces) {
+    set_error("NULL pointer argument");
+    return FMM_ERR_ARG;
+  }
+  if (n < 1 || n > int64_t(2147483646) || height < 1 || height > kMaxHeight || order < 1 ||
+      order > kMaxOrder || (precision != FMM_FP64 && precision != FMM_MIXED_FP32)) {
+    set_error("invalid n, height, order or precision");
+    return FMM_ERR_ARG;
+  }
+  Request* r = new Request();
+  r->pos = positions;
+  r->q = charges;
+  r->n = n;
+  r->h = height;
+  r->order = order;
+  r->prec = precision;
+  r->phi = potential;
+  r->f = forces;
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->id = s->next_id++;
+  r->t_submit = s->now();
+  s->all[r->id] = r;
+  s->pending.push_back(r);
+  ++s->st.submitted;
+  s->cv_work.notify_all();
+  return r->id;
+}
+
+static void fill_stats(const Request* r, fmm_request_stats* out) {
+  if (!out) return;
+  out->status = r->status;
+  out->done = r->done ? 1 : 0;
+  out->submit_s = r->t_submit;
+  out->admit_s = r->t_admit;
+  out->done_s = r->t_done;
+  out->batch = r->batch;
+  out->plan_bytes = r->bytes;
+}
+
+int fmm_server_poll(fmm_server_t s, int64_t ticket, fmm_request_stats* out) {
+  if (!s) return FMM_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) {
+    set_error("unknown ticket");
+    return FMM_ERR_ARG;
+  }
+  fill_stats(it->second, out);
+  return it->second->done ? 1 : 0;
+}
+
+int fmm_server_wait(fmm_server_t s, int64_t ticket, fmm_request_stats* out) {
+  if (!s) return FMM_ERR_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) {
+    set_error("unknown ticket");
+    return FMM_ERR_ARG;
+  }
+  Request* r = it->second;
+  s->cv_done.wait(lk, [&] { return r->done; });
+  fill_stats(r, out);
+  return r->status;
+}
+
+double fmm_server_now(fmm_server_t s) { return s ? s->now() : 0.0; }
+
+int fmm_server_get_stats(fmm_server_t s, struct fmm_server_stats* out) {
+  if (!s || !out) return FMM_ERR_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  return FMM_OK;
+}
+
+void fmm_server_destroy(fmm_server_t s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->all) {
+    if (kv.second->plan) fmm_release(kv.second->plan);
+    delete kv.second;
+  }
+  for (int i = 0; i < kBuffers; ++i) {
+    if (s->buf[i].last) (void)hipEventDestroy(s->buf[i].last);
+    (void)hipHostFree(s->buf[i].pinned);
+    (void)hipFree(s->buf[i].dev);
+  }
+  (void)hipStreamDestroy(s->plan_stream);
+  (void)hipStreamDestroy(s->exec_stream);
+  delete s;
+}
+
+}  // extern "C"

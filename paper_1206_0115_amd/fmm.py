@@ -46,6 +46,21 @@ class FmmInfo(ctypes.Structure):
     ]
 
 
+class RequestStats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("done", ctypes.c_int32),
+        ("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+        ("done_s", ctypes.c_double),
+        ("batch", ctypes.c_int64), ("plan_bytes", ctypes.c_int64),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "submitted", "completed", "rejected", "batches", "graph_captures", "graph_replays",
+        "max_batch_jobs", "max_active_seen", "peak_admitted_bytes")]
+
+
 _lib = None
 
 
@@ -73,6 +88,17 @@ def lib():
     L.fmm_plan_export.argtypes = [vp, i32, i32, vp, sz]
     L.fmm_set_m2l_timing_events.argtypes = [vp, vp]
     L.fmm_trim_cache.restype = None
+    L.fmm_server_create.argtypes = [sz, i32]
+    L.fmm_server_create.restype = vp
+    L.fmm_server_submit.argtypes = [vp, vp, vp, i64, i32, i32, i32, vp, vp]
+    L.fmm_server_submit.restype = i64
+    L.fmm_server_poll.argtypes = [vp, i64, ctypes.POINTER(RequestStats)]
+    L.fmm_server_wait.argtypes = [vp, i64, ctypes.POINTER(RequestStats)]
+    L.fmm_server_now.argtypes = [vp]
+    L.fmm_server_now.restype = ctypes.c_double
+    L.fmm_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.fmm_server_destroy.argtypes = [vp]
+    L.fmm_server_destroy.restype = None
     _lib = L
     return L
 
@@ -213,3 +239,73 @@ def set_m2l_timing_events(ev0, ev1):
 
 def trim_cache():
     lib().fmm_trim_cache()
+
+
+class Request:
+    """A queued evaluation; keeps its input and output tensors alive."""
+
+    def __init__(self, server, ticket, tensors, potential, forces):
+        self.server, self.ticket = server, ticket
+        self._tensors = tensors
+        self.potential, self.forces = potential, forces
+
+    def poll(self):
+        st = RequestStats()
+        rc = lib().fmm_server_poll(self.server._h, self.ticket, ctypes.byref(st))
+        if rc < 0:
+            raise FMMError(rc, last_error())
+        return st if rc == 1 else None
+
+    def wait(self):
+        st = RequestStats()
+        lib().fmm_server_wait(self.server._h, self.ticket, ctypes.byref(st))
+        return st
+
+
+class Server:
+    """The serving loop (``fmm_server_*``): continuous batching of evaluations
+    admitted by device-memory footprint."""
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 32):
+        h = lib().fmm_server_create(int(hbm_budget_bytes), int(max_active))
+        if not h:
+            raise FMMError(FMM_ERR_ARG, last_error())
+        self._h = ctypes.c_void_p(h)
+
+    def submit(self, positions, charges, height, order, precision="fp64",
+               potential=None, forces=None) -> Request:
+        import torch
+        n = int(positions.shape[0])
+        pp = _dev_f64(positions, (n, 3), "positions")
+        qp = _dev_f64(charges, (n,), "charges")
+        if potential is None:
+            potential = torch.empty(n, dtype=torch.float64, device=positions.device)
+        if forces is None:
+            forces = torch.empty(n, 3, dtype=torch.float64, device=positions.device)
+        mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        t = lib().fmm_server_submit(self._h, pp, qp, n, int(height), int(order), mode,
+                                    _dev_f64(potential, (n,), "potential"),
+                                    _dev_f64(forces, (n, 3), "forces"))
+        if t < 0:
+            raise FMMError(int(t), last_error())
+        return Request(self, int(t), (positions, charges), potential, forces)
+
+    def now(self) -> float:
+        return float(lib().fmm_server_now(self._h))
+
+    def stats(self) -> ServerStats:
+        out = ServerStats()
+        _check(lib().fmm_server_get_stats(self._h, ctypes.byref(out)))
+        return out
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fmm_server_destroy(h)
+        self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
