@@ -54,8 +54,33 @@ enum fmm_precision {
   /* P2P in FP32 with leaf-local coordinates and per-source-leaf FP64 folding;
    * M2L as FP32 MFMA contractions with FP32 accumulation folded into FP64 per
    * far offset; P2M, M2M, L2L, L2P and the output sums stay FP64 */
-  FMM_MIXED_FP32 = 1
+  FMM_MIXED_FP32 = 1,
+  /* FMM_FP64 with the compressed M2L of Sec. 2.1.2 ("improved M2L"): each of
+   * the 16 canonical operators factorised by one SVD, truncated at singular
+   * values s_k >= eps s_1 (eps from fmm_plan_set_m2l_tolerance, default 1e-8),
+   * applied as two skinny MFMA products per far offset */
+  FMM_FP64_SVD = 2,
+  /* FMM_MIXED_FP32 with the compressed M2L in FP32 MFMA (FP64 folding) */
+  FMM_MIXED_SVD = 3
 };
+
+/* Truncation tolerance of the compressed M2L (0 < eps < 1); takes effect for
+ * the SVD precision modes.  The truncated operators of an order and tolerance
+ * are computed once per device (rocSOLVER SVD of the 16 canonical operators)
+ * and cached.  Returns FMM_ERR_ARG for a tolerance outside (0, 1). */
+int fmm_plan_set_m2l_tolerance(fmm_plan_t plan, double eps);
+
+/* Compressed-M2L facts of the plan's current order and tolerance (host
+ * struct; computes the truncated operators if needed).  rank[c] is the number
+ * of singular values kept for canonical operator c; weighted_rank the mean
+ * rank over the 316 far offsets (the paper's "weighted r_16", Table 1). */
+struct fmm_svd_info {
+  double eps;
+  int32_t rank[16];
+  int32_t rmax_pad;
+  double weighted_rank;
+};
+int fmm_plan_svd_info(fmm_plan_t plan, struct fmm_svd_info* out);
 
 /*
  * Build a plan (the octree, Sec. 3.2 and 4.2): root box, Morton keys, stable
@@ -118,6 +143,9 @@ struct fmm_info {
   int64_t m2l_tiles;          /* MFMA work tiles (64 target cells each) */
   int64_t m2l_active_slots;   /* tile-offset pairs with at least one source */
   int64_t device_bytes;       /* device memory held by the plan */
+  double m2l_flops;           /* algorithmic M2L flops of one evaluation in the
+                                 current mode: 2 l^6 per pair (dense) or
+                                 4 l^3 r_t per pair (compressed, unpadded rank) */
 };
 int fmm_plan_info(fmm_plan_t plan, struct fmm_info* out);
 

@@ -49,7 +49,17 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.ld = op->ld;
   J.mt = op->mt;
   J.kc = op->kc;
-  J.nmb = m2l_nmb(op->mt);
+  J.nmb = p->svd ? m2l_svd_nmb(op->mt) : m2l_nmb(op->mt);
+  J.svd = p->svd ? 1 : 0;
+  if (p->svd) {
+    J.xs = p->svd->rmax_pad + 4;
+    J.svd_rpad = p->svd->rpad;
+    J.svd_off = p->svd->off;
+    J.p1_64 = p->svd->p1_64;
+    J.p1_32 = p->svd->p1_32;
+    J.p2_64 = p->svd->p2_64;
+    J.p2_32 = p->svd->p2_32;
+  }
   J.ntiles = int(p->ntiles);
   J.has_far = h >= 3;
   J.geo = {p->lo[0], p->lo[1], p->lo[2], p->L / double(int64_t(1) << (h - 1)), h - 1};
@@ -215,19 +225,55 @@ void fmm_release(fmm_plan_t plan) {
   delete plan;
 }
 
+// Apply the precision mode and M2L tolerance: allocate the FP32 multipoles of
+// the mixed modes, fetch the compressed operators of the SVD modes, and
+// refresh the device-side job description.
+static void apply_mode(fmm_plan_s* p, int mode) {
+  if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
+  const bool mixed = mode == FMM_MIXED_FP32 || mode == FMM_MIXED_SVD;
+  const bool svd = mode == FMM_FP64_SVD || mode == FMM_MIXED_SVD;
+  if (mixed && !p->W32 && p->height >= 3) {
+    const size_t rows = size_t(p->ncell_total + 1);
+    p->W32 = static_cast<float*>(p->alloc(sizeof(float) * rows * p->ops->ld));
+  }
+  p->svd = svd && p->height >= 3 ? fmm::get_svd_ops(p->order, p->m2l_eps, p->last_stream)
+                                 : nullptr;
+  p->precision = mode;
+  fmm::upload_job(p, p->last_stream);
+}
+
 int fmm_plan_set_precision(fmm_plan_t p, int mode) {
   if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
-  if (mode != FMM_FP64 && mode != FMM_MIXED_FP32)
+  if (mode < FMM_FP64 || mode > FMM_MIXED_SVD)
     return fail(FMM_ERR_ARG, "unknown precision mode " + std::to_string(mode));
   return guarded([&]() -> int {
     std::lock_guard<std::mutex> lk(p->mu);
-    if (mode == FMM_MIXED_FP32 && !p->W32 && p->height >= 3) {
-      if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
-      const size_t rows = size_t(p->ncell_total + 1);
-      p->W32 = static_cast<float*>(p->alloc(sizeof(float) * rows * p->ops->ld));
-      fmm::upload_job(p, p->last_stream);
-    }
-    p->precision = mode;
+    apply_mode(p, mode);
+    return FMM_OK;
+  });
+}
+
+int fmm_plan_set_m2l_tolerance(fmm_plan_t p, double eps) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(FMM_ERR_ARG, "tolerance must be in (0, 1)");
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->m2l_eps = eps;
+    apply_mode(p, p->precision);
+    return FMM_OK;
+  });
+}
+
+int fmm_plan_svd_info(fmm_plan_t p, struct fmm_svd_info* out) {
+  if (!p || !out) return fail(FMM_ERR_ARG, "NULL argument");
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    const fmm::SvdOps* sv = fmm::get_svd_ops(p->order, p->m2l_eps, p->last_stream);
+    std::memset(out, 0, sizeof(*out));
+    out->eps = sv->eps;
+    for (int c = 0; c < 16; ++c) out->rank[c] = sv->rank[c];
+    out->rmax_pad = sv->rmax_pad;
+    out->weighted_rank = sv->weighted_rank;
     return FMM_OK;
   });
 }
@@ -286,6 +332,17 @@ int fmm_plan_info(fmm_plan_t p, struct fmm_info* out) {
   out->m2l_tiles = p->ntiles;
   out->m2l_active_slots = p->active_slots;
   out->device_bytes = int64_t(p->bytes);
+  // algorithmic M2L flops of one evaluation in the current mode
+  const double l3 = double(p->order) * p->order * p->order;
+  if (p->svd) {
+    double fl = 0.0;
+    for (int k = 0; k < fmm::kOffsets; ++k)
+      fl += double(p->pairs_by_kid[k]) * 4.0 * l3 *
+            double(p->svd->rank[fmm::kid_canon(k)]);
+    out->m2l_flops = fl;
+  } else {
+    out->m2l_flops = 2.0 * l3 * l3 * double(p->far_pairs);
+  }
   return FMM_OK;
 }
 

@@ -527,9 +527,11 @@ __global__ __launch_bounds__(256) void cast_kernel(const JobDev* __restrict__ jo
 
 void launch_m2l_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
                      hipStream_t s);
+void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
+                         int xs, hipStream_t s);
 
 void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const StepTab* tab,
-                 const CallDev* calls, int grid, hipStream_t s) {
+                 const CallDev* calls, int grid, hipStream_t s, int xs) {
   const unsigned g = unsigned(grid);
   switch (kind) {
     case kStepGather:
@@ -550,6 +552,9 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       break;
     case kStepM2L:
       launch_m2l_step(L, fp32, jobs, tab, grid, s);
+      break;
+    case kStepM2LSvd:
+      launch_m2l_svd_step(L, fp32, jobs, tab, grid, xs, s);
       break;
     case kStepL2L:
       l2l_kernel<<<g, kTransThreads, 0, s>>>(jobs, tab);
@@ -575,7 +580,7 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
 void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* phi_n,
               double* f_n, double* phi_f, double* f_f, hipStream_t s) {
   const int L = p->order, h = p->height;
-  const bool mixed = p->precision == FMM_MIXED_FP32;
+  const bool mixed = p->precision == FMM_MIXED_FP32 || p->precision == FMM_MIXED_SVD;
   const JobDev* J = p->job_d;
   const unsigned chunks = unsigned((p->n + kChunk - 1) / kChunk);
   gather1_kernel<<<chunks, kChunk, 0, s>>>(J, q);
@@ -590,8 +595,8 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
                   p->tab_h[kTabCast].start[1], s);
     if (g_m2l_ev0) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev0, s));
     if (p->ntiles > 0)
-      launch_step(kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
-                  p->tab_h[kTabM2L].start[1], s);
+      launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
+                  p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
     if (g_m2l_ev1) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev1, s));
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,

@@ -68,6 +68,27 @@ struct OpSet {
 };
 const OpSet* get_opset(int order, hipStream_t stream);
 
+// Compressed M2L operators (Sec. 2.1.2): one SVD per canonical operator,
+// truncated at s_k >= eps s_1, shared by its 316-offset orbit through the
+// signed permutations; cached per (device, order, eps).
+struct SvdOps {
+  int order = 0;
+  double eps = 0.0;
+  int rank[16] = {0};       // kept singular values per canonical operator
+  int rmax_pad = 0;         // largest padded rank (multiple of 16)
+  double weighted_rank = 0; // sum over the 316 offsets of the rank / 316
+  int64_t flops_per_pair_weighted = 0;  // sum_t 4 l^3 rpad_t / 316, rounded
+  int* rpad = nullptr;      // [316] padded rank per packed operator
+  int64_t* off = nullptr;   // [316] element offset of its factors
+  std::vector<int> rpad_h;
+  double* p1_64 = nullptr;  // S V^T factors in fragment order
+  float* p1_32 = nullptr;
+  double* p2_64 = nullptr;  // U factors in fragment order
+  float* p2_32 = nullptr;
+};
+const SvdOps* get_svd_ops(int order, double eps, hipStream_t stream);
+int kid_canon(int kid);  // canonical class (0..15) of packed operator kid
+
 // ------------------------------------------------------------- the plan
 struct M2LTile {
   int level;
@@ -95,7 +116,8 @@ enum {
   kTabCount = 3 + 2 * kMaxHeight
 };
 
-int m2l_nmb(int mt);  // M-blocks per M2L tile for mt 16-row tiles
+int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
+int m2l_svd_nmb(int mt);  // the same for the compressed M2L
 
 }  // namespace fmm
 
@@ -105,6 +127,8 @@ struct fmm_plan_s {
   int height = 0, order = 0, precision = FMM_FP64;
   double lo[3] = {0, 0, 0}, L = 1.0;
   const fmm::OpSet* ops = nullptr;
+  double m2l_eps = 1e-8;              // truncation of the compressed M2L
+  const fmm::SvdOps* svd = nullptr;   // set when the precision mode compresses
 
   // particles
   double *px = nullptr, *py = nullptr, *pz = nullptr;
@@ -133,6 +157,7 @@ struct fmm_plan_s {
   int64_t far_pairs = 0;           // M2L (target, source) cell pairs
   int64_t far_pairs_level[fmm::kMaxHeight] = {0};
   int64_t active_slots = 0;        // sum over tiles of slots with a source
+  int64_t pairs_by_kid[fmm::kOffsets] = {0};  // far pairs per packed operator
 
   // evaluation buffers
   double *qs = nullptr, *W = nullptr, *Loc = nullptr;

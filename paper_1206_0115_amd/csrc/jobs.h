@@ -55,6 +55,15 @@ struct JobDev {
   double scale[kMaxHeightJ];  // 1 / a_l, the M2L level factor
   const double* kp64;
   const float* kp32;
+  // compressed M2L (svd != 0): per packed operator kid, the padded rank and
+  // the element offset of its two factors in the packs below
+  int svd, xs;
+  const int* svd_rpad;
+  const int64_t* svd_off;
+  const double* p1_64;  // S V^T (rank x l^3) in MFMA fragment order
+  const float* p1_32;
+  const double* p2_64;  // U (l^3 x rank) in MFMA fragment order
+  const float* p2_32;
   const int* slot_kid;
   const double* cheb;
   const double* child;
@@ -98,9 +107,11 @@ __device__ inline int step_find(const StepTab& t, int item) {
 // Host-side launchers (eval.hip / m2l.hip).  `grid` <= 0 means one block per
 // item (the total must then be given); a positive grid makes every block loop
 // over items with that stride (persistent launch).
+// kStepM2LSvd is the compressed M2L; `xs` is then the LDS row stride (the
+// largest padded rank of the launch's jobs + 4).
 enum StepKind { kStepGather, kStepP2M, kStepM2M, kStepCast, kStepM2L, kStepL2L, kStepL2P,
-                kStepP2P, kStepCombine };
+                kStepP2P, kStepCombine, kStepM2LSvd };
 void launch_step(StepKind kind, int order, bool fp32, const JobDev* jobs, const StepTab* tab,
-                 const CallDev* calls, int grid, hipStream_t s);
+                 const CallDev* calls, int grid, hipStream_t s, int xs = 0);
 
 }  // namespace fmm

@@ -18,12 +18,15 @@
 // X(l^3 x 64) on MFMA, X the gathered source multipoles, and writes its local
 // expansions once (no atomics, deterministic).
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "device_util.h"
@@ -296,9 +299,18 @@ __device__ inline f4 mfma16x16x4(float a, float b, f4 c) {
 // lane group g = lane/16 holds k = 16c + 4g + s at step s, so both operands
 // are fetched as 4 consecutive values per lane.  FOLD: FP32 partial sums are
 // added into FP64 accumulators after every far offset.
+// Build-time tuning of the dense kernel: wavefronts per SIMD the register
+// allocation must allow, and whether FP64 double-buffers the B fragments.
+#ifndef FMM_M2L_WAVES_PER_SIMD
+#define FMM_M2L_WAVES_PER_SIMD 2
+#endif
+#ifndef FMM_M2L_F64_PREFETCH_B
+#define FMM_M2L_F64_PREFETCH_B 0
+#endif
+
 template <typename T, int MTW, bool FOLD>
-__global__ __launch_bounds__(256) void m2l_kernel(const JobDev* __restrict__ jobs,
-                                                  const StepTab* __restrict__ tab) {
+__global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
+    const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   typedef typename Vec4<T>::type T4;
   const int total = step_total(*tab);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -347,17 +359,24 @@ __global__ __launch_bounds__(256) void m2l_kernel(const JobDev* __restrict__ job
         bptr[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
       const T* aptr = Kp + (int64_t(kid) * MT + mt0) * KC * 256 + lane * 4;
 
+      // The A fragments are double-buffered one chunk ahead; so are the B
+      // fragments in FP32.  In FP64 the second buffer would cost the second
+      // wavefront per SIMD (registers), which hides those loads instead.
+      constexpr bool kPrefetchB = sizeof(T) == 4 || FMM_M2L_F64_PREFETCH_B;
       T4 bv[4], av[MTW];
       for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j]);
       for (int i = 0; i < MTW; ++i)
         av[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + int64_t(i) * KC * 256)
                         : T4{0, 0, 0, 0};
       for (int c = 0; c < KC; ++c) {
-        T4 bn[4], an[MTW];
+        T4 bn[kPrefetchB ? 4 : 1], an[MTW];
         const bool more = c + 1 < KC;
+        if (!kPrefetchB && c > 0)
+          for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j] + 16 * c);
         if (more) {
-          for (int j = 0; j < 4; ++j)
-            bn[j] = *reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1));
+          if (kPrefetchB)
+            for (int j = 0; j < 4; ++j)
+              bn[kPrefetchB ? j : 0] = *reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1));
           for (int i = 0; i < MTW; ++i)
             an[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + (int64_t(i) * KC + c + 1) * 256)
                             : T4{0, 0, 0, 0};
@@ -369,7 +388,8 @@ __global__ __launch_bounds__(256) void m2l_kernel(const JobDev* __restrict__ job
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
         if (more) {
-          for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+          if (kPrefetchB)
+            for (int j = 0; j < 4; ++j) bv[j] = bn[kPrefetchB ? j : 0];
           for (int i = 0; i < MTW; ++i) av[i] = an[i];
         }
       }
@@ -418,10 +438,11 @@ static void launch_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid
 }
 
 // M-tiles per wavefront: fewest idle M-tile slots, then the largest count
-// (fewest M-blocks, so the gathered source columns are read fewest times).
+// (fewest M-blocks, so the gathered source columns are read fewest times);
+// at most 3, which keeps two wavefronts per SIMD without spills.
 int m2l_mtw(int mt) {
   int best = 1, best_waste = 1 << 30;
-  for (int w = 1; w <= 4; ++w) {
+  for (int w = 1; w <= 3; ++w) {
     const int per_block = 4 * w;
     const int nmb = (mt + per_block - 1) / per_block;
     const int waste = nmb * per_block - mt;
@@ -447,6 +468,387 @@ void launch_m2l_step(int order, bool fp32, const JobDev* jobs, const StepTab* ta
     launch_mtw<float, true>(mtw, jobs, tab, grid, s);
   else
     launch_mtw<double, false>(mtw, jobs, tab, grid, s);
+  FMM_HIP_CHECK(hipGetLastError());
+}
+
+// ============================================================ compressed M2L
+// Sec. 2.1.2: instead of one large SVD of all 316 operators, each of the 16
+// canonical operators Kc gets its own SVD Kc = Uc Sc Vc^T, truncated at
+// s_k >= eps s_1.  An offset t = G tc reuses it through the same signed
+// permutation g as the dense operators:
+//     Kh_t[m][n] ~ sum_k Uc[g(m)][k] s_k Vc[g(n)][k],
+// so per far offset the tile computes X = (S Vc^T)_g W (rank x 64) and then
+// Loc += (Uc)_g X: 4 l^3 r flops per (target, source) pair instead of 2 l^6.
+namespace {
+
+// Factors in MFMA fragment order, per packed operator kid (rank padded to
+// rp = 16 ceil(r/16)), both blocks rp * ld elements at off[kid]:
+//   p1[((i*kc + c)*64 + lane)*4 + s] = s_k Vc[g(n)][k],  k = 16i + lane%16,
+//                                                        n = 16c + 4(lane/16) + s
+//   p2[((i*nr + c)*64 + lane)*4 + s] = Uc[g(m)][k],      m = 16i + lane%16,
+//                                                        k = 16c + 4(lane/16) + s
+// rocSOLVER works column-major: it factorises M = Kc^T (the row-major buffer
+// read column-major) as M = U_M S V_M^T and returns U_M and V_M^T, so
+// Uc[a][k] = Vt[a*n + k] and Vc[b][k] = U[k*n + b].
+__global__ void svd_pack_kernel(const double* __restrict__ U, const double* __restrict__ Vt,
+                                const double* __restrict__ S, const int* __restrict__ info,
+                                const int* __restrict__ rank, const int* __restrict__ rpad,
+                                const int64_t* __restrict__ off, int l, int mt, int kc,
+                                double* __restrict__ p1_64, float* __restrict__ p1_32,
+                                double* __restrict__ p2_64, float* __restrict__ p2_32) {
+  const int kid = blockIdx.y;
+  const int l3 = l * l * l;
+  const int* in = info + 7 * kid;  // canon, pi[3], sg[3]
+  const int c = in[0];
+  const int r = rank[c], rp = rpad[kid], nr = rp / 16;
+  const int64_t nblk = int64_t(rp) * kc * 16;  // elements per factor block
+  const double* Uc = U + int64_t(c) * l3 * l3;
+  const double* Vc = Vt + int64_t(c) * l3 * l3;
+  const double* Sc = S + int64_t(c) * l3;
+  auto gmap = [&](int m) {
+    int mm[3] = {m / (l * l), (m / l) % l, m % l}, gm[3];
+    for (int d = 0; d < 3; ++d) gm[in[1 + d]] = in[4 + d] > 0 ? mm[d] : l - 1 - mm[d];
+    return (gm[0] * l + gm[1]) * l + gm[2];
+  };
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < nblk;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int s = int(e & 3), lane = int((e >> 2) & 63);
+    const int64_t q = e >> 8;
+    {  // phase-1 factor: rows k (rp), columns n (ld)
+      const int cc = int(q % kc), i = int(q / kc);
+      const int k = 16 * i + (lane & 15), n = 16 * cc + 4 * (lane >> 4) + s;
+      double v = 0.0;
+      if (k < r && n < l3) v = Sc[k] * Uc[int64_t(k) * l3 + gmap(n)];
+      p1_64[off[kid] + e] = v;
+      p1_32[off[kid] + e] = float(v);
+    }
+    {  // phase-2 factor: rows m (ld), columns k (rp)
+      const int cc = int(q % nr), i = int(q / nr);
+      const int m = 16 * i + (lane & 15), k = 16 * cc + 4 * (lane >> 4) + s;
+      double v = 0.0;
+      if (m < l3 && k < r) v = Vc[int64_t(gmap(m)) * l3 + k];
+      p2_64[off[kid] + e] = v;
+      p2_32[off[kid] + e] = float(v);
+    }
+  }
+}
+
+std::mutex g_svd_mu;
+std::map<std::tuple<int, int, double>, std::unique_ptr<SvdOps>> g_svd;
+rocblas_handle g_blas[64] = {nullptr};
+
+}  // namespace
+
+int kid_canon(int kid) { return tables().offs[kid].canon; }
+
+const SvdOps* get_svd_ops(int l, double eps, hipStream_t s) {
+  int dev = 0;
+  FMM_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_svd_mu);
+  auto key = std::make_tuple(dev, l, eps);
+  auto it = g_svd.find(key);
+  if (it != g_svd.end()) return it->second.get();
+  const OpSet* op = get_opset(l, s);
+  const StaticTables& T = tables();
+  const int l3 = l * l * l;
+  auto sv = std::make_unique<SvdOps>();
+  sv->order = l;
+  sv->eps = eps;
+
+  std::vector<void*> tmp;
+  auto talloc = [&](size_t b) {
+    void* q = dev_alloc(b);
+    tmp.push_back(q);
+    return q;
+  };
+  try {
+    // the 16 canonical operators, then their SVDs (batched)
+    double xi[kMaxOrder];
+    cheb_nodes(l, xi);
+    std::vector<int> tc(48), info(7 * kOffsets);
+    for (int c = 0; c < 16; ++c)
+      for (int d = 0; d < 3; ++d) tc[3 * c + d] = T.canon[c][d];
+    for (int k = 0; k < kOffsets; ++k) {
+      info[7 * k] = T.offs[k].canon;
+      for (int d = 0; d < 3; ++d) {
+        info[7 * k + 1 + d] = T.offs[k].pi[d];
+        info[7 * k + 4 + d] = T.offs[k].sg[d];
+      }
+    }
+    double* xi_d = static_cast<double*>(talloc(sizeof(double) * l));
+    int* tc_d = static_cast<int*>(talloc(sizeof(int) * 48));
+    int* info_d = static_cast<int*>(talloc(sizeof(int) * info.size()));
+    FMM_HIP_CHECK(hipMemcpyAsync(xi_d, xi, sizeof(double) * l, hipMemcpyHostToDevice, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(tc_d, tc.data(), sizeof(int) * 48, hipMemcpyHostToDevice, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(info_d, info.data(), sizeof(int) * info.size(),
+                                 hipMemcpyHostToDevice, s));
+    const size_t nn = size_t(l3) * l3;
+    double* A = static_cast<double*>(talloc(sizeof(double) * 16 * nn));
+    double* U = static_cast<double*>(talloc(sizeof(double) * 16 * nn));
+    double* Vt = static_cast<double*>(talloc(sizeof(double) * 16 * nn));
+    double* S = static_cast<double*>(talloc(sizeof(double) * 16 * l3));
+    double* E = static_cast<double*>(talloc(sizeof(double) * 16 * l3));
+    int* dinfo = static_cast<int*>(talloc(sizeof(int) * 16));
+    canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, A);
+    FMM_HIP_CHECK(hipGetLastError());
+    if (dev < 0 || dev >= 64) throw FmmError{FMM_ERR_HIP, "device index out of range"};
+    if (!g_blas[dev] && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success)
+      throw FmmError{FMM_ERR_HIP, "rocblas_create_handle failed"};
+    if (rocblas_set_stream(g_blas[dev], s) != rocblas_status_success)
+      throw FmmError{FMM_ERR_HIP, "rocblas_set_stream failed"};
+    const rocblas_status st = rocsolver_dgesvd_strided_batched(
+        g_blas[dev], rocblas_svect_all, rocblas_svect_all, l3, l3, A, l3, rocblas_stride(nn), S,
+        rocblas_stride(l3), U, l3, rocblas_stride(nn), Vt, l3, rocblas_stride(nn), E,
+        rocblas_stride(l3), rocblas_outofplace, dinfo, 16);
+    if (st != rocblas_status_success) throw FmmError{FMM_ERR_HIP, "rocsolver gesvd failed"};
+    std::vector<double> Sh(16 * size_t(l3));
+    int hinfo[16];
+    FMM_HIP_CHECK(hipMemcpyAsync(Sh.data(), S, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(hinfo, dinfo, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    for (int c = 0; c < 16; ++c)
+      if (hinfo[c] != 0) throw FmmError{FMM_ERR_HIP, "rocsolver gesvd did not converge"};
+
+    // ranks: singular values come sorted, largest first
+    int rank_h[16];
+    for (int c = 0; c < 16; ++c) {
+      const double* sc = &Sh[size_t(c) * l3];
+      int r = 0;
+      while (r < l3 && sc[r] >= eps * sc[0]) ++r;
+      rank_h[c] = std::max(r, 1);
+      sv->rank[c] = rank_h[c];
+    }
+    sv->rpad_h.resize(kOffsets);
+    std::vector<int64_t> off(kOffsets);
+    int64_t tot = 0;
+    double wr = 0.0, wf = 0.0;
+    for (int k = 0; k < kOffsets; ++k) {
+      const int r = rank_h[T.offs[k].canon];
+      const int rp = 16 * ((r + 15) / 16);
+      sv->rpad_h[k] = rp;
+      sv->rmax_pad = std::max(sv->rmax_pad, rp);
+      off[k] = tot;
+      tot += int64_t(rp) * op->ld;
+      wr += r;
+      wf += 4.0 * l3 * r;
+    }
+    sv->weighted_rank = wr / kOffsets;
+    sv->flops_per_pair_weighted = int64_t(wf / kOffsets + 0.5);
+    int* rank_d = static_cast<int*>(talloc(sizeof(int) * 16));
+    FMM_HIP_CHECK(hipMemcpyAsync(rank_d, rank_h, sizeof(rank_h), hipMemcpyHostToDevice, s));
+    sv->rpad = static_cast<int*>(dev_alloc(sizeof(int) * kOffsets));
+    sv->off = static_cast<int64_t*>(dev_alloc(sizeof(int64_t) * kOffsets));
+    FMM_HIP_CHECK(hipMemcpyAsync(sv->rpad, sv->rpad_h.data(), sizeof(int) * kOffsets,
+                                 hipMemcpyHostToDevice, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(sv->off, off.data(), sizeof(int64_t) * kOffsets,
+                                 hipMemcpyHostToDevice, s));
+    sv->p1_64 = static_cast<double*>(dev_alloc(sizeof(double) * tot));
+    sv->p2_64 = static_cast<double*>(dev_alloc(sizeof(double) * tot));
+    sv->p1_32 = static_cast<float*>(dev_alloc(sizeof(float) * tot));
+    sv->p2_32 = static_cast<float*>(dev_alloc(sizeof(float) * tot));
+    svd_pack_kernel<<<dim3(64, kOffsets), 256, 0, s>>>(U, Vt, S, info_d, rank_d, sv->rpad,
+                                                        sv->off, l, op->mt, op->kc, sv->p1_64,
+                                                        sv->p1_32, sv->p2_64, sv->p2_32);
+    FMM_HIP_CHECK(hipGetLastError());
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    for (void* q : tmp) dev_free(q);
+    throw;
+  }
+  for (void* q : tmp) dev_free(q);
+  const SvdOps* r = sv.get();
+  g_svd[key] = std::move(sv);
+  return r;
+}
+
+// One workgroup = 4 wavefronts = one (tile, M-block) item.  Per far offset:
+//   phase 1  X(rp x 64) = (S V^T)_g W: wavefront w computes the 16 targets
+//            16w..16w+15 for all rank rows, two 16-row tiles per pass over
+//            the l^3 coefficients; X goes to LDS as X[target][k];
+//   phase 2  Y(l^3 x 64) += U_g X: wavefront w owns MTW 16-row tiles of the
+//            output and all 64 targets; B fragments come from LDS.
+template <typename T, int MTW, bool FOLD>
+__global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
+                                                      const StepTab* __restrict__ tab) {
+  typedef typename Vec4<T>::type T4;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* X = reinterpret_cast<T*>(lds_raw);
+  const int total = step_total(*tab);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c16 = lane & 15;
+  const bool f64 = sizeof(T) == 8;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    int b = it;
+    if (int(gridDim.x) == total) {
+      const int n8 = (total / 8) * 8;
+      if (b < n8) b = (b % 8) * (n8 / 8) + b / 8;
+    }
+    const int k = step_find(*tab, b);
+    const JobDev& J = jobs[tab->job[k]];
+    const int local = b - tab->start[k];
+    const int tile = local / J.nmb, mb = local % J.nmb;
+    const int MT = J.mt, KC = J.kc, ld = J.ld, XS = J.xs;
+    const int mt0 = (mb * 4 + wave) * MTW;
+    const int nmt = mt0 < MT ? min(MTW, MT - mt0) : 0;
+    const M2LTile tl = J.tiles[tile];
+    const T* __restrict__ Wp = FOLD ? reinterpret_cast<const T*>(J.W32)
+                                    : reinterpret_cast<const T*>(J.W);
+    const T* __restrict__ P1 = FOLD ? reinterpret_cast<const T*>(J.p1_32)
+                                    : reinterpret_cast<const T*>(J.p1_64);
+    const T* __restrict__ P2 = FOLD ? reinterpret_cast<const T*>(J.p2_32)
+                                    : reinterpret_cast<const T*>(J.p2_64);
+    T4 acc[MTW][4];
+    d4 acc64[FOLD ? MTW : 1][4];
+    for (int i = 0; i < MTW; ++i)
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = T4{0, 0, 0, 0};
+        if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
+      }
+    const int nact = J.tile_nact[tile];
+    const unsigned char* act = J.tile_act + int64_t(tile) * kSlots;
+    const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN;
+    const int* kidp = J.slot_kid + tl.parity * kSlots;
+
+    for (int ia = 0; ia < nact; ++ia) {
+      const int s = act[ia];
+      const int kid = kidp[s];
+      const int rp = J.svd_rpad[kid], nr = rp >> 4;
+      const int64_t off = J.svd_off[kid];
+      // ---- phase 1: X = (S V^T)_g W for all 64 targets.  Wavefront w takes
+      // the K-chunks w, w+4, ... for up to two rank tiles per pass (eight
+      // independent MFMA chains, no operand loaded twice in the workgroup);
+      // the four partial sums are added into X in wavefront order ----
+      const T* bp[4];
+      for (int j = 0; j < 4; ++j)
+        bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+      for (int i0 = 0; i0 < nr; i0 += 2) {
+        const int np = min(2, nr - i0);
+        const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
+        T4 x[2][4];
+        for (int j = 0; j < 4; ++j) x[0][j] = x[1][j] = T4{0, 0, 0, 0};
+        T4 bv[4], av[2];
+        if (wave < KC) {
+          for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * wave);
+          for (int i = 0; i < 2; ++i)
+            av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + wave) * 256)
+                           : T4{0, 0, 0, 0};
+        }
+        for (int c = wave; c < KC; c += 4) {
+          T4 bn[4], an[2];
+          const bool more = c + 4 < KC;
+          if (more) {
+            for (int j = 0; j < 4; ++j)
+              bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
+            for (int i = 0; i < 2; ++i)
+              an[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256)
+                             : T4{0, 0, 0, 0};
+          }
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
+          if (more) {
+            for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+            for (int i = 0; i < 2; ++i) av[i] = an[i];
+          }
+        }
+        // D rows: FP32 item r -> 4g + r, FP64 item r -> 4r + g
+        for (int w = 0; w < 4; ++w) {
+          if (wave == w)
+            for (int i = 0; i < np; ++i)
+              for (int j = 0; j < 4; ++j) {
+                T* xrow = X + (16 * j + c16) * XS + 16 * (i0 + i);
+                for (int r = 0; r < 4; ++r) {
+                  const int row = f64 ? 4 * r + g : 4 * g + r;
+                  xrow[row] = w == 0 ? x[i][j][r] : xrow[row] + x[i][j][r];
+                }
+              }
+          __syncthreads();
+        }
+      }
+      // ---- phase 2: Loc rows of this wavefront's M-tiles ----
+      if (nmt > 0) {
+        const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
+        for (int c = 0; c < nr; ++c) {
+          T4 bv[4], av[MTW];
+          for (int j = 0; j < 4; ++j)
+            bv[j] = *reinterpret_cast<const T4*>(X + (16 * j + c16) * XS + 16 * c + 4 * g);
+          for (int i = 0; i < MTW; ++i)
+            av[i] = i < nmt ? *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256)
+                            : T4{0, 0, 0, 0};
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int i = 0; i < MTW; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
+        }
+        if (FOLD) {
+          for (int i = 0; i < MTW; ++i)
+            for (int j = 0; j < 4; ++j) {
+              for (int r = 0; r < 4; ++r) acc64[FOLD ? i : 0][j][r] += double(acc[i][j][r]);
+              acc[i][j] = T4{0, 0, 0, 0};
+            }
+        }
+      }
+      __syncthreads();
+    }
+
+    const double sc = J.scale[tl.level];
+    for (int j = 0; j < 4; ++j) {
+      const int col = 16 * j + c16;
+      if (col >= tl.count) continue;
+      double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+      for (int i = 0; i < nmt; ++i) {
+        const int base = 16 * (mt0 + i);
+        for (int r = 0; r < 4; ++r) {
+          const int row = f64 ? 4 * r + g : 4 * g + r;
+          out[base + row] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+        }
+      }
+    }
+  }
+}
+
+// M-tiles per wavefront for the compressed kernel: the whole output in one
+// M-block when it fits 4 x 6 tiles (phase 1 then runs once per tile).
+int m2l_svd_mtw(int mt) {
+  for (int w = 1; w <= 6; ++w)
+    if (4 * w >= mt) return w;
+  return 6;
+}
+
+int m2l_svd_nmb(int mt) {
+  const int w = m2l_svd_mtw(mt);
+  return (mt + 4 * w - 1) / (4 * w);
+}
+
+template <typename T, bool FOLD>
+static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid,
+                           size_t lds, hipStream_t s) {
+  switch (mtw) {
+    case 1: m2l_svd_kernel<T, 1, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 2: m2l_svd_kernel<T, 2, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 3: m2l_svd_kernel<T, 3, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 4: m2l_svd_kernel<T, 4, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 5: m2l_svd_kernel<T, 5, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    default: m2l_svd_kernel<T, 6, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+  }
+}
+
+void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
+                         int xs, hipStream_t s) {
+  const int l3 = order * order * order;
+  const int mtw = m2l_svd_mtw((l3 + 15) / 16);
+  const size_t lds = size_t(kTileN) * xs * (fp32 ? sizeof(float) : sizeof(double));
+  if (fp32)
+    launch_svd_mtw<float, true>(mtw, jobs, tab, grid, lds, s);
+  else
+    launch_svd_mtw<double, false>(mtw, jobs, tab, grid, lds, s);
   FMM_HIP_CHECK(hipGetLastError());
 }
 

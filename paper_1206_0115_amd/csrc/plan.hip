@@ -396,7 +396,8 @@ __global__ __launch_bounds__(64) void tile_src_kernel(
     const LevelDev* __restrict__ levels, const int64_t* __restrict__ lev_off,
     const signed char* __restrict__ slot_t,  // [8][189][3]
     int zero_row, int* __restrict__ tile_src, unsigned char* __restrict__ act,
-    int* __restrict__ nact, unsigned long long* __restrict__ pairs_level) {
+    int* __restrict__ nact, unsigned long long* __restrict__ pairs_level,
+    const int* __restrict__ slot_kid, unsigned long long* __restrict__ pairs_kid) {
   const int tile = blockIdx.x, j = threadIdx.x;
   const M2LTile T = tiles[tile];
   const LevelDev L = levels[T.level];
@@ -416,7 +417,11 @@ __global__ __launch_bounds__(64) void tile_src_kernel(
     out[s * kTileN + j] = b >= 0 ? b + int(lev_off[T.level]) : zero_row;
     const uint64_t m = __ballot(b >= 0);
     if (m) {
-      if (j == 0) act[int64_t(tile) * kSlots + na] = (unsigned char)s;
+      if (j == 0) {
+        act[int64_t(tile) * kSlots + na] = (unsigned char)s;
+        atomicAdd(&pairs_kid[slot_kid[T.parity * kSlots + s]],
+                  (unsigned long long)__popcll(m));
+      }
       ++na;
       npairs += __popcll(m);
     }
@@ -566,9 +571,11 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   }
 
   // --- near lists ---
+  // counters: far pairs per level, near pairs, then far pairs per operator
+  const size_t ncount = kMaxHeight + 2 + kOffsets;
   unsigned long long* counters =
-      static_cast<unsigned long long*>(talloc(sizeof(unsigned long long) * (kMaxHeight + 2)));
-  FMM_HIP_CHECK(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * (kMaxHeight + 2), s));
+      static_cast<unsigned long long*>(talloc(sizeof(unsigned long long) * ncount));
+  FMM_HIP_CHECK(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * ncount, s));
   p->near = static_cast<int*>(p->alloc(sizeof(int) * 27 * nl));
   near_kernel<<<grid_for(nl, 256), 256, 0, s>>>(ldev[h - 1], p->leaf_start, p->near,
                                                 counters + kMaxHeight);
@@ -645,15 +652,17 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
       FMM_HIP_CHECK(hipMemcpyAsync(off_d, offs_h, sizeof(offs_h), hipMemcpyHostToDevice, s));
       tile_src_kernel<<<unsigned(p->ntiles), 64, 0, s>>>(
           p->tiles, p->tgt, ld_d, off_d, p->ops->slot_t,
-          int(p->ncell_total), p->tile_src, p->tile_act, p->tile_nact, counters);
+          int(p->ncell_total), p->tile_src, p->tile_act, p->tile_nact, counters,
+          p->ops->slot_kid, counters + kMaxHeight + 2);
       FMM_HIP_CHECK(hipGetLastError());
     }
   }
 
   // --- statistics ---
-  unsigned long long hc[kMaxHeight + 2];
+  unsigned long long hc[kMaxHeight + 2 + kOffsets];
   FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
   FMM_HIP_CHECK(hipStreamSynchronize(s));
+  for (int k = 0; k < kOffsets; ++k) p->pairs_by_kid[k] = int64_t(hc[kMaxHeight + 2 + k]);
   p->near_pairs = int64_t(hc[kMaxHeight]);
   p->far_pairs = 0;
   for (int l = 0; l < kMaxHeight; ++l) {

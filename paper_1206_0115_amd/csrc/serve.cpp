@@ -39,7 +39,8 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // block loops over the items of the batch with this stride).
 int persistent_grid(StepKind k) {
   switch (k) {
-    case kStepM2L: return 512;
+    case kStepM2L:
+    case kStepM2LSvd: return 512;
     case kStepP2P:
     case kStepP2M:
     case kStepL2P: return 4096;
@@ -67,6 +68,7 @@ struct Launch {
   StepKind kind;
   int order;
   bool fp32;
+  int xs;  // LDS row stride of the compressed M2L
 };
 
 struct TableBuf {
@@ -242,7 +244,7 @@ bool fmm_server_s::launch_batch() {
   auto add = [&](StepKind kind, int order, bool fp32, auto want, auto items, auto level) {
     StepTab& t = tabs[seq.size()];
     std::memset(&t, 0, sizeof(t));
-    int tot = 0;
+    int tot = 0, xs = 0;
     for (int j = 0; j < nj; ++j) {
       if (!want(reqs[j])) continue;
       const int it = items(reqs[j]);
@@ -251,19 +253,25 @@ bool fmm_server_s::launch_batch() {
       t.level[t.njobs] = level(reqs[j]);
       t.start[t.njobs] = tot;
       tot += it;
+      xs = std::max(xs, reqs[j]->plan->job_h.xs);
       ++t.njobs;
     }
     t.start[t.njobs] = tot;
     if (t.njobs == 0) return;
     if (seq.size() + 1 >= size_t(kMaxSteps)) throw FmmError{FMM_ERR_HIP, "batch step table full"};
-    seq.push_back({kind, order, fp32});
-    key += std::to_string(int(kind)) + ":" + std::to_string(order) + (fp32 ? "f" : "d") + ";";
+    if (kind != kStepM2LSvd) xs = 0;
+    seq.push_back({kind, order, fp32, xs});
+    key += std::to_string(int(kind)) + ":" + std::to_string(order) + (fp32 ? "f" : "d") + ":" +
+           std::to_string(xs) + ";";
   };
   auto all_ = [](Request*) { return true; };
   auto lvl0 = [](Request*) { return 0; };
   auto chunks = [](Request* r) { return int((r->n + 255) / 256); };
   auto far = [](Request* r) { return r->h >= 3; };
-  auto mixed = [](Request* r) { return r->prec == FMM_MIXED_FP32; };
+  auto mixed = [](Request* r) {
+    return r->prec == FMM_MIXED_FP32 || r->prec == FMM_MIXED_SVD;
+  };
+  auto svd = [](Request* r) { return r->plan->svd != nullptr; };
 
   std::vector<int> orders;
   for (Request* r : reqs)
@@ -285,9 +293,12 @@ bool fmm_server_s::launch_batch() {
       [](Request* r) { return int(r->plan->ncell_total + 1 - r->plan->lev[2].off); }, lvl0);
   for (int L : orders)
     for (int f32 = 0; f32 < 2; ++f32)
-      add(kStepM2L, L, f32 != 0,
-          [&](Request* r) { return far(r) && r->order == L && mixed(r) == (f32 != 0); },
-          [](Request* r) { return int(r->plan->ntiles) * r->plan->job_h.nmb; }, lvl0);
+      for (int cmp = 0; cmp < 2; ++cmp)
+        add(cmp ? kStepM2LSvd : kStepM2L, L, f32 != 0,
+            [&](Request* r) {
+              return far(r) && r->order == L && mixed(r) == (f32 != 0) && svd(r) == (cmp != 0);
+            },
+            [](Request* r) { return int(r->plan->ntiles) * r->plan->job_h.nmb; }, lvl0);
   for (int s = 0; s < steps; ++s)
     add(kStepL2L, 0, false, [&](Request* r) { return r->h - 4 >= s; },
         [&](Request* r) { return int(r->plan->lev[3 + s].ncell); },
@@ -312,7 +323,7 @@ bool fmm_server_s::launch_batch() {
     FMM_HIP_CHECK(hipMemcpyAsync(B.dev, B.pinned, kTableBytes, hipMemcpyHostToDevice, exec_stream));
     for (size_t i = 0; i < seq.size(); ++i)
       launch_step(seq[i].kind, seq[i].order, seq[i].fp32, jobs_d, tabs_d + i, calls_d,
-                  persistent_grid(seq[i].kind), exec_stream);
+                  persistent_grid(seq[i].kind), exec_stream, seq[i].xs);
     FMM_HIP_CHECK(hipStreamEndCapture(exec_stream, &g));
     hipGraphExec_t ge = nullptr;
     FMM_HIP_CHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -444,7 +455,7 @@ int64_t fmm_server_submit(fmm_server_t s, const double* positions, const double*
     return FMM_ERR_ARG;
   }
   if (n < 1 || n > int64_t(2147483646) || height < 1 || height > kMaxHeight || order < 1 ||
-      order > kMaxOrder || (precision != FMM_FP64 && precision != FMM_MIXED_FP32)) {
+      order > kMaxOrder || precision < FMM_FP64 || precision > FMM_MIXED_SVD) {
     set_error("invalid n, height, order or precision");
     return FMM_ERR_ARG;
   }

@@ -16,8 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_ERR_ARG, FMM_ERR_OOM, FMM_ERR_HIP, FMM_ERR_STATE = 0, -1, -2, -3, -4
-FMM_FP64, FMM_MIXED_FP32 = 0, 1
-PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED_FP32}
+FMM_FP64, FMM_MIXED_FP32, FMM_FP64_SVD, FMM_MIXED_SVD = 0, 1, 2, 3
+PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED_FP32,
+              "fp64_svd": FMM_FP64_SVD, "mixed_svd": FMM_MIXED_SVD}
 
 EXPORT_KEYS, EXPORT_PERM, EXPORT_LEAF_START, EXPORT_CELL_KEYS = 0, 1, 2, 3
 EXPORT_NEAR_OFF, EXPORT_NEAR_IDX, EXPORT_FAR_OFF, EXPORT_FAR_IDX = 4, 5, 6, 7
@@ -43,6 +44,16 @@ class FmmInfo(ctypes.Structure):
         ("m2l_tiles", ctypes.c_int64),
         ("m2l_active_slots", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
+        ("m2l_flops", ctypes.c_double),
+    ]
+
+
+class SvdInfo(ctypes.Structure):
+    _fields_ = [
+        ("eps", ctypes.c_double),
+        ("rank", ctypes.c_int32 * 16),
+        ("rmax_pad", ctypes.c_int32),
+        ("weighted_rank", ctypes.c_double),
     ]
 
 
@@ -84,6 +95,8 @@ def lib():
     L.fmm_release.restype = None
     L.fmm_last_error.restype = ctypes.c_char_p
     L.fmm_plan_set_precision.argtypes = [vp, i32]
+    L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
+    L.fmm_plan_svd_info.argtypes = [vp, ctypes.POINTER(SvdInfo)]
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
     L.fmm_plan_export.argtypes = [vp, i32, i32, vp, sz]
     L.fmm_set_m2l_timing_events.argtypes = [vp, vp]
@@ -157,6 +170,14 @@ class Plan:
         mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         _check(lib().fmm_plan_set_precision(self._h, mode))
         self.precision = mode
+
+    def set_m2l_tolerance(self, eps: float):
+        _check(lib().fmm_plan_set_m2l_tolerance(self._h, float(eps)))
+
+    def svd_info(self) -> SvdInfo:
+        out = SvdInfo()
+        _check(lib().fmm_plan_svd_info(self._h, ctypes.byref(out)))
+        return out
 
     def evaluate(self, charges, potential=None, forces=None, stream=None):
         import torch

@@ -1,0 +1,91 @@
+"""Compressed M2L on the GPU (Sec. 2.1.2, one SVD per canonical operator,
+reused over its 316-offset orbit by signed permutations) against the oracle's
+compressed M2L (one SVD per offset, no symmetry) at the same tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1206_0115_amd import fmm, inputs
+
+pytestmark = pytest.mark.gpu
+
+SVD_TOL = 1e-10  # two independent SVD routines; everything else FP64
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+CASES = [
+    ("cube", 20000, 4, 5, 1001, 1e-7),
+    ("sphere", 6000, 5, 4, 14, 1e-8),
+    ("cube", 3000, 3, 7, 13, 1e-6),
+    ("cube", 2500, 3, 9, 19, 1e-9),
+    ("cube", 700, 6, 3, 15, 1e-5),
+]
+
+
+@pytest.mark.parametrize("kind,n,h,l,seed,eps", CASES)
+def test_compressed_parity_with_oracle(kind, n, h, l, seed, eps):
+    print(f"compressed parity {kind} n={n} h={h} l={l} eps={eps}", flush=True)
+    pos, q = inputs.make(kind, n, seed)
+    plan = fmm.Plan(dev(pos), h, l)
+    plan.set_m2l_tolerance(eps)
+    plan.set_precision("fp64_svd")
+    ops, ranks = oracle.compressed_unit_ops(l, eps)
+    si = plan.svd_info()
+    assert si.weighted_rank == pytest.approx(np.mean(list(ranks.values())), abs=1e-12)
+    assert sorted(si.rank) == sorted({tuple(sorted(map(abs, t), reverse=True)): r
+                                      for t, r in ranks.items()}.values())
+    tree = oracle.Tree(pos, h)
+    p_o, f_o = tree.fmm(l, q, unit_ops=ops)
+    phi, f = plan.evaluate(dev(q))
+    torch.cuda.synchronize()
+    e = max(rel(host(phi), p_o), rel(host(f), f_o))
+    print(f"  vs compressed oracle {e:.2e}", flush=True)
+    assert e <= SVD_TOL
+    # and against the dense FP64 path on the GPU: of the order of eps
+    plan.set_precision("fp64")
+    p64, f64 = plan.evaluate(dev(q))
+    torch.cuda.synchronize()
+    assert max(rel(host(phi), host(p64)), rel(host(f), host(f64))) < 10 * eps
+
+
+def test_mixed_compressed_full_size_gate():
+    kind, n, h, l, seed = inputs.CONFIGS["cube1m_h6_p7"]
+    pos, q = inputs.make(kind, n, seed)
+    plan = fmm.Plan(dev(pos), h, l)
+    p64, f64 = [host(t) for t in plan.evaluate(dev(q))]
+    for mode, gate in (("fp64_svd", 1e-7), ("mixed_svd", 1e-6)):
+        plan.set_precision(mode)
+        phi, f = [host(t) for t in plan.evaluate(dev(q))]
+        e = max(rel(phi, p64), rel(f, f64))
+        print(f"  {mode} (eps {plan.svd_info().eps:g}) vs fp64 {e:.2e}", flush=True)
+        assert e <= gate
+    inf = plan.info()
+    assert 0 < inf.m2l_flops < 2.0 * l ** 6 * inf.far_pairs / 3
+
+
+def test_compressed_deterministic():
+    pos, q = inputs.sphere_surface(30000, 43)
+    plan = fmm.Plan(dev(pos), 6, 5, "mixed_svd")
+    a = [host(t) for t in plan.evaluate(dev(q))]
+    b = [host(t) for t in plan.evaluate(dev(q))]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_tolerance_rejects_bad_values():
+    pos, _ = inputs.uniform_cube(100, 44)
+    plan = fmm.Plan(dev(pos), 3, 4)
+    for bad in (0.0, 1.0, -1e-3, float("nan")):
+        with pytest.raises(fmm.FMMError):
+            plan.set_m2l_tolerance(bad)

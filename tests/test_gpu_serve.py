@@ -24,7 +24,7 @@ def make_requests(k, seed=0):
         kind = "cube" if rng.random() < 0.5 else "sphere"
         l = int(rng.choice([3, 5, 7]))
         h = int(rng.integers(2, 6))
-        prec = "mixed" if rng.random() < 0.4 else "fp64"
+        prec = ["fp64", "mixed", "fp64_svd", "mixed_svd"][int(rng.integers(0, 4))]
         pos, q = inputs.make(kind, n, 500 + i)
         reqs.append((torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda(), h, l, prec))
     return reqs
