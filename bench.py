@@ -174,6 +174,77 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+COPY_BYTES = 1 << 30  # the plain copy that calibrates the HBM counters
+
+
+def run_traffic_probe(args):
+    """One copy of COPY_BYTES (device to device) and then, for every
+    precision mode, one plan + evaluation of the workload: the program that
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs to measure HBM traffic."""
+    import torch
+
+    from paper_1206_0115_amd import fmm, inputs
+
+    fmm.lib()
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    kind, n, h, l, seed = inputs.CONFIGS[args.workload]
+    pos, q = inputs.make(kind, n, seed)
+    pos_d, q_d = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
+    for m in ("fp64", "mixed", "fp64_svd", "mixed_svd"):
+        p = fmm.Plan(pos_d, h, l, m)
+        p.evaluate(q_d)
+        torch.cuda.synchronize()
+        p.release()
+        print("probe", m, flush=True)
+
+
+def ingest_traffic(args):
+    """Turn the two counter CSVs of the traffic probe into
+    profiles/m2l_traffic.json: per mode, the M2L launch's HBM bytes, with
+    FETCH_SIZE and WRITE_SIZE each scaled so that the calibration copy reads
+    exactly COPY_BYTES."""
+    import csv
+
+    def per_dispatch(path, counter):
+        out = []
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        out.sort()
+        return out
+
+    fetch = per_dispatch(args.ingest_traffic[0], "FETCH_SIZE")
+    write = per_dispatch(args.ingest_traffic[1], "WRITE_SIZE")
+    modes = ["fp64", "mixed", "fp64_svd", "mixed_svd"]
+
+    def scale_and_m2l(rows):
+        copies = [v for _, k, v in rows if "copy" in k.lower()]
+        cal = max(copies)  # the 1 GiB copy is the largest copy dispatch
+        m2l = [v for _, k, v in rows if "m2l_kernel" in k or "m2l_svd_kernel" in k]
+        return COPY_BYTES / (cal * 1024.0), cal, m2l
+
+    sf, calf, mf = scale_and_m2l(fetch)
+    sw, calw, mw = scale_and_m2l(write)
+    if len(mf) != len(modes) or len(mw) != len(modes):
+        raise SystemExit(f"expected {len(modes)} M2L dispatches, got {len(mf)}/{len(mw)}")
+    path = os.path.join(ROOT, "profiles", "m2l_traffic.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d[args.workload] = {}
+    for m, fv, wv in zip(modes, mf, mw):
+        d[args.workload][m] = {
+            "fetch_kib_raw": fv, "write_kib_raw": wv,
+            "fetch_scale": sf, "write_scale": sw,
+            "copy_fetch_kib_raw": calf, "copy_write_kib_raw": calw,
+            "bytes_per_launch": fv * 1024.0 * sf + wv * 1024.0 * sw,
+            "kernel_sha": m2l_source_hash()}
+    json.dump(d, open(path, "w"), indent=1)
+    print(json.dumps(d[args.workload]))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +257,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--serve", action="store_true",
                     help="benchmark the serving loop instead (Poisson request stream)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="the program to run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/m2l_traffic.json from the two counter CSVs")
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-precision", default="mixed_svd",
@@ -199,6 +274,12 @@ def main():
                   f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 
+    if args.ingest_traffic:
+        ingest_traffic(args)
+        return
+    if args.traffic_probe:
+        run_traffic_probe(args)
+        return
     if args.serve:
         run_serve(args)
         return

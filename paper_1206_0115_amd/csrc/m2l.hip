@@ -411,7 +411,9 @@ __global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
       const int col = 16 * j + c16;
       if (col >= tl.count) continue;
       double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
-      for (int i = 0; i < nmt; ++i) {
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        if (i >= nmt) continue;  // constant trip count keeps acc[] in registers
         const int base = 16 * (mt0 + i);
         if (f64) {
           for (int r = 0; r < 4; ++r)
@@ -759,8 +761,11 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
         // D rows: FP32 item r -> 4g + r, FP64 item r -> 4r + g
         for (int w = 0; w < 4; ++w) {
           if (wave == w)
-            for (int i = 0; i < np; ++i)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
               for (int j = 0; j < 4; ++j) {
+                if (i >= np) continue;
                 T* xrow = X + (16 * j + c16) * XS + 16 * (i0 + i);
                 for (int r = 0; r < 4; ++r) {
                   const int row = f64 ? 4 * r + g : 4 * g + r;
@@ -803,7 +808,9 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
       const int col = 16 * j + c16;
       if (col >= tl.count) continue;
       double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
-      for (int i = 0; i < nmt; ++i) {
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        if (i >= nmt) continue;
         const int base = 16 * (mt0 + i);
         for (int r = 0; r < 4; ++r) {
           const int row = f64 ? 4 * r + g : 4 * g + r;
