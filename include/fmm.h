@@ -129,6 +129,20 @@ const char* fmm_last_error(void);
 /* Select the arithmetic of later evaluations (enum fmm_precision). */
 int fmm_plan_set_precision(fmm_plan_t plan, int mode);
 
+/* Task schedule of later evaluations (the FMM task flow of Sec. 3.2 and its
+ * pipelining, Sec. 3.3).  The near field (P2P) depends only on the charges
+ * and the far field (P2M, M2M, M2L, L2L, L2P) writes other buffers, so the two
+ * branches may run at the same time and meet at the final sum.
+ *   FMM_SCHEDULE_SERIAL  every operator in order on the caller's stream
+ *   FMM_SCHEDULE_FORKED  (default) P2P on a stream owned by the plan, forked
+ *                        from and joined back into the caller's stream with
+ *                        events; the far chain stays on the caller's stream
+ * Both schedules launch the same kernels on the same data: results are
+ * bit-identical.  Stream capture of the caller's stream captures the fork
+ * and the join.  Returns FMM_ERR_ARG for a null plan or unknown schedule. */
+enum fmm_schedule { FMM_SCHEDULE_SERIAL = 0, FMM_SCHEDULE_FORKED = 1 };
+int fmm_plan_set_schedule(fmm_plan_t plan, int schedule);
+
 /* Plan facts (host struct). */
 struct fmm_info {
   int64_t n;

@@ -120,6 +120,9 @@ fmm_plan_s::~fmm_plan_s() {
     (void)hipEventSynchronize(done);
     (void)hipEventDestroy(done);
   }
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (side) (void)hipStreamDestroy(side);
   for (void* p : blocks) fmm::dev_free(p);
 }
 
@@ -207,6 +210,9 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
     }
     fmm::upload_job(p, stream);
     FMM_HIP_CHECK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
     return FMM_OK;
   });
   if (rc != FMM_OK) {
@@ -232,12 +238,29 @@ static void apply_mode(fmm_plan_s* p, int mode) {
   if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
   const bool mixed = mode == FMM_MIXED_FP32 || mode == FMM_MIXED_SVD;
   const bool svd = mode == FMM_FP64_SVD || mode == FMM_MIXED_SVD;
+  const fmm::SvdOps* sv = svd && p->height >= 3
+                             ? fmm::get_svd_ops(p->order, p->m2l_eps, p->last_stream)
+                             : nullptr;
+  if (sv) {
+    // the compressed kernel keeps four rank x 16*NT slabs in LDS
+    const size_t need = fmm::m2l_svd_lds_bytes(sv->rmax_pad + 4, mixed);
+    int have = 0;
+    FMM_HIP_CHECK(hipDeviceGetAttribute(&have, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                        p->device));
+    if (need > size_t(have))
+      throw fmm::FmmError{FMM_ERR_ARG,
+                          "compressed M2L at order " + std::to_string(p->order) +
+                              " and tolerance " + std::to_string(p->m2l_eps) + " keeps rank " +
+                              std::to_string(sv->rmax_pad) + " and needs " +
+                              std::to_string(need) + " B of LDS (device: " +
+                              std::to_string(have) +
+                              "); use a larger tolerance or the dense mode"};
+  }
   if (mixed && !p->W32 && p->height >= 3) {
     const size_t rows = size_t(p->ncell_total + 1);
     p->W32 = static_cast<float*>(p->alloc(sizeof(float) * rows * p->ops->ld));
   }
-  p->svd = svd && p->height >= 3 ? fmm::get_svd_ops(p->order, p->m2l_eps, p->last_stream)
-                                 : nullptr;
+  p->svd = sv;
   p->precision = mode;
   fmm::upload_job(p, p->last_stream);
 }
@@ -253,13 +276,30 @@ int fmm_plan_set_precision(fmm_plan_t p, int mode) {
   });
 }
 
+int fmm_plan_set_schedule(fmm_plan_t p, int schedule) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (schedule != FMM_SCHEDULE_SERIAL && schedule != FMM_SCHEDULE_FORKED)
+    return fail(FMM_ERR_ARG, "unknown schedule " + std::to_string(schedule));
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->schedule = schedule;
+    return FMM_OK;
+  });
+}
+
 int fmm_plan_set_m2l_tolerance(fmm_plan_t p, double eps) {
   if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
   if (!(eps > 0.0 && eps < 1.0)) return fail(FMM_ERR_ARG, "tolerance must be in (0, 1)");
   return guarded([&]() -> int {
     std::lock_guard<std::mutex> lk(p->mu);
+    const double prev = p->m2l_eps;
     p->m2l_eps = eps;
-    apply_mode(p, p->precision);
+    try {
+      apply_mode(p, p->precision);
+    } catch (...) {
+      p->m2l_eps = prev;
+      throw;
+    }
     return FMM_OK;
   });
 }

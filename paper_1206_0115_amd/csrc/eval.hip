@@ -576,7 +576,8 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
 }
 
 // One plan: the step tables were built at plan time; every launch has one
-// block per item.
+// block per item.  In the forked schedule the near field runs on the plan's
+// side stream between two events, concurrently with the far chain.
 void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* phi_n,
               double* f_n, double* phi_f, double* f_f, hipStream_t s) {
   const int L = p->order, h = p->height;
@@ -585,6 +586,13 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   const unsigned chunks = unsigned((p->n + kChunk - 1) / kChunk);
   gather1_kernel<<<chunks, kChunk, 0, s>>>(J, q);
   FMM_HIP_CHECK(hipGetLastError());
+  const bool forked = p->schedule == FMM_SCHEDULE_FORKED;
+  if (forked) {
+    FMM_HIP_CHECK(hipEventRecord(p->ev_fork, s));
+    FMM_HIP_CHECK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), p->side);
+    FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
+  }
   if (h >= 3) {
     launch_step(kStepP2M, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
     for (int st = 0; st + 4 <= h; ++st)
@@ -603,7 +611,10 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
                   p->tab_h[kTabL2L + st].start[1], s);
     launch_step(kStepL2P, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
   }
-  launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+  if (forked)
+    FMM_HIP_CHECK(hipStreamWaitEvent(s, p->ev_join, 0));
+  else
+    launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
   CallDev c{q, phi, f, phi_n, f_n, phi_f, f_f};
   combine1_kernel<<<chunks, kChunk, 0, s>>>(J, c);
   FMM_HIP_CHECK(hipGetLastError());

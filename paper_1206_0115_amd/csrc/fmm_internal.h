@@ -118,6 +118,8 @@ enum {
 
 int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
 int m2l_svd_nmb(int mt);  // the same for the compressed M2L
+// LDS bytes of one compressed-M2L workgroup for a slab stride of xs values
+size_t m2l_svd_lds_bytes(int xs, bool fp32);
 
 }  // namespace fmm
 
@@ -171,6 +173,9 @@ struct fmm_plan_s {
   fmm::StepTab* tab_d = nullptr;
 
   hipEvent_t done = nullptr;       // recorded after each evaluation
+  int schedule = FMM_SCHEDULE_FORKED;
+  hipStream_t side = nullptr;      // the near-field branch of the forked schedule
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool in_flight = false;
   hipStream_t last_stream = nullptr;  // stream of the last evaluation
   std::vector<void*> blocks;       // every device block this plan owns

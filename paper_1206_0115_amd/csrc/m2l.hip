@@ -664,18 +664,44 @@ const SvdOps* get_svd_ops(int l, double eps, hipStream_t s) {
   return r;
 }
 
-// One workgroup = 4 wavefronts = one (tile, M-block) item.  Per far offset:
-//   phase 1  X(rp x 64) = (S V^T)_g W: wavefront w computes the 16 targets
-//            16w..16w+15 for all rank rows, two 16-row tiles per pass over
-//            the l^3 coefficients; X goes to LDS as X[target][k];
-//   phase 2  Y(l^3 x 64) += U_g X: wavefront w owns MTW 16-row tiles of the
-//            output and all 64 targets; B fragments come from LDS.
-template <typename T, int MTW, bool FOLD>
-__global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
-                                                      const StepTab* __restrict__ tab) {
+// Target columns per workgroup of the compressed kernel: 16 * FMM_M2L_SVD_NT
+// (2: half a tile, which keeps two workgroups per CU; 4: the whole tile).
+#ifndef FMM_M2L_SVD_NT
+#define FMM_M2L_SVD_NT 2
+#endif
+constexpr int kSvdNT = FMM_M2L_SVD_NT;
+static_assert(kSvdNT == 1 || kSvdNT == 2 || kSvdNT == 4, "16, 32 or 64 target columns");
+// Whether phase 2 loads its U fragments one rank chunk ahead.
+#ifndef FMM_M2L_SVD_P2_PREFETCH
+#define FMM_M2L_SVD_P2_PREFETCH 0
+#endif
+// Wavefronts per SIMD the register allocation must allow, FP32 and FP64.
+#ifndef FMM_M2L_SVD_WAVES_F32
+#define FMM_M2L_SVD_WAVES_F32 1
+#endif
+#ifndef FMM_M2L_SVD_WAVES_F64
+#define FMM_M2L_SVD_WAVES_F64 1
+#endif
+
+// One workgroup = 4 wavefronts = one (tile, M-block, N-group) item, the
+// N-group being NC = 16 NT of the tile's 64 target columns.  Per far offset:
+//   phase 1  X(rp x NC) = (S V^T)_g W.  Wavefront w takes the K-chunks w,
+//            w+4, ... of the l^3 contraction for every rank tile (two per
+//            pass) and writes its partial sums to its own LDS slab P[w];
+//   phase 2  Y(l^3 x NC) += U_g X, X read as P[0]+P[1]+P[2]+P[3] (always
+//            in that order, so every wavefront sees the same X and the
+//            result does not depend on timing).  Wavefront w owns MTW
+//            16-row M-tiles of the output.
+// Two barriers per offset: after the partial sums, and before the slabs
+// are overwritten by the next offset.
+template <typename T, int MTW, int NT, bool FOLD>
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
+                                                 : FMM_M2L_SVD_WAVES_F64) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
+                                                         const StepTab* __restrict__ tab) {
   typedef typename Vec4<T>::type T4;
+  constexpr int NC = 16 * NT, NG = 4 / NT;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* X = reinterpret_cast<T*>(lds_raw);
+  T* P = reinterpret_cast<T*>(lds_raw);
   const int total = step_total(*tab);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
@@ -689,27 +715,32 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
     const int k = step_find(*tab, b);
     const JobDev& J = jobs[tab->job[k]];
     const int local = b - tab->start[k];
-    const int tile = local / J.nmb, mb = local % J.nmb;
+    const int tile = local / J.nmb, rem = local % J.nmb;
+    const int mb = rem / NG, col0 = NC * (rem % NG);
+    const M2LTile tl = J.tiles[tile];
+    if (col0 >= tl.count) continue;  // the same for the whole workgroup
     const int MT = J.mt, KC = J.kc, ld = J.ld, XS = J.xs;
     const int mt0 = (mb * 4 + wave) * MTW;
     const int nmt = mt0 < MT ? min(MTW, MT - mt0) : 0;
-    const M2LTile tl = J.tiles[tile];
     const T* __restrict__ Wp = FOLD ? reinterpret_cast<const T*>(J.W32)
                                     : reinterpret_cast<const T*>(J.W);
     const T* __restrict__ P1 = FOLD ? reinterpret_cast<const T*>(J.p1_32)
                                     : reinterpret_cast<const T*>(J.p1_64);
     const T* __restrict__ P2 = FOLD ? reinterpret_cast<const T*>(J.p2_32)
                                     : reinterpret_cast<const T*>(J.p2_64);
-    T4 acc[MTW][4];
-    d4 acc64[FOLD ? MTW : 1][4];
+    T* Pw = P + wave * NC * XS;
+    T4 acc[MTW][NT];
+    d4 acc64[FOLD ? MTW : 1][NT];
+#pragma unroll
     for (int i = 0; i < MTW; ++i)
-      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
         acc[i][j] = T4{0, 0, 0, 0};
         if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
       }
     const int nact = J.tile_nact[tile];
     const unsigned char* act = J.tile_act + int64_t(tile) * kSlots;
-    const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN;
+    const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN + col0;
     const int* kidp = J.slot_kid + tl.parity * kSlots;
 
     for (int ia = 0; ia < nact; ++ia) {
@@ -717,31 +748,34 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
       const int kid = kidp[s];
       const int rp = J.svd_rpad[kid], nr = rp >> 4;
       const int64_t off = J.svd_off[kid];
-      // ---- phase 1: X = (S V^T)_g W for all 64 targets.  Wavefront w takes
-      // the K-chunks w, w+4, ... for up to two rank tiles per pass (eight
-      // independent MFMA chains, no operand loaded twice in the workgroup);
-      // the four partial sums are added into X in wavefront order ----
-      const T* bp[4];
-      for (int j = 0; j < 4; ++j)
+      // ---- phase 1: this wavefront's share of X, into its slab ----
+      const T* bp[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
         bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
       for (int i0 = 0; i0 < nr; i0 += 2) {
         const int np = min(2, nr - i0);
         const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
-        T4 x[2][4];
-        for (int j = 0; j < 4; ++j) x[0][j] = x[1][j] = T4{0, 0, 0, 0};
-        T4 bv[4], av[2];
+        T4 x[2][NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) x[0][j] = x[1][j] = T4{0, 0, 0, 0};
+        T4 bv[NT], av[2];
         if (wave < KC) {
-          for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * wave);
+#pragma unroll
+          for (int j = 0; j < NT; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * wave);
+#pragma unroll
           for (int i = 0; i < 2; ++i)
             av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + wave) * 256)
                            : T4{0, 0, 0, 0};
         }
         for (int c = wave; c < KC; c += 4) {
-          T4 bn[4], an[2];
+          T4 bn[NT], an[2];
           const bool more = c + 4 < KC;
           if (more) {
-            for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
               bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
+#pragma unroll
             for (int i = 0; i < 2; ++i)
               an[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256)
                              : T4{0, 0, 0, 0};
@@ -751,50 +785,84 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
+              for (int j = 0; j < NT; ++j)
                 if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
           if (more) {
-            for (int j = 0; j < 4; ++j) bv[j] = bn[j];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bv[j] = bn[j];
+#pragma unroll
             for (int i = 0; i < 2; ++i) av[i] = an[i];
           }
         }
-        // D rows: FP32 item r -> 4g + r, FP64 item r -> 4r + g
-        for (int w = 0; w < 4; ++w) {
-          if (wave == w)
+        // D rows: FP32 item r -> row 4g + r, FP64 item r -> row 4r + g
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                if (i >= np) continue;
-                T* xrow = X + (16 * j + c16) * XS + 16 * (i0 + i);
-                for (int r = 0; r < 4; ++r) {
-                  const int row = f64 ? 4 * r + g : 4 * g + r;
-                  xrow[row] = w == 0 ? x[i][j][r] : xrow[row] + x[i][j][r];
-                }
-              }
-          __syncthreads();
-        }
+          for (int j = 0; j < NT; ++j) {
+            if (i >= np) continue;
+            T* xrow = Pw + (16 * j + c16) * XS + 16 * (i0 + i);
+            if (f64) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) xrow[4 * r + g] = x[i][j][r];
+            } else {
+              *reinterpret_cast<T4*>(xrow + 4 * g) = x[i][j];
+            }
+          }
       }
+      __syncthreads();
       // ---- phase 2: Loc rows of this wavefront's M-tiles ----
       if (nmt > 0) {
         const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
-        for (int c = 0; c < nr; ++c) {
-          T4 bv[4], av[MTW];
-          for (int j = 0; j < 4; ++j)
-            bv[j] = *reinterpret_cast<const T4*>(X + (16 * j + c16) * XS + 16 * c + 4 * g);
+        constexpr bool kPre = FMM_M2L_SVD_P2_PREFETCH;
+        T4 av[MTW];
+        if (kPre) {
+#pragma unroll
           for (int i = 0; i < MTW; ++i)
-            av[i] = i < nmt ? *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256)
+            av[i] = i < nmt ? *reinterpret_cast<const T4*>(a2 + int64_t(i) * nr * 256)
                             : T4{0, 0, 0, 0};
+        }
+        for (int c = 0; c < nr; ++c) {
+          T4 bv[NT], an[kPre ? MTW : 1];
+          if (!kPre) {
+#pragma unroll
+            for (int i = 0; i < MTW; ++i)
+              av[i] = i < nmt ? *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256)
+                              : T4{0, 0, 0, 0};
+          } else if (c + 1 < nr) {
+#pragma unroll
+            for (int i = 0; i < MTW; ++i)
+              an[kPre ? i : 0] =
+                  i < nmt ? *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c + 1) * 256)
+                          : T4{0, 0, 0, 0};
+          }
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int o = (16 * j + c16) * XS + 16 * c + 4 * g;
+            T4 v = *reinterpret_cast<const T4*>(P + o);
+#pragma unroll
+            for (int w = 1; w < 4; ++w) v += *reinterpret_cast<const T4*>(P + w * NC * XS + o);
+            bv[j] = v;
+          }
 #pragma unroll
           for (int st = 0; st < 4; ++st)
 #pragma unroll
-            for (int i = 0; i < MTW; ++i)
+            for (int i = 0; i < MTW; ++i) {
+              if (i >= nmt) continue;
 #pragma unroll
-              for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
+              for (int j = 0; j < NT; ++j)
+                acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
+            }
+          if (kPre && c + 1 < nr) {
+#pragma unroll
+            for (int i = 0; i < MTW; ++i) av[i] = an[kPre ? i : 0];
+          }
         }
         if (FOLD) {
+#pragma unroll
           for (int i = 0; i < MTW; ++i)
-            for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+#pragma unroll
               for (int r = 0; r < 4; ++r) acc64[FOLD ? i : 0][j][r] += double(acc[i][j][r]);
               acc[i][j] = T4{0, 0, 0, 0};
             }
@@ -804,14 +872,16 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
     }
 
     const double sc = J.scale[tl.level];
-    for (int j = 0; j < 4; ++j) {
-      const int col = 16 * j + c16;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = col0 + 16 * j + c16;
       if (col >= tl.count) continue;
       double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         if (i >= nmt) continue;
         const int base = 16 * (mt0 + i);
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = f64 ? 4 * r + g : 4 * g + r;
           out[base + row] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
@@ -822,7 +892,7 @@ __global__ __launch_bounds__(256) void m2l_svd_kernel(const JobDev* __restrict__
 }
 
 // M-tiles per wavefront for the compressed kernel: the whole output in one
-// M-block when it fits 4 x 6 tiles (phase 1 then runs once per tile).
+// M-block when it fits 4 x 6 tiles (phase 1 then runs once per N-group).
 int m2l_svd_mtw(int mt) {
   for (int w = 1; w <= 6; ++w)
     if (4 * w >= mt) return w;
@@ -831,19 +901,24 @@ int m2l_svd_mtw(int mt) {
 
 int m2l_svd_nmb(int mt) {
   const int w = m2l_svd_mtw(mt);
-  return (mt + 4 * w - 1) / (4 * w);
+  return (mt + 4 * w - 1) / (4 * w) * (4 / kSvdNT);
+}
+
+size_t m2l_svd_lds_bytes(int xs, bool fp32) {
+  return size_t(4) * 16 * kSvdNT * xs * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 template <typename T, bool FOLD>
 static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid,
                            size_t lds, hipStream_t s) {
+  constexpr int NT = kSvdNT;
   switch (mtw) {
-    case 1: m2l_svd_kernel<T, 1, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 2: m2l_svd_kernel<T, 2, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 3: m2l_svd_kernel<T, 3, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 4: m2l_svd_kernel<T, 4, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 5: m2l_svd_kernel<T, 5, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    default: m2l_svd_kernel<T, 6, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 1: m2l_svd_kernel<T, 1, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 2: m2l_svd_kernel<T, 2, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 3: m2l_svd_kernel<T, 3, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 4: m2l_svd_kernel<T, 4, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 5: m2l_svd_kernel<T, 5, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    default: m2l_svd_kernel<T, 6, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
   }
 }
 
@@ -851,7 +926,7 @@ void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab
                          int xs, hipStream_t s) {
   const int l3 = order * order * order;
   const int mtw = m2l_svd_mtw((l3 + 15) / 16);
-  const size_t lds = size_t(kTileN) * xs * (fp32 ? sizeof(float) : sizeof(double));
+  const size_t lds = m2l_svd_lds_bytes(xs, fp32);
   if (fp32)
     launch_svd_mtw<float, true>(mtw, jobs, tab, grid, lds, s);
   else

@@ -19,6 +19,8 @@ FMM_OK, FMM_ERR_ARG, FMM_ERR_OOM, FMM_ERR_HIP, FMM_ERR_STATE = 0, -1, -2, -3, -4
 FMM_FP64, FMM_MIXED_FP32, FMM_FP64_SVD, FMM_MIXED_SVD = 0, 1, 2, 3
 PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED_FP32,
               "fp64_svd": FMM_FP64_SVD, "mixed_svd": FMM_MIXED_SVD}
+FMM_SCHEDULE_SERIAL, FMM_SCHEDULE_FORKED = 0, 1
+SCHEDULES = {"serial": FMM_SCHEDULE_SERIAL, "forked": FMM_SCHEDULE_FORKED}
 
 EXPORT_KEYS, EXPORT_PERM, EXPORT_LEAF_START, EXPORT_CELL_KEYS = 0, 1, 2, 3
 EXPORT_NEAR_OFF, EXPORT_NEAR_IDX, EXPORT_FAR_OFF, EXPORT_FAR_IDX = 4, 5, 6, 7
@@ -95,6 +97,7 @@ def lib():
     L.fmm_release.restype = None
     L.fmm_last_error.restype = ctypes.c_char_p
     L.fmm_plan_set_precision.argtypes = [vp, i32]
+    L.fmm_plan_set_schedule.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
     L.fmm_plan_svd_info.argtypes = [vp, ctypes.POINTER(SvdInfo)]
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
@@ -170,6 +173,13 @@ class Plan:
         mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         _check(lib().fmm_plan_set_precision(self._h, mode))
         self.precision = mode
+
+    def set_schedule(self, schedule):
+        """"serial" (every operator on the caller's stream) or "forked" (the
+        near field on the plan's side stream, concurrently with the far
+        chain; the default)."""
+        code = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        _check(lib().fmm_plan_set_schedule(self._h, code))
 
     def set_m2l_tolerance(self, eps: float):
         _check(lib().fmm_plan_set_m2l_tolerance(self._h, float(eps)))

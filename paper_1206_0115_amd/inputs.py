@@ -49,4 +49,7 @@ CONFIGS = {
     "cube1m_h6_p7": ("cube", 1_000_000, 6, 7, 1002),
     "sphere10m_h8_p7": ("sphere", 10_000_000, 8, 7, 1003),
     "cube30m_h9_p10": ("cube", 30_000_000, 9, 10, 1005),
+    # the 30M configuration's density twin: the same 1.79 particles per
+    # leaf slot (468,750 / 8^6) at order 10, small enough for the oracle
+    "cube469k_h7_p10": ("cube", 468_750, 7, 10, 1005),
 }

@@ -60,8 +60,10 @@ def test_compressed_parity_with_oracle(kind, n, h, l, seed, eps):
     assert max(rel(host(phi), host(p64)), rel(host(f), host(f64))) < 10 * eps
 
 
-def test_mixed_compressed_full_size_gate():
-    kind, n, h, l, seed = inputs.CONFIGS["cube1m_h6_p7"]
+@pytest.mark.parametrize("name", ["cube1m_h6_p7", "cube469k_h7_p10"])
+def test_mixed_compressed_full_size_gate(name):
+    kind, n, h, l, seed = inputs.CONFIGS[name]
+    print(f"compressed gates {name}", flush=True)
     pos, q = inputs.make(kind, n, seed)
     plan = fmm.Plan(dev(pos), h, l)
     p64, f64 = [host(t) for t in plan.evaluate(dev(q))]

@@ -154,13 +154,14 @@ def test_deterministic_and_reusable():
 
 
 FULL = [
-    ("cube1m_h6_p7",),
-    ("sphere10m_h8_p7",),
+    ("cube1m_h6_p7", 96),
+    ("sphere10m_h8_p7", 96),
+    ("cube469k_h7_p10", 48),  # density twin of the 30M, order-10 cube
 ]
 
 
-@pytest.mark.parametrize("name", [c[0] for c in FULL])
-def test_full_size_sampled_parity(name):
+@pytest.mark.parametrize("name,samples", FULL)
+def test_full_size_sampled_parity(name, samples):
     kind, n, h, l, seed = inputs.CONFIGS[name]
     say(f"full-size sampled parity {name}")
     pos, q = inputs.make(kind, n, seed)
@@ -169,7 +170,7 @@ def test_full_size_sampled_parity(name):
     check_plan(plan, tree)
     phi, f = plan.evaluate(dev(q))
     torch.cuda.synchronize()
-    idx = np.sort(np.random.default_rng(7).choice(n, 96, replace=False))
+    idx = np.sort(np.random.default_rng(7).choice(n, samples, replace=False))
     p_o, f_o = tree.fmm(l, q, targets=idx)
     assert rel(host(phi)[idx], p_o) <= FP64_TOL
     assert rel(host(f)[idx], f_o) <= FP64_TOL
