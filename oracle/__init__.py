@@ -50,6 +50,9 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_direct.argtypes = [_pd, _i64, _pd, _pd, _pd]
     lib.oracle_direct_sampled.argtypes = [_pd, _i64, _pd, _pi64, _i64, _pd, _pd]
+    lib.oracle_direct_k.argtypes = [_pd, _i64, _pd, _pd, _pd, ctypes.c_int]
+    lib.oracle_direct_sampled_k.argtypes = [_pd, _i64, _pd, _pi64, _i64, _pd, _pd,
+                                            ctypes.c_int]
     lib.oracle_cheb_nodes.argtypes = [ctypes.c_int, _pd]
     lib.oracle_cheb_S.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
     lib.oracle_cheb_S.restype = ctypes.c_double
@@ -62,6 +65,8 @@ def _load():
                                _pd, _pd, _pd]
     lib.oracle_m2l_matrix.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                       _pint, _pd]
+    lib.oracle_m2l_matrix_k.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        _pint, _pd, ctypes.c_int]
     lib.oracle_tree_build.argtypes = [_pd, _i64, ctypes.c_int]
     lib.oracle_tree_build.restype = ctypes.c_void_p
     lib.oracle_tree_free.argtypes = [ctypes.c_void_p]
@@ -76,7 +81,7 @@ def _load():
     lib.oracle_fmm.argtypes = [ctypes.c_void_p, ctypes.c_int, _pd, _pi64, _i64,
                                _pd, _pd, _pd, _pd, _pd, _pd]
     lib.oracle_fmm_ops.argtypes = [ctypes.c_void_p, ctypes.c_int, _pd, _pi64, _i64, _pd,
-                                   _pd, _pd, _pd, _pd, _pd, _pd]
+                                   _pd, _pd, _pd, _pd, _pd, _pd, ctypes.c_int]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
     _lib = lib
@@ -102,20 +107,21 @@ def get_threads() -> int:
     return int(_load().oracle_get_threads())
 
 
-def direct(pos, q):
-    """Direct O(N^2) potentials and forces (Eq. 1-2)."""
+def direct(pos, q, kernel=1):
+    """Direct O(N^2) potentials and forces (Eq. 1-2) for the kernel
+    |x - y|^-kernel (1: the paper's 1/r; 2: 1/r^2)."""
     pos = _f64(pos)
     n = pos.shape[0]
     q = _f64(q, (n,))
     phi = np.empty(n)
     f = np.empty((n, 3))
-    rc = _load().oracle_direct(_ptr(pos), n, _ptr(q), _ptr(phi), _ptr(f))
+    rc = _load().oracle_direct_k(_ptr(pos), n, _ptr(q), _ptr(phi), _ptr(f), int(kernel))
     if rc != 0:
         raise ValueError("oracle_direct failed")
     return phi, f
 
 
-def direct_sampled(pos, q, idx):
+def direct_sampled(pos, q, idx, kernel=1):
     """Exact sums at the targets ``idx`` over all sources."""
     pos = _f64(pos)
     n = pos.shape[0]
@@ -124,8 +130,8 @@ def direct_sampled(pos, q, idx):
     s = idx.shape[0]
     phi = np.empty(s)
     f = np.empty((s, 3))
-    rc = _load().oracle_direct_sampled(_ptr(pos), n, _ptr(q), _ptr(idx, _pi64), s,
-                                       _ptr(phi), _ptr(f))
+    rc = _load().oracle_direct_sampled_k(_ptr(pos), n, _ptr(q), _ptr(idx, _pi64), s,
+                                         _ptr(phi), _ptr(f), int(kernel))
     if rc != 0:
         raise ValueError("oracle_direct_sampled failed")
     return phi, f
@@ -187,11 +193,11 @@ def l2p(l, pos, q, center, a, Loc):
     return phi, f
 
 
-def m2l_matrix(l, a, w, t):
+def m2l_matrix(l, a, w, t, kernel=1):
     tt = np.ascontiguousarray(t, dtype=np.int32)
     K = np.empty((l ** 3, l ** 3))
-    if _load().oracle_m2l_matrix(l, float(a), float(w), tt.ctypes.data_as(_pint),
-                                 _ptr(K)) != 0:
+    if _load().oracle_m2l_matrix_k(l, float(a), float(w), tt.ctypes.data_as(_pint),
+                                   _ptr(K), int(kernel)) != 0:
         raise ValueError("oracle_m2l_matrix failed")
     return K
 
@@ -262,9 +268,10 @@ class Tree:
         lib.oracle_tree_far(self._h, level, _ptr(off, _pi64), _ptr(idx, _pi64))
         return off, idx
 
-    def fmm(self, l, q, targets=None, parts=False, unit_ops=None):
-        """FMM potentials and forces; near + far, or the four parts.  With
-        ``unit_ops`` (from :func:`compressed_unit_ops`) M2L uses those
+    def fmm(self, l, q, targets=None, parts=False, unit_ops=None, kernel=1):
+        """FMM potentials and forces for the kernel |x - y|^-kernel; near +
+        far, or the four parts.  With ``unit_ops`` (from
+        :func:`compressed_unit_ops`, for the same kernel) M2L uses those
         operators instead of the exact kernel matrices."""
         q = _f64(q, (self.n,))
         if unit_ops is not None:
@@ -286,7 +293,7 @@ class Tree:
         ff = np.empty((nt, 3)) if parts else None
         rc = _load().oracle_fmm_ops(self._h, int(l), _ptr(q), tptr, nt, _ptr(unit_ops),
                                     _ptr(phi), _ptr(f), _ptr(pn), _ptr(fn), _ptr(pf),
-                                    _ptr(ff))
+                                    _ptr(ff), int(kernel))
         if rc != 0:
             raise ValueError(f"oracle_fmm failed ({rc})")
         if parts:
@@ -294,9 +301,9 @@ class Tree:
         return phi, f
 
 
-def fmm(pos, q, h, l, targets=None):
+def fmm(pos, q, h, l, targets=None, kernel=1):
     """Convenience: build the tree and evaluate."""
-    return Tree(pos, h).fmm(l, q, targets=targets)
+    return Tree(pos, h).fmm(l, q, targets=targets, kernel=kernel)
 
 
 def far_offsets():
@@ -313,20 +320,20 @@ def far_offsets():
 _ops_cache = {}
 
 
-def compressed_unit_ops(l, eps):
+def compressed_unit_ops(l, eps, kernel=1):
     """Compressed M2L of Sec. 2.1.2: for every far offset t, the unit
     operator (cells of half-width 1) replaced by its truncated SVD, keeping
     the singular values s_k >= eps * s_1 (eps = 0 keeps all).  Each offset's
     operator is decomposed on its own (numpy's LAPACK SVD; no symmetry is
     used).  Returns (ops[343][l^3][l^3], {offset: rank})."""
-    key = (l, float(eps))
+    key = (l, float(eps), int(kernel))
     if key in _ops_cache:
         return _ops_cache[key]
     l3 = l ** 3
     ops = np.zeros((343, l3, l3))
     ranks = {}
     for t, i in far_offsets():
-        K = m2l_matrix(l, 1.0, 2.0, t)
+        K = m2l_matrix(l, 1.0, 2.0, t, kernel)
         U, s, Vt = np.linalg.svd(K)
         r = int(np.sum(s >= eps * s[0]))
         ops[i] = (U[:, :r] * s[:r]) @ Vt[:r]

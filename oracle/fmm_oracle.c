@@ -50,8 +50,12 @@ int oracle_get_threads(void) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Eq. (1)-(2): one source j acting on target i.  Zero-distance pairs skip.  */
-static inline void pair_accumulate(const double* xi, const double* xj,
+/* Eq. (1)-(2) for the kernel family P(x, y) = |x - y|^-p, p = 1 (the paper's
+ * Laplace kernel) or p = 2 (a second homogeneous kernel, Sec. 2.1: the
+ * black-box scheme needs only point evaluations of P).  One source j acting
+ * on target i: phi += q_j r^-p, and the force factor -grad_x P = p r^-(p+2) d
+ * with d = x_i - x_j.  Zero-distance pairs are skipped.                      */
+static inline void pair_accumulate(int p, const double* xi, const double* xj,
                                    double qj, double* phi, double* fx,
                                    double* fy, double* fz) {
   double dx = xi[0] - xj[0];
@@ -59,23 +63,42 @@ static inline void pair_accumulate(const double* xi, const double* xj,
   double dz = xi[2] - xj[2];
   double r2 = (dx * dx + dy * dy) + dz * dz;
   if (r2 == 0.0) return;
-  double ir = 1.0 / sqrt(r2);
-  *phi += qj * ir;
-  double s = qj * ir * ir * ir;
+  double s;
+  if (p == 2) {
+    double ir2 = 1.0 / r2;
+    *phi += qj * ir2;
+    s = 2.0 * qj * ir2 * ir2;
+  } else {
+    double ir = 1.0 / sqrt(r2);
+    *phi += qj * ir;
+    s = qj * ir * ir * ir;
+  }
   *fx += s * dx;
   *fy += s * dy;
   *fz += s * dz;
 }
 
+/* the kernel at distance^2 r2 (r2 > 0) */
+static inline double kernel_value(int p, double r2) {
+  return p == 2 ? 1.0 / r2 : 1.0 / sqrt(r2);
+}
+
+static int valid_kernel(int p) { return p == 1 || p == 2; }
+
 int oracle_direct(const double* pos, int64_t n, const double* q, double* phi,
                   double* f) {
-  if (n < 0 || (n > 0 && (!pos || !q || !phi || !f))) return -1;
+  return oracle_direct_k(pos, n, q, phi, f, 1);
+}
+
+int oracle_direct_k(const double* pos, int64_t n, const double* q, double* phi,
+                    double* f, int p) {
+  if (n < 0 || (n > 0 && (!pos || !q || !phi || !f)) || !valid_kernel(p)) return -1;
 #pragma omp parallel for schedule(static) num_threads(oracle_get_threads())
   for (int64_t i = 0; i < n; ++i) {
-    double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     for (int64_t j = 0; j < n; ++j)
-      pair_accumulate(&pos[3 * i], &pos[3 * j], q[j], &p, &fx, &fy, &fz);
-    phi[i] = p;
+      pair_accumulate(p, &pos[3 * i], &pos[3 * j], q[j], &ph, &fx, &fy, &fz);
+    phi[i] = ph;
     f[3 * i + 0] = q[i] * fx;
     f[3 * i + 1] = q[i] * fy;
     f[3 * i + 2] = q[i] * fz;
@@ -86,17 +109,24 @@ int oracle_direct(const double* pos, int64_t n, const double* q, double* phi,
 int oracle_direct_sampled(const double* pos, int64_t n, const double* q,
                           const int64_t* idx, int64_t s, double* phi,
                           double* f) {
-  if (n < 0 || s < 0 || (s > 0 && (!pos || !q || !idx || !phi || !f)))
+  return oracle_direct_sampled_k(pos, n, q, idx, s, phi, f, 1);
+}
+
+int oracle_direct_sampled_k(const double* pos, int64_t n, const double* q,
+                            const int64_t* idx, int64_t s, double* phi,
+                            double* f, int p) {
+  if (n < 0 || s < 0 || (s > 0 && (!pos || !q || !idx || !phi || !f)) ||
+      !valid_kernel(p))
     return -1;
   for (int64_t k = 0; k < s; ++k)
     if (idx[k] < 0 || idx[k] >= n) return -1;
 #pragma omp parallel for schedule(static) num_threads(oracle_get_threads())
   for (int64_t k = 0; k < s; ++k) {
     int64_t i = idx[k];
-    double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     for (int64_t j = 0; j < n; ++j)
-      pair_accumulate(&pos[3 * i], &pos[3 * j], q[j], &p, &fx, &fy, &fz);
-    phi[k] = p;
+      pair_accumulate(p, &pos[3 * i], &pos[3 * j], q[j], &ph, &fx, &fy, &fz);
+    phi[k] = ph;
     f[3 * k + 0] = q[i] * fx;
     f[3 * k + 1] = q[i] * fy;
     f[3 * k + 2] = q[i] * fz;
@@ -284,9 +314,9 @@ static void l2p_point(const basis_t* b, const double* x, double qi,
   f[2] = -qi * (gz / a);
 }
 
-/* M2L: K[m][n] = 1 / |x_m - y_n| with x_m = c + a xb_m (target cell) and
- * y_n = c + w t + a xb_n (source cell), i.e. |a (xb_m - xb_n) - w t|. */
-static void m2l_matrix(const basis_t* b, double a, double w, const int* t,
+/* M2L: K[m][n] = P(x_m, y_n) with x_m = c + a xb_m (target cell) and
+ * y_n = c + w t + a xb_n (source cell), i.e. |a (xb_m - xb_n) - w t|^-p. */
+static void m2l_matrix(int p, const basis_t* b, double a, double w, const int* t,
                        double* K) {
   const int l = b->l, l3 = l * l * l;
   for (int m1 = 0; m1 < l; ++m1)
@@ -300,7 +330,7 @@ static void m2l_matrix(const basis_t* b, double a, double w, const int* t,
               double dz = a * (b->xi[m3] - b->xi[n3]) - w * t[2];
               double r2 = (dx * dx + dy * dy) + dz * dz;
               K[(size_t)((m1 * l + m2) * l + m3) * l3 + (n1 * l + n2) * l + n3] =
-                  1.0 / sqrt(r2);
+                  kernel_value(p, r2);
             }
 }
 
@@ -351,10 +381,17 @@ int oracle_l2p(int l, int64_t n, const double* pos, const double* q,
 }
 
 int oracle_m2l_matrix(int l, double a, double w, const int* t, double* K) {
-  if (l < 1 || l > MAXO || !t || !K || !(a > 0.0) || !(w > 0.0)) return -1;
+  return oracle_m2l_matrix_k(l, a, w, t, K, 1);
+}
+
+int oracle_m2l_matrix_k(int l, double a, double w, const int* t, double* K,
+                        int p) {
+  if (l < 1 || l > MAXO || !t || !K || !(a > 0.0) || !(w > 0.0) ||
+      !valid_kernel(p))
+    return -1;
   basis_t b;
   basis_init(&b, l);
-  m2l_matrix(&b, a, w, t, K);
+  m2l_matrix(p, &b, a, w, t, K);
   return 0;
 }
 
@@ -688,14 +725,14 @@ int oracle_fmm(const oracle_tree* t, int l, const double* q,
                double* phi_near, double* f_near, double* phi_far,
                double* f_far) {
   return oracle_fmm_ops(t, l, q, targets, nt, NULL, phi, f, phi_near, f_near,
-                        phi_far, f_far);
+                        phi_far, f_far, 1);
 }
 
 int oracle_fmm_ops(const oracle_tree* t, int l, const double* q,
                    const int64_t* targets, int64_t nt, const double* unit_ops,
                    double* phi, double* f, double* phi_near, double* f_near,
-                   double* phi_far, double* f_far) {
-  if (!t || !q || l < 1 || l > MAXO) return -1;
+                   double* phi_far, double* f_far, int p) {
+  if (!t || !q || l < 1 || l > MAXO || !valid_kernel(p)) return -1;
   const int64_t n = t->n;
   const int h = t->h;
   if (!targets) nt = n;
@@ -804,11 +841,13 @@ int oracle_fmm_ops(const oracle_tree* t, int l, const double* q,
         int id = ids[k];
         int tt[3] = {id / 49 - 3, (id / 7) % 7 - 3, id % 7 - 3};
         if (unit_ops) {
-          /* given operator between half-width-1 cells, scaled to this level */
+          /* given operator between half-width-1 cells, scaled to this level
+           * by the kernel's homogeneity: P(a x, a y) = a^-p P(x, y) */
           const double* src = unit_ops + (size_t)id * l3 * l3;
-          for (size_t e = 0; e < (size_t)l3 * l3; ++e) K[id][e] = src[e] / a;
+          const double sc = p == 2 ? 1.0 / (a * a) : 1.0 / a;
+          for (size_t e = 0; e < (size_t)l3 * l3; ++e) K[id][e] = src[e] * sc;
         } else {
-          m2l_matrix(&B, a, w, tt, K[id]);
+          m2l_matrix(p, &B, a, w, tt, K[id]);
         }
       }
 
@@ -865,14 +904,14 @@ int oracle_fmm_ops(const oracle_tree* t, int l, const double* q,
   for (int64_t k = 0; k < nt; ++k) {
     int64_t i = tsorted[k];
     int64_t a = t->leaf_of[i];
-    double p = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     for (int64_t e = t->near_off[a]; e < t->near_off[a + 1]; ++e) {
       int64_t b = t->near_idx[e];
       for (int64_t j = t->leaf_start[b]; j < t->leaf_start[b + 1]; ++j)
-        pair_accumulate(&t->pos_s[3 * i], &t->pos_s[3 * j], qs[j], &p, &fx,
+        pair_accumulate(p, &t->pos_s[3 * i], &t->pos_s[3 * j], qs[j], &ph, &fx,
                         &fy, &fz);
     }
-    pn[k] = p;
+    pn[k] = ph;
     fn[3 * k + 0] = qs[i] * fx;
     fn[3 * k + 1] = qs[i] * fy;
     fn[3 * k + 2] = qs[i] * fz;

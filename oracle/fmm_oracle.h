@@ -42,6 +42,13 @@ int oracle_direct(const double* pos, int64_t n, const double* q, double* phi,
 int oracle_direct_sampled(const double* pos, int64_t n, const double* q,
                           const int64_t* idx, int64_t s, double* phi,
                           double* f);
+/* The same two for the kernel P = |x - y|^-p, p = 1 (1/r, the calls above)
+ * or p = 2 (1/r^2; force q_i sum_j q_j 2 (x_i - x_j) / r^4).  Other p: -1. */
+int oracle_direct_k(const double* pos, int64_t n, const double* q, double* phi,
+                    double* f, int p);
+int oracle_direct_sampled_k(const double* pos, int64_t n, const double* q,
+                            const int64_t* idx, int64_t s, double* phi,
+                            double* f, int p);
 
 /* ---- Chebyshev interpolation (Eq. 5) ---- */
 int oracle_cheb_nodes(int l, double* xi);                  /* xi[l] */
@@ -63,6 +70,9 @@ int oracle_l2p(int l, int64_t n, const double* pos, const double* q,
 /* K[l^3][l^3]: M2L matrix between cells of half-width a, width w, whose
  * centres differ by w*t (source minus target). */
 int oracle_m2l_matrix(int l, double a, double w, const int* t, double* K);
+/* the same for the kernel |x - y|^-p (p = 1 or 2) */
+int oracle_m2l_matrix_k(int l, double a, double w, const int* t, double* K,
+                        int p);
 
 /* ---- octree (plan) ---- */
 typedef struct oracle_tree oracle_tree;
@@ -91,16 +101,17 @@ int oracle_fmm(const oracle_tree* t, int l, const double* q,
                double* phi_near, double* f_near, double* phi_far,
                double* f_far);
 
-/* As oracle_fmm, but M2L uses given unit operators instead of evaluating the
- * kernel: unit_ops[id][l^3][l^3] for the offset t with
+/* As oracle_fmm, for the kernel |x - y|^-p (p = 1 or 2), and, when
+ * unit_ops is not NULL, with M2L through given unit operators instead of
+ * kernel evaluations: unit_ops[id][l^3][l^3] for the offset t with
  * id = (tx+3)*49 + (ty+3)*7 + (tz+3) is the operator between cells of width
- * 2 (half-width 1); level lv uses it scaled by 1/a_lv (1/r is homogeneous of
- * degree -1).  Used for the compressed M2L of Sec. 2.1.2, whose truncated
- * operators the caller computes. */
+ * 2 (half-width 1); level lv uses it scaled by a_lv^-p (the kernel is
+ * homogeneous of degree -p).  Used for the compressed M2L of Sec. 2.1.2,
+ * whose truncated operators the caller computes. */
 int oracle_fmm_ops(const oracle_tree* t, int l, const double* q,
                    const int64_t* targets, int64_t nt, const double* unit_ops,
                    double* phi, double* f, double* phi_near, double* f_near,
-                   double* phi_far, double* f_far);
+                   double* phi_far, double* f_far, int p);
 
 /* number of OpenMP threads the oracle uses (0 = library default) */
 void oracle_set_threads(int nthreads);
