@@ -143,6 +143,23 @@ int fmm_plan_set_precision(fmm_plan_t plan, int mode);
 enum fmm_schedule { FMM_SCHEDULE_SERIAL = 0, FMM_SCHEDULE_FORKED = 1 };
 int fmm_plan_set_schedule(fmm_plan_t plan, int schedule);
 
+/* Kernel of later evaluations.  The black-box scheme (Sec. 2.1) needs only
+ * point evaluations of the kernel P(x, y): the interpolation operators (P2M,
+ * M2M, L2L, L2P) do not depend on it, M2L evaluates it between Chebyshev
+ * nodes, and P2P evaluates it directly.  Both kernels are homogeneous, so the
+ * unit M2L operators of Sec. 2.1.2 serve every level with the scale a^-p.
+ *   FMM_KERNEL_INV_R   (default) P = 1/r, the paper's Laplace kernel (Eq. 2):
+ *                      phi_i = sum_j q_j / r_ij,
+ *                      F_i = q_i sum_j q_j (x_i - x_j) / r_ij^3
+ *   FMM_KERNEL_INV_R2  P = 1/r^2: phi_i = sum_j q_j / r_ij^2,
+ *                      F_i = -q_i grad phi = q_i sum_j q_j 2 (x_i - x_j) / r_ij^4
+ * Zero-distance pairs contribute nothing in both.  The operators of a new
+ * (order, kernel) are built once per device and cached; the call waits for
+ * the plan's in-flight evaluation.  Returns FMM_ERR_ARG for a null plan or an
+ * unknown kernel.  The serving calls use FMM_KERNEL_INV_R. */
+enum fmm_kernel { FMM_KERNEL_INV_R = 1, FMM_KERNEL_INV_R2 = 2 };
+int fmm_plan_set_kernel(fmm_plan_t plan, int kernel);
+
 /* Plan facts (host struct). */
 struct fmm_info {
   int64_t n;

@@ -50,6 +50,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.mt = op->mt;
   J.kc = op->kc;
   J.nmb = p->svd ? m2l_svd_nmb(op->mt) : m2l_nmb(op->mt);
+  J.kernel = p->kernel;
   J.svd = p->svd ? 1 : 0;
   if (p->svd) {
     J.xs = p->svd->rmax_pad + 4;
@@ -73,8 +74,11 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
     J.parent[l] = p->lev[l].parent;
     J.keys[l] = p->lev[l].keys;
   }
-  for (int l = 0; l < kMaxHeight; ++l)
-    J.scale[l] = double(int64_t(1) << std::min(l + 1, 62)) / p->L;
+  // a_l = L / 2^(l+1); the unit operators are scaled by a_l^-p
+  for (int l = 0; l < kMaxHeight; ++l) {
+    const double inv_a = double(int64_t(1) << std::min(l + 1, 62)) / p->L;
+    J.scale[l] = p->kernel == FMM_KERNEL_INV_R2 ? inv_a * inv_a : inv_a;
+  }
   J.tiles = p->tiles;
   J.tgt = p->tgt;
   J.tile_src = p->tile_src;
@@ -193,7 +197,7 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
     p->n = n;
     p->height = height;
     p->order = order;
-    p->ops = fmm::get_opset(order, stream);
+    p->ops = fmm::get_opset(order, p->kernel, stream);
     fmm::build_plan(p, positions, stream);
     const int ld = p->ops->ld;
     const size_t rows = size_t(p->ncell_total + 1);
@@ -239,7 +243,7 @@ static void apply_mode(fmm_plan_s* p, int mode) {
   const bool mixed = mode == FMM_MIXED_FP32 || mode == FMM_MIXED_SVD;
   const bool svd = mode == FMM_FP64_SVD || mode == FMM_MIXED_SVD;
   const fmm::SvdOps* sv = svd && p->height >= 3
-                             ? fmm::get_svd_ops(p->order, p->m2l_eps, p->last_stream)
+                             ? fmm::get_svd_ops(p->order, p->m2l_eps, p->kernel, p->last_stream)
                              : nullptr;
   if (sv) {
     // the compressed kernel keeps four rank x 16*NT slabs in LDS
@@ -287,6 +291,28 @@ int fmm_plan_set_schedule(fmm_plan_t p, int schedule) {
   });
 }
 
+int fmm_plan_set_kernel(fmm_plan_t p, int kernel) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (kernel != FMM_KERNEL_INV_R && kernel != FMM_KERNEL_INV_R2)
+    return fail(FMM_ERR_ARG, "unknown kernel " + std::to_string(kernel));
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
+    const int prev = p->kernel;
+    const fmm::OpSet* prev_ops = p->ops;
+    p->kernel = kernel;
+    try {
+      p->ops = fmm::get_opset(p->order, kernel, p->last_stream);
+      apply_mode(p, p->precision);
+    } catch (...) {
+      p->kernel = prev;
+      p->ops = prev_ops;
+      throw;
+    }
+    return FMM_OK;
+  });
+}
+
 int fmm_plan_set_m2l_tolerance(fmm_plan_t p, double eps) {
   if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
   if (!(eps > 0.0 && eps < 1.0)) return fail(FMM_ERR_ARG, "tolerance must be in (0, 1)");
@@ -308,7 +334,7 @@ int fmm_plan_svd_info(fmm_plan_t p, struct fmm_svd_info* out) {
   if (!p || !out) return fail(FMM_ERR_ARG, "NULL argument");
   return guarded([&]() -> int {
     std::lock_guard<std::mutex> lk(p->mu);
-    const fmm::SvdOps* sv = fmm::get_svd_ops(p->order, p->m2l_eps, p->last_stream);
+    const fmm::SvdOps* sv = fmm::get_svd_ops(p->order, p->m2l_eps, p->kernel, p->last_stream);
     std::memset(out, 0, sizeof(*out));
     out->eps = sv->eps;
     for (int c = 0; c < 16; ++c) out->rank[c] = sv->rank[c];

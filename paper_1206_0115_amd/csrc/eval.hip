@@ -284,143 +284,188 @@ __device__ inline int p2p_groups(int nt) {
   return P;
 }
 
+// One near-field pair for the kernel |x - y|^-KP: adds the potential term
+// q r^-KP to ph and the force factor KP q r^-(KP+2) times d to (fx, fy, fz);
+// the target charge multiplies the force at the end.  Zero distance adds 0.
+template <int KP>
+__device__ __forceinline__ void pair_f64(double dx, double dy, double dz, double q, double& ph,
+                                         double& fx, double& fy, double& fz) {
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  double t, s;
+  if (KP == 2) {
+    const double ir2 = r2 > 0.0 ? 1.0 / r2 : 0.0;
+    t = q * ir2;
+    s = 2.0 * t * ir2;
+  } else {
+    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    t = q * ir;
+    s = t * ir * ir;
+  }
+  ph += t;
+  fx += s * dx;
+  fy += s * dy;
+  fz += s * dz;
+}
+
+// The same in FP32 (v_rsq_f32 for 1/r, v_rcp_f32 for 1/r^2).
+template <int KP>
+__device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float q, float& ph,
+                                         float& fx, float& fy, float& fz) {
+  const float r2 = dx * dx + dy * dy + dz * dz;
+  float t, s;
+  if (KP == 2) {
+    const float ir2 = r2 > 0.f ? __builtin_amdgcn_rcpf(r2) : 0.f;
+    t = q * ir2;
+    s = 2.f * t * ir2;
+  } else {
+    const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    t = q * ir;
+    s = t * ir * ir;
+  }
+  ph += t;
+  fx += s * dx;
+  fy += s * dy;
+  fz += s * dz;
+}
+
+template <int KP>
+__device__ __forceinline__ void p2p_f64_leaf(const JobDev& J, int a, double* sx, double* sy,
+                                             double* sz, double* sq) {
+  const int lane = threadIdx.x;
+  const double *px = J.px, *py = J.py, *pz = J.pz, *qs = J.qs;
+  const int t0 = J.leaf_start[a], nt = J.leaf_start[a + 1] - t0;
+  const int P = p2p_groups(nt);
+  const int S = 64 / P;
+  const int split = lane / P;
+  for (int tb = 0; tb < nt; tb += 64) {
+    const int ti = tb + (lane % P);
+    const bool valid = ti < nt;
+    const int it = t0 + (valid ? ti : 0);
+    const double xi = px[it], yi = py[it], zi = pz[it];
+    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int sl = 0; sl < 27; ++sl) {
+      const int b = J.near[27 * a + sl];
+      if (b < 0) continue;
+      const int j0 = J.leaf_start[b], j1 = J.leaf_start[b + 1];
+      for (int jb = j0; jb < j1; jb += 64) {
+        const int cnt = min(64, j1 - jb);
+        __syncthreads();
+        if (lane < cnt) {
+          sx[lane] = px[jb + lane];
+          sy[lane] = py[jb + lane];
+          sz[lane] = pz[jb + lane];
+          sq[lane] = qs[jb + lane];
+        }
+        __syncthreads();
+        for (int kk = split; kk < cnt; kk += S)
+          pair_f64<KP>(xi - sx[kk], yi - sy[kk], zi - sz[kk], sq[kk], ph, fx, fy, fz);
+      }
+    }
+    for (int o = P; o < 64; o <<= 1) {
+      ph += __shfl_xor(ph, o, 64);
+      fx += __shfl_xor(fx, o, 64);
+      fy += __shfl_xor(fy, o, 64);
+      fz += __shfl_xor(fz, o, 64);
+    }
+    if (valid && split == 0) {
+      const int i = t0 + ti;
+      const double qi = qs[i];
+      J.phi_n[i] = ph;
+      J.f_n[3 * i] = qi * fx;
+      J.f_n[3 * i + 1] = qi * fy;
+      J.f_n[3 * i + 2] = qi * fz;
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void p2p_f64_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
   __shared__ double sx[64], sy[64], sz[64], sq[64];
-  const int lane = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
-    const double *px = J.px, *py = J.py, *pz = J.pz, *qs = J.qs;
-    const int t0 = J.leaf_start[a], nt = J.leaf_start[a + 1] - t0;
-    const int P = p2p_groups(nt);
-    const int S = 64 / P;
-    const int split = lane / P;
-    for (int tb = 0; tb < nt; tb += 64) {
-      const int ti = tb + (lane % P);
-      const bool valid = ti < nt;
-      const int it = t0 + (valid ? ti : 0);
-      const double xi = px[it], yi = py[it], zi = pz[it];
-      double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-      for (int sl = 0; sl < 27; ++sl) {
-        const int b = J.near[27 * a + sl];
-        if (b < 0) continue;
-        const int j0 = J.leaf_start[b], j1 = J.leaf_start[b + 1];
-        for (int jb = j0; jb < j1; jb += 64) {
-          const int cnt = min(64, j1 - jb);
-          __syncthreads();
-          if (lane < cnt) {
-            sx[lane] = px[jb + lane];
-            sy[lane] = py[jb + lane];
-            sz[lane] = pz[jb + lane];
-            sq[lane] = qs[jb + lane];
-          }
-          __syncthreads();
-          for (int kk = split; kk < cnt; kk += S) {
-            const double dx = xi - sx[kk], dy = yi - sy[kk], dz = zi - sz[kk];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
-            const double qir = sq[kk] * ir;
-            ph += qir;
-            const double s3 = qir * ir * ir;
-            fx += s3 * dx;
-            fy += s3 * dy;
-            fz += s3 * dz;
-          }
-        }
-      }
-      for (int o = P; o < 64; o <<= 1) {
-        ph += __shfl_xor(ph, o, 64);
-        fx += __shfl_xor(fx, o, 64);
-        fy += __shfl_xor(fy, o, 64);
-        fz += __shfl_xor(fz, o, 64);
-      }
-      if (valid && split == 0) {
-        const int i = t0 + ti;
-        const double qi = qs[i];
-        J.phi_n[i] = ph;
-        J.f_n[3 * i] = qi * fx;
-        J.f_n[3 * i + 1] = qi * fy;
-        J.f_n[3 * i + 2] = qi * fz;
-      }
-    }
+    if (J.kernel == 2)
+      p2p_f64_leaf<2>(J, a, sx, sy, sz, sq);
+    else
+      p2p_f64_leaf<1>(J, a, sx, sy, sz, sq);
     __syncthreads();
   }
 }
 
 // FP32 near field.  The pair difference is taken in FP64 (full rate on this
 // chip) and rounded once, so it carries a relative error of 2^-24 of the
-// distance itself however close the pair is; r^2, rsqrt (v_rsq_f32) and the
-// products are FP32; partial sums over one source leaf are kept in FP32 and
-// folded into FP64 accumulators.
+// distance itself however close the pair is; r^2, the reciprocal (square)
+// root and the products are FP32; partial sums over one source leaf are kept
+// in FP32 and folded into FP64 accumulators.
+template <int KP>
+__device__ __forceinline__ void p2p_f32_leaf(const JobDev& J, int a, double* sx, double* sy,
+                                             double* sz, float* sq) {
+  const int lane = threadIdx.x;
+  const double *px = J.px, *py = J.py, *pz = J.pz;
+  const int t0 = J.leaf_start[a], nt = J.leaf_start[a + 1] - t0;
+  const int P = p2p_groups(nt);
+  const int S = 64 / P;
+  const int split = lane / P;
+  for (int tb = 0; tb < nt; tb += 64) {
+    const int ti = tb + (lane % P);
+    const bool valid = ti < nt;
+    const int it = t0 + (valid ? ti : 0);
+    const double xi = px[it], yi = py[it], zi = pz[it];
+    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int sl = 0; sl < 27; ++sl) {
+      const int b = J.near[27 * a + sl];
+      if (b < 0) continue;
+      const int j0 = J.leaf_start[b], j1 = J.leaf_start[b + 1];
+      float p32 = 0.f, x32 = 0.f, y32 = 0.f, z32 = 0.f;
+      for (int jb = j0; jb < j1; jb += 64) {
+        const int cnt = min(64, j1 - jb);
+        __syncthreads();
+        if (lane < cnt) {
+          sx[lane] = px[jb + lane];
+          sy[lane] = py[jb + lane];
+          sz[lane] = pz[jb + lane];
+          sq[lane] = J.prel[jb + lane].w;
+        }
+        __syncthreads();
+        for (int kk = split; kk < cnt; kk += S)
+          pair_f32<KP>(float(xi - sx[kk]), float(yi - sy[kk]), float(zi - sz[kk]), sq[kk], p32,
+                       x32, y32, z32);
+      }
+      ph += double(p32);
+      fx += double(x32);
+      fy += double(y32);
+      fz += double(z32);
+    }
+    for (int o = P; o < 64; o <<= 1) {
+      ph += __shfl_xor(ph, o, 64);
+      fx += __shfl_xor(fx, o, 64);
+      fy += __shfl_xor(fy, o, 64);
+      fz += __shfl_xor(fz, o, 64);
+    }
+    if (valid && split == 0) {
+      const int i = t0 + ti;
+      const double qi = J.qs[i];
+      J.phi_n[i] = ph;
+      J.f_n[3 * i] = qi * fx;
+      J.f_n[3 * i + 1] = qi * fy;
+      J.f_n[3 * i + 2] = qi * fz;
+    }
+  }
+}
+
 __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
   __shared__ double sx[64], sy[64], sz[64];
   __shared__ float sq[64];
-  const int lane = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
-    const double *px = J.px, *py = J.py, *pz = J.pz;
-    const int t0 = J.leaf_start[a], nt = J.leaf_start[a + 1] - t0;
-    const int P = p2p_groups(nt);
-    const int S = 64 / P;
-    const int split = lane / P;
-    for (int tb = 0; tb < nt; tb += 64) {
-      const int ti = tb + (lane % P);
-      const bool valid = ti < nt;
-      const int it = t0 + (valid ? ti : 0);
-      const double xi = px[it], yi = py[it], zi = pz[it];
-      double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-      for (int sl = 0; sl < 27; ++sl) {
-        const int b = J.near[27 * a + sl];
-        if (b < 0) continue;
-        const int j0 = J.leaf_start[b], j1 = J.leaf_start[b + 1];
-        float p32 = 0.f, x32 = 0.f, y32 = 0.f, z32 = 0.f;
-        for (int jb = j0; jb < j1; jb += 64) {
-          const int cnt = min(64, j1 - jb);
-          __syncthreads();
-          if (lane < cnt) {
-            sx[lane] = px[jb + lane];
-            sy[lane] = py[jb + lane];
-            sz[lane] = pz[jb + lane];
-            sq[lane] = J.prel[jb + lane].w;
-          }
-          __syncthreads();
-          for (int kk = split; kk < cnt; kk += S) {
-            const float dx = float(xi - sx[kk]), dy = float(yi - sy[kk]), dz = float(zi - sz[kk]);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
-            const float qir = sq[kk] * ir;
-            p32 += qir;
-            const float s3 = qir * ir * ir;
-            x32 += s3 * dx;
-            y32 += s3 * dy;
-            z32 += s3 * dz;
-          }
-        }
-        ph += double(p32);
-        fx += double(x32);
-        fy += double(y32);
-        fz += double(z32);
-      }
-      for (int o = P; o < 64; o <<= 1) {
-        ph += __shfl_xor(ph, o, 64);
-        fx += __shfl_xor(fx, o, 64);
-        fy += __shfl_xor(fy, o, 64);
-        fz += __shfl_xor(fz, o, 64);
-      }
-      if (valid && split == 0) {
-        const int i = t0 + ti;
-        const double qi = J.qs[i];
-        J.phi_n[i] = ph;
-        J.f_n[3 * i] = qi * fx;
-        J.f_n[3 * i + 1] = qi * fy;
-        J.f_n[3 * i + 2] = qi * fz;
-      }
-    }
+    if (J.kernel == 2)
+      p2p_f32_leaf<2>(J, a, sx, sy, sz, sq);
+    else
+      p2p_f32_leaf<1>(J, a, sx, sy, sz, sq);
     __syncthreads();
   }
 }

@@ -66,7 +66,8 @@ struct OpSet {
   int* slot_kid = nullptr;    // [8][189] packed-operator index of each slot
   signed char* slot_t = nullptr;  // [8][189][3] offset (tx, ty, tz) of each slot
 };
-const OpSet* get_opset(int order, hipStream_t stream);
+// operators of an order for the kernel |x - y|^-kernel (1 or 2), cached per device
+const OpSet* get_opset(int order, int kernel, hipStream_t stream);
 
 // Compressed M2L operators (Sec. 2.1.2): one SVD per canonical operator,
 // truncated at s_k >= eps s_1, shared by its 316-offset orbit through the
@@ -86,7 +87,7 @@ struct SvdOps {
   double* p2_64 = nullptr;  // U factors in fragment order
   float* p2_32 = nullptr;
 };
-const SvdOps* get_svd_ops(int order, double eps, hipStream_t stream);
+const SvdOps* get_svd_ops(int order, double eps, int kernel, hipStream_t stream);
 int kid_canon(int kid);  // canonical class (0..15) of packed operator kid
 
 // ------------------------------------------------------------- the plan
@@ -174,6 +175,7 @@ struct fmm_plan_s {
 
   hipEvent_t done = nullptr;       // recorded after each evaluation
   int schedule = FMM_SCHEDULE_FORKED;
+  int kernel = FMM_KERNEL_INV_R;   // exponent p of the kernel |x - y|^-p
   hipStream_t side = nullptr;      // the near-field branch of the forked schedule
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool in_flight = false;

@@ -38,6 +38,7 @@ struct JobDev {
   const uint64_t* leaf_keys;
   const int* near;
   int n, nleaf, height, order, ld, mt, kc, nmb, ntiles, has_far;
+  int kernel;  // p of the kernel |x - y|^-p (1 or 2)
   LeafGeom geo;
   double* W;
   float* W32;
@@ -52,7 +53,7 @@ struct JobDev {
   const int* tile_src;
   const unsigned char* tile_act;
   const int* tile_nact;
-  double scale[kMaxHeightJ];  // 1 / a_l, the M2L level factor
+  double scale[kMaxHeightJ];  // a_l^-p, the M2L level factor
   const double* kp64;
   const float* kp32;
   // compressed M2L (svd != 0): per packed operator kid, the padded rank and

@@ -129,9 +129,10 @@ void cheb_T(int l, double x, double* T) {
   for (int n = 2; n < l; ++n) T[n] = 2.0 * x * T[n - 1] - T[n - 2];
 }
 
-// Canonical unit operators: Kc[c][m][n] = 1 / |xb_m - xb_n - 2 tc|
+// Canonical unit operators: Kc[c][m][n] = |xb_m - xb_n - 2 tc|^-p for the
+// kernel |x - y|^-p (p = 1 or 2)
 __global__ void canon_kernel(const double* __restrict__ xi, const int* __restrict__ tc,
-                             int l, int ncanon, double* __restrict__ Kc) {
+                             int l, int ncanon, int p, double* __restrict__ Kc) {
   const int l3 = l * l * l;
   const int64_t total = int64_t(ncanon) * l3 * l3;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
@@ -144,7 +145,8 @@ __global__ void canon_kernel(const double* __restrict__ xi, const int* __restric
     const double dx = xi[m1] - xi[n1] - 2.0 * tc[3 * c];
     const double dy = xi[m2] - xi[n2] - 2.0 * tc[3 * c + 1];
     const double dz = xi[m3] - xi[n3] - 2.0 * tc[3 * c + 2];
-    Kc[e] = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    Kc[e] = p == 2 ? 1.0 / r2 : 1.0 / sqrt(r2);
   }
 }
 
@@ -186,15 +188,16 @@ __global__ void pack_kernel(const double* __restrict__ Kc, const int* __restrict
 }
 
 std::mutex g_ops_mu;
-std::map<std::pair<int, int>, std::unique_ptr<OpSet>> g_ops;  // (device, order)
+// (device, order, kernel exponent)
+std::map<std::tuple<int, int, int>, std::unique_ptr<OpSet>> g_ops;
 
 }  // namespace
 
-const OpSet* get_opset(int l, hipStream_t s) {
+const OpSet* get_opset(int l, int kernel, hipStream_t s) {
   int dev = 0;
   FMM_HIP_CHECK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ops_mu);
-  auto it = g_ops.find({dev, l});
+  auto it = g_ops.find(std::make_tuple(dev, l, kernel));
   if (it != g_ops.end()) return it->second.get();
   const StaticTables& T = tables();
   auto op = std::make_unique<OpSet>();
@@ -255,7 +258,7 @@ const OpSet* get_opset(int l, hipStream_t s) {
     const size_t npack = size_t(kOffsets) * op->mt * op->kc * 256;
     op->kpack64 = static_cast<double*>(dev_alloc(sizeof(double) * npack));
     op->kpack32 = static_cast<float*>(dev_alloc(sizeof(float) * npack));
-    canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, kc_d);
+    canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, kernel, kc_d);
     FMM_HIP_CHECK(hipGetLastError());
     pack_kernel<<<4096, 256, 0, s>>>(kc_d, info_d, l, op->mt, op->kc, op->kpack64, op->kpack32);
     FMM_HIP_CHECK(hipGetLastError());
@@ -267,7 +270,7 @@ const OpSet* get_opset(int l, hipStream_t s) {
   }
   for (void* q : tmp) dev_free(q);
   const OpSet* r = op.get();
-  g_ops[{dev, l}] = std::move(op);
+  g_ops[std::make_tuple(dev, l, kernel)] = std::move(op);
   return r;
 }
 
@@ -536,21 +539,22 @@ __global__ void svd_pack_kernel(const double* __restrict__ U, const double* __re
 }
 
 std::mutex g_svd_mu;
-std::map<std::tuple<int, int, double>, std::unique_ptr<SvdOps>> g_svd;
+// (device, order, tolerance, kernel exponent)
+std::map<std::tuple<int, int, double, int>, std::unique_ptr<SvdOps>> g_svd;
 rocblas_handle g_blas[64] = {nullptr};
 
 }  // namespace
 
 int kid_canon(int kid) { return tables().offs[kid].canon; }
 
-const SvdOps* get_svd_ops(int l, double eps, hipStream_t s) {
+const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
   int dev = 0;
   FMM_HIP_CHECK(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_svd_mu);
-  auto key = std::make_tuple(dev, l, eps);
+  auto key = std::make_tuple(dev, l, eps, kernel);
   auto it = g_svd.find(key);
   if (it != g_svd.end()) return it->second.get();
-  const OpSet* op = get_opset(l, s);
+  const OpSet* op = get_opset(l, kernel, s);
   const StaticTables& T = tables();
   const int l3 = l * l * l;
   auto sv = std::make_unique<SvdOps>();
@@ -591,7 +595,7 @@ const SvdOps* get_svd_ops(int l, double eps, hipStream_t s) {
     double* S = static_cast<double*>(talloc(sizeof(double) * 16 * l3));
     double* E = static_cast<double*>(talloc(sizeof(double) * 16 * l3));
     int* dinfo = static_cast<int*>(talloc(sizeof(int) * 16));
-    canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, A);
+    canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, kernel, A);
     FMM_HIP_CHECK(hipGetLastError());
     if (dev < 0 || dev >= 64) throw FmmError{FMM_ERR_HIP, "device index out of range"};
     if (!g_blas[dev] && rocblas_create_handle(&g_blas[dev]) != rocblas_status_success)

@@ -21,6 +21,8 @@ PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED
               "fp64_svd": FMM_FP64_SVD, "mixed_svd": FMM_MIXED_SVD}
 FMM_SCHEDULE_SERIAL, FMM_SCHEDULE_FORKED = 0, 1
 SCHEDULES = {"serial": FMM_SCHEDULE_SERIAL, "forked": FMM_SCHEDULE_FORKED}
+FMM_KERNEL_INV_R, FMM_KERNEL_INV_R2 = 1, 2
+KERNELS = {"inv_r": FMM_KERNEL_INV_R, "inv_r2": FMM_KERNEL_INV_R2}
 
 EXPORT_KEYS, EXPORT_PERM, EXPORT_LEAF_START, EXPORT_CELL_KEYS = 0, 1, 2, 3
 EXPORT_NEAR_OFF, EXPORT_NEAR_IDX, EXPORT_FAR_OFF, EXPORT_FAR_IDX = 4, 5, 6, 7
@@ -98,6 +100,7 @@ def lib():
     L.fmm_last_error.restype = ctypes.c_char_p
     L.fmm_plan_set_precision.argtypes = [vp, i32]
     L.fmm_plan_set_schedule.argtypes = [vp, i32]
+    L.fmm_plan_set_kernel.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
     L.fmm_plan_svd_info.argtypes = [vp, ctypes.POINTER(SvdInfo)]
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
@@ -151,7 +154,8 @@ def _dev_f64(t, shape, name):
 class Plan:
     """An FMM plan over fixed particle positions (``fmm_plan``)."""
 
-    def __init__(self, positions, height: int, order: int, precision="fp64", stream=None):
+    def __init__(self, positions, height: int, order: int, precision="fp64", stream=None,
+                 kernel="inv_r"):
         self.n = int(positions.shape[0])
         ptr = _dev_f64(positions, (self.n, 3), "positions")
         if stream is None:
@@ -163,6 +167,9 @@ class Plan:
             raise FMMError(FMM_ERR_ARG, last_error())
         self._h = ctypes.c_void_p(h)
         self.height, self.order = int(height), int(order)
+        self.kernel = FMM_KERNEL_INV_R
+        if kernel not in ("inv_r", FMM_KERNEL_INV_R):
+            self.set_kernel(kernel)
         self.set_precision(precision)
 
     @property
@@ -180,6 +187,12 @@ class Plan:
         chain; the default)."""
         code = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         _check(lib().fmm_plan_set_schedule(self._h, code))
+
+    def set_kernel(self, kernel):
+        """"inv_r" (1/r, the default) or "inv_r2" (1/r^2)."""
+        code = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        _check(lib().fmm_plan_set_kernel(self._h, code))
+        self.kernel = code
 
     def set_m2l_tolerance(self, eps: float):
         _check(lib().fmm_plan_set_m2l_tolerance(self._h, float(eps)))

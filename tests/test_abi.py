@@ -51,6 +51,7 @@ def test_calls_reject_null_plan():
     assert lib.fmm_evaluate_parts(None, fake, fake, fake, fake, fake, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_precision(None, 0) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_schedule(None, fmm.FMM_SCHEDULE_SERIAL) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_set_kernel(None, fmm.FMM_KERNEL_INV_R2) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_info(None, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_export(None, 0, 0, fake, 8) == fmm.FMM_ERR_ARG
     assert lib.fmm_set_m2l_timing_events(fake, None) == fmm.FMM_ERR_ARG
