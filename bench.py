@@ -26,7 +26,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # dense MFMA: FP64, FP32
+# MI355X published peaks: dense MFMA FP64 / FP32 (the FP64 / FP32 vector
+# peaks are the same numbers), and HBM3E bandwidth
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+HBM_GBPS = 8000.0
 GATE = 1e-6
 
 
@@ -318,14 +321,17 @@ def main():
         plan.release()
     ok = [m for m in modes if errors[m] <= GATE]
 
+    def new_events(k):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+        for x in ev:  # materialise the HIP events before handing them over
+            x.record(stream)
+        return ev
+
     def run_steps(prec, steps, warmup):
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-               torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps + warmup)]
+        """Plan + evaluate + release per step on the default (forked)
+        schedule; the M2L launch bracketed by HIP events in every step."""
         with torch.cuda.stream(stream):
-            for e in ev:  # materialise the HIP events before handing them over
-                for x in e:
-                    x.record(stream)
+            ev = [new_events(4) for _ in range(steps + warmup)]
             stream.synchronize()
             torch.cuda.synchronize()
             t0 = None
@@ -346,6 +352,27 @@ def main():
         step_ms = np.array([a.elapsed_time(b) for a, b, _, _ in ev[warmup:]])
         m2l_ms = np.array([a.elapsed_time(b) for _, _, a, b in ev[warmup:]])
         return (t1 - t0) * 1e3 / steps, step_ms, m2l_ms
+
+    def step_times(prec, reps):
+        """Average duration of each bulk operator's kernel, every operator on
+        one stream (serial schedule, so no kernel shares the GPU)."""
+        names = ("m2l", "p2p", "p2m", "l2p")
+        with torch.cuda.stream(stream):
+            p = fmm.Plan(pos_d, h, l, prec, stream=stream)
+            p.set_schedule("serial")
+            p.evaluate(q_d, phi, frc, stream=stream)
+            ev = [new_events(2 * len(names)) for _ in range(reps)]
+            stream.synchronize()
+            for e in ev:
+                for k, name in enumerate(names):
+                    fmm.set_step_timing_events(name, e[2 * k], e[2 * k + 1])
+                p.evaluate(q_d, phi, frc, stream=stream)
+            stream.synchronize()
+            for name in names:
+                fmm.set_step_timing_events(name, None, None)
+            p.release()
+        return {name: float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
+                for k, name in enumerate(names)}
 
     def eval_only(prec, steps):
         with torch.cuda.stream(stream):
@@ -382,6 +409,30 @@ def main():
             "flops_per_launch": flops, "far_pairs": int(infos[precision].far_pairs),
             "avg_launch_ms": round(m2l_s * 1e3, 4)}
 
+    # every bulk operator against the roof that bounds it (serial schedule)
+    st = step_times(precision, 10)
+    inf = infos[precision]
+    l3 = l ** 3
+    p2p_flops = 20.0 * float(inf.near_pairs)
+    p2m_bytes = 32.0 * n + 8.0 * l3 * float(inf.n_leaf)
+    l2p_bytes = 64.0 * n + 8.0 * l3 * float(inf.n_leaf)
+    vpeak = PEAK_TFLOPS["mixed" if precision.startswith("mixed") else "fp64"]
+
+    def rate(work, ms, peak, unit, bound, what):
+        a = work / (ms / 1e3) / (1e12 if unit == "TFLOP/s" else 1e9)
+        return {"bound": bound, "avg_ms": round(ms, 4), "achieved": round(a, 2), "peak": peak,
+                "unit": unit, "frac": round(a / peak, 4), "work_per_launch": work, "work": what}
+
+    kernels = {
+        "m2l": rate(flops, st["m2l"], peak, "TFLOP/s", "mfma", "algorithmic flops"),
+        "p2p": rate(p2p_flops, st["p2p"], vpeak, "TFLOP/s", "valu",
+                    "20 flops per directed near pair"),
+        "p2m": rate(p2m_bytes, st["p2m"], HBM_GBPS, "GB/s", "hbm",
+                    "32 B per particle read + l^3 x 8 B per leaf written"),
+        "l2p": rate(l2p_bytes, st["l2p"], HBM_GBPS, "GB/s", "hbm",
+                    "64 B per particle read and written + l^3 x 8 B per leaf read"),
+    }
+
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(kind, n, h, l, seed, args.cpu_budget)
@@ -403,7 +454,8 @@ def main():
         "config": {"workload": args.workload, "kind": kind, "N": n, "height": h, "order": l,
                    "seed": seed, "precision": precision,
                    "m2l_svd_tolerance": svd.eps if precision.endswith("svd") else None,
-                   "step": "plan+evaluate+release, inputs resident in HBM"},
+                   "step": "plan+evaluate+release, inputs resident in HBM",
+                   "schedule": "forked (near field beside the far chain)"},
         "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "eval_only_ms": round(eval_ms, 4),
@@ -416,6 +468,7 @@ def main():
                       "m2l_flops": float(infos[m].m2l_flops)} for m in modes},
         "svd_weighted_rank": round(svd.weighted_rank, 3),
         "roofline": roof,
+        "kernels": kernels,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

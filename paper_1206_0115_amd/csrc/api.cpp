@@ -508,11 +508,17 @@ int fmm_plan_export(fmm_plan_t p, int what, int level, void* dst, size_t bytes) 
   });
 }
 
-int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1) {
+int fmm_set_step_timing_events(int step, hipEvent_t ev0, hipEvent_t ev1) {
+  if (step < FMM_TIME_M2L || step > FMM_TIME_L2P)
+    return fail(FMM_ERR_ARG, "unknown timed step " + std::to_string(step));
   if ((ev0 == nullptr) != (ev1 == nullptr)) return fail(FMM_ERR_ARG, "pass both events or none");
-  fmm::g_m2l_ev0 = ev0;
-  fmm::g_m2l_ev1 = ev1;
+  fmm::g_time_ev[step][0] = ev0;
+  fmm::g_time_ev[step][1] = ev1;
   return FMM_OK;
+}
+
+int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1) {
+  return fmm_set_step_timing_events(FMM_TIME_M2L, ev0, ev1);
 }
 
 void fmm_trim_cache(void) { fmm::dev_trim(); }

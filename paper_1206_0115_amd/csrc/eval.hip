@@ -620,6 +620,22 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
   FMM_HIP_CHECK(hipGetLastError());
 }
 
+namespace {
+// the step's timing events, if set, around a launch on stream s
+struct Timed {
+  int step;
+  hipStream_t s;
+  Timed(int st, hipStream_t str) : step(st), s(str) {
+    if (g_time_ev[step][0]) FMM_HIP_CHECK(hipEventRecord(g_time_ev[step][0], s));
+  }
+  // a failed record here only loses a timing; launch errors are reported by
+  // the launch itself
+  ~Timed() {
+    if (g_time_ev[step][1]) (void)hipEventRecord(g_time_ev[step][1], s);
+  }
+};
+}  // namespace
+
 // One plan: the step tables were built at plan time; every launch has one
 // block per item.  In the forked schedule the near field runs on the plan's
 // side stream between two events, concurrently with the far chain.
@@ -635,31 +651,43 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   if (forked) {
     FMM_HIP_CHECK(hipEventRecord(p->ev_fork, s));
     FMM_HIP_CHECK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), p->side);
+    {
+      Timed t(FMM_TIME_P2P, p->side);
+      launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), p->side);
+    }
     FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
   }
   if (h >= 3) {
-    launch_step(kStepP2M, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+    {
+      Timed t(FMM_TIME_P2M, s);
+      launch_step(kStepP2M, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+    }
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepM2M, L, false, J, p->tab_d + kTabM2M + st, nullptr,
                   p->tab_h[kTabM2M + st].start[1], s);
     if (mixed)
       launch_step(kStepCast, L, true, J, p->tab_d + kTabCast, nullptr,
                   p->tab_h[kTabCast].start[1], s);
-    if (g_m2l_ev0) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev0, s));
-    if (p->ntiles > 0)
-      launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
-                  p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
-    if (g_m2l_ev1) FMM_HIP_CHECK(hipEventRecord(g_m2l_ev1, s));
+    {
+      Timed t(FMM_TIME_M2L, s);
+      if (p->ntiles > 0)
+        launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
+                    p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
+    }
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,
                   p->tab_h[kTabL2L + st].start[1], s);
-    launch_step(kStepL2P, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+    {
+      Timed t(FMM_TIME_L2P, s);
+      launch_step(kStepL2P, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+    }
   }
-  if (forked)
+  if (forked) {
     FMM_HIP_CHECK(hipStreamWaitEvent(s, p->ev_join, 0));
-  else
+  } else {
+    Timed t(FMM_TIME_P2P, s);
     launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+  }
   CallDev c{q, phi, f, phi_n, f_n, phi_f, f_f};
   combine1_kernel<<<chunks, kChunk, 0, s>>>(J, c);
   FMM_HIP_CHECK(hipGetLastError());

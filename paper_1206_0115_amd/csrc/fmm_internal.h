@@ -197,6 +197,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f,
               hipStream_t stream);
 // fill the plan's JobDev and step tables and copy them to the device (api.cpp)
 void upload_job(fmm_plan_s* p, hipStream_t stream);
-// M2L timing hook: the last M2L launch is bracketed by these events when set
-extern thread_local hipEvent_t g_m2l_ev0, g_m2l_ev1;
+// Step timing hooks (enum fmm_timed_step): the step's launch in later
+// evaluations on this thread is bracketed by these events when they are set.
+extern thread_local hipEvent_t g_time_ev[4][2];
 }  // namespace fmm

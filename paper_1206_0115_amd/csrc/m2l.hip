@@ -35,7 +35,7 @@
 
 namespace fmm {
 
-thread_local hipEvent_t g_m2l_ev0 = nullptr, g_m2l_ev1 = nullptr;
+thread_local hipEvent_t g_time_ev[4][2] = {{nullptr, nullptr}};
 
 // ------------------------------------------------------------ tables
 namespace {

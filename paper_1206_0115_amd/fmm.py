@@ -106,6 +106,7 @@ def lib():
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
     L.fmm_plan_export.argtypes = [vp, i32, i32, vp, sz]
     L.fmm_set_m2l_timing_events.argtypes = [vp, vp]
+    L.fmm_set_step_timing_events.argtypes = [i32, vp, vp]
     L.fmm_trim_cache.restype = None
     L.fmm_server_create.argtypes = [sz, i32]
     L.fmm_server_create.restype = vp
@@ -269,6 +270,23 @@ class Plan:
             self.release()
         except Exception:
             pass
+
+
+FMM_TIME_M2L, FMM_TIME_P2P, FMM_TIME_P2M, FMM_TIME_L2P = 0, 1, 2, 3
+TIMED_STEPS = {"m2l": FMM_TIME_M2L, "p2p": FMM_TIME_P2P, "p2m": FMM_TIME_P2M,
+               "l2p": FMM_TIME_L2P}
+
+
+def set_step_timing_events(step, ev0, ev1):
+    """Bracket one operator's kernel ("m2l", "p2p", "p2m" or "l2p") in later
+    evaluations on this thread with two ``torch.cuda.Event`` objects (or None
+    to stop)."""
+    code = TIMED_STEPS[step] if isinstance(step, str) else int(step)
+    if ev0 is None:
+        _check(lib().fmm_set_step_timing_events(code, None, None))
+        return
+    _check(lib().fmm_set_step_timing_events(code, ctypes.c_void_p(ev0.cuda_event),
+                                            ctypes.c_void_p(ev1.cuda_event)))
 
 
 def set_m2l_timing_events(ev0, ev1):
