@@ -51,6 +51,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.kc = op->kc;
   J.nmb = p->svd ? m2l_svd_nmb(op->mt) : m2l_nmb(op->mt);
   J.kernel = p->kernel;
+  J.w32_leaf = p->w32_leaf ? 1 : 0;
   J.svd = p->svd ? 1 : 0;
   if (p->svd) {
     J.xs = p->svd->rmax_pad + 4;
@@ -97,7 +98,9 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   std::memset(p->tab_h, 0, sizeof(p->tab_h));
   p->tab_h[kTabLeaf] = one_job(int(p->nleaf));
   if (h >= 3) {
-    p->tab_h[kTabCast] = one_job(int(p->ncell_total + 1 - p->lev[2].off));
+    // rows cast to FP32: levels 2 .. h-2 when P2M writes the leaves in FP32
+    p->tab_h[kTabCast] = one_job(int((p->w32_leaf ? p->lev[h - 1].off : p->ncell_total + 1) -
+                                     p->lev[2].off));
     p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb);
     for (int st = 0; st + 4 <= h; ++st) {
       p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
@@ -114,9 +117,19 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
 
 void* fmm_plan_s::alloc(size_t b) {
   void* p = fmm::dev_alloc(b);
-  blocks.push_back(p);
+  blocks.push_back({p, b});
   bytes += b;
   return p;
+}
+
+void fmm_plan_s::free_block(void* ptr) {
+  for (size_t i = 0; i < blocks.size(); ++i)
+    if (blocks[i].first == ptr) {
+      bytes -= blocks[i].second;
+      fmm::dev_free(ptr);
+      blocks.erase(blocks.begin() + i);
+      return;
+    }
 }
 
 fmm_plan_s::~fmm_plan_s() {
@@ -127,7 +140,7 @@ fmm_plan_s::~fmm_plan_s() {
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   if (side) (void)hipStreamDestroy(side);
-  for (void* p : blocks) fmm::dev_free(p);
+  for (auto& b : blocks) fmm::dev_free(b.first);
 }
 
 namespace {
@@ -207,10 +220,8 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
     if (height >= 3) {
       p->phi_f = static_cast<double*>(p->alloc(sizeof(double) * n));
       p->f_f = static_cast<double*>(p->alloc(sizeof(double) * 3 * n));
-      p->W = static_cast<double*>(p->alloc(sizeof(double) * rows * ld));
       p->Loc = static_cast<double*>(p->alloc(sizeof(double) * rows * ld));
-      // the row past the last cell is the zero source of absent M2L slots
-      FMM_HIP_CHECK(hipMemsetAsync(p->W + (rows - 1) * ld, 0, sizeof(double) * ld, stream));
+      // the multipole buffers depend on the precision mode: ensure_w
     }
     fmm::upload_job(p, stream);
     FMM_HIP_CHECK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
@@ -235,9 +246,51 @@ void fmm_release(fmm_plan_t plan) {
   delete plan;
 }
 
-// Apply the precision mode and M2L tolerance: allocate the FP32 multipoles of
-// the mixed modes, fetch the compressed operators of the SVD modes, and
-// refresh the device-side job description.
+static bool is_mixed(int mode) { return mode == FMM_MIXED_FP32 || mode == FMM_MIXED_SVD; }
+
+// Multipole storage for the plan's precision mode.  FP64 modes: W (FP64) for
+// every cell.  Mixed modes: W32 (FP32) for every cell, written directly by P2M
+// at the leaf level and cast from W above it, and W (FP64) only for the
+// levels above the leaves, where M2M runs in FP64; this halves the largest
+// buffer at the 288 GB scale.  The row past the last cell is the zero source
+// of absent M2L slots.  Returns whether a buffer changed.
+static bool ensure_w(fmm_plan_s* p, hipStream_t s) {
+  if (p->height < 3) return false;
+  const bool mixed = is_mixed(p->precision);
+  const int ld = p->ops->ld;
+  const int64_t rows = p->ncell_total + 1;
+  const int64_t want64 = mixed ? p->lev[p->height - 1].off : rows;
+  bool changed = false;
+  if (p->w64_rows != want64 || !p->W) {
+    if (p->W) p->free_block(p->W);
+    p->W = nullptr;  // a failed allocation below leaves no stale pointer
+    p->w64_rows = 0;
+    p->W = static_cast<double*>(p->alloc(sizeof(double) * size_t(want64) * ld));
+    if (!mixed)
+      FMM_HIP_CHECK(hipMemsetAsync(p->W + (rows - 1) * ld, 0, sizeof(double) * ld, s));
+    p->w64_rows = want64;
+    changed = true;
+  }
+  if (mixed && !p->W32) {
+    p->w32_leaf = false;
+    p->W32 = static_cast<float*>(p->alloc(sizeof(float) * size_t(rows) * ld));
+    FMM_HIP_CHECK(hipMemsetAsync(p->W32 + (rows - 1) * ld, 0, sizeof(float) * ld, s));
+    changed = true;
+  } else if (!mixed && p->W32) {
+    p->free_block(p->W32);
+    p->W32 = nullptr;
+    changed = true;
+  }
+  if (p->w32_leaf != mixed) {
+    p->w32_leaf = mixed;
+    changed = true;
+  }
+  return changed;
+}
+
+// Apply the precision mode and M2L tolerance: size the multipole buffers for
+// the mode, fetch the compressed operators of the SVD modes, and refresh the
+// device-side job description.
 static void apply_mode(fmm_plan_s* p, int mode) {
   if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
   const bool mixed = mode == FMM_MIXED_FP32 || mode == FMM_MIXED_SVD;
@@ -260,12 +313,9 @@ static void apply_mode(fmm_plan_s* p, int mode) {
                               std::to_string(have) +
                               "); use a larger tolerance or the dense mode"};
   }
-  if (mixed && !p->W32 && p->height >= 3) {
-    const size_t rows = size_t(p->ncell_total + 1);
-    p->W32 = static_cast<float*>(p->alloc(sizeof(float) * rows * p->ops->ld));
-  }
   p->svd = sv;
   p->precision = mode;
+  ensure_w(p, p->last_stream);
   fmm::upload_job(p, p->last_stream);
 }
 
@@ -358,6 +408,8 @@ static int eval_common(fmm_plan_t p, const double* q, double* phi, double* f, do
     int dev = 0;
     FMM_HIP_CHECK(hipGetDevice(&dev));
     if (dev != p->device) return fail(FMM_ERR_ARG, "plan belongs to another device");
+    // the first evaluation of a plan whose mode was never set allocates here
+    if (ensure_w(p, s)) fmm::upload_job(p, s);
     fmm::evaluate(p, q, phi, f, pn, fn, pf, ff, s);
     FMM_HIP_CHECK(hipEventRecord(p->done, s));
     p->in_flight = true;

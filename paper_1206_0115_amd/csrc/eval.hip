@@ -81,10 +81,19 @@ __global__ __launch_bounds__(256) void p2m_kernel(const JobDev* __restrict__ job
         }
       __syncthreads();
     }
-    double* out = J.W + (J.lev_off[J.height - 1] + a) * J.ld;
-    if (owner)
-      for (int m3 = 0; m3 < L; ++m3) out[(m1 * L + m2) * L + m3] = acc[m3];
-    for (int e = L * L * L + t; e < J.ld; e += nt) out[e] = 0.0;
+    const int64_t row = (J.lev_off[J.height - 1] + a) * int64_t(J.ld);
+    if (J.w32_leaf) {
+      // mixed modes keep the leaf multipoles in FP32 only
+      float* out = J.W32 + row;
+      if (owner)
+        for (int m3 = 0; m3 < L; ++m3) out[(m1 * L + m2) * L + m3] = float(acc[m3]);
+      for (int e = L * L * L + t; e < J.ld; e += nt) out[e] = 0.f;
+    } else {
+      double* out = J.W + row;
+      if (owner)
+        for (int m3 = 0; m3 < L; ++m3) out[(m1 * L + m2) * L + m3] = acc[m3];
+      for (int e = L * L * L + t; e < J.ld; e += nt) out[e] = 0.0;
+    }
   }
 }
 
@@ -117,9 +126,14 @@ __global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __rest
       const double* Sx = Sc + ((o & 1) ? L2 : 0);
       const double* Sy = Sc + (((o >> 1) & 1) ? L2 : 0);
       const double* Sz = Sc + (((o >> 2) & 1) ? L2 : 0);
-      const double* wc = J.W + (J.lev_off[lv + 1] + c) * ld;
+      const int64_t crow = (J.lev_off[lv + 1] + c) * int64_t(ld);
       __syncthreads();
-      for (int e = t; e < L3; e += kTransThreads) b0[e] = wc[e];
+      if (J.w32_leaf && lv + 1 == J.height - 1) {
+        // leaf children stored in FP32 (mixed modes); the contraction is FP64
+        for (int e = t; e < L3; e += kTransThreads) b0[e] = double(J.W32[crow + e]);
+      } else {
+        for (int e = t; e < L3; e += kTransThreads) b0[e] = J.W[crow + e];
+      }
       __syncthreads();
       for (int e = t; e < L3; e += kTransThreads) {  // along z
         const int ab = e / L, m3 = e % L;
@@ -542,7 +556,8 @@ __global__ __launch_bounds__(kChunk) void combine1_kernel(const JobDev* __restri
   combine_chunk(*job, call, blockIdx.x);
 }
 
-// FP32 copy of the multipoles of levels >= 2; item = one row.
+// FP32 copy of the multipoles of levels 2 .. h-2 (the leaf level is written
+// in FP32 by P2M in the mixed modes); item = one row.
 __global__ __launch_bounds__(256) void cast_kernel(const JobDev* __restrict__ jobs,
                                                    const StepTab* __restrict__ tab) {
   FOR_ITEMS(tab) {
@@ -665,7 +680,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepM2M, L, false, J, p->tab_d + kTabM2M + st, nullptr,
                   p->tab_h[kTabM2M + st].start[1], s);
-    if (mixed)
+    if (mixed && p->tab_h[kTabCast].start[1] > 0)
       launch_step(kStepCast, L, true, J, p->tab_d + kTabCast, nullptr,
                   p->tab_h[kTabCast].start[1], s);
     {

@@ -176,15 +176,18 @@ struct fmm_plan_s {
   hipEvent_t done = nullptr;       // recorded after each evaluation
   int schedule = FMM_SCHEDULE_FORKED;
   int kernel = FMM_KERNEL_INV_R;   // exponent p of the kernel |x - y|^-p
+  int64_t w64_rows = 0;            // rows allocated in W (all cells + 1, or levels < h-1)
+  bool w32_leaf = false;           // mixed modes: leaf multipoles only in W32
   hipStream_t side = nullptr;      // the near-field branch of the forked schedule
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool in_flight = false;
   hipStream_t last_stream = nullptr;  // stream of the last evaluation
-  std::vector<void*> blocks;       // every device block this plan owns
+  std::vector<std::pair<void*, size_t>> blocks;  // every device block this plan owns
   size_t bytes = 0;
   std::mutex mu;
 
   void* alloc(size_t b);
+  void free_block(void* ptr);      // return one block of this plan to the cache
   ~fmm_plan_s();
 };
 

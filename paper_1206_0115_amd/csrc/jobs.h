@@ -39,6 +39,7 @@ struct JobDev {
   const int* near;
   int n, nleaf, height, order, ld, mt, kc, nmb, ntiles, has_far;
   int kernel;  // p of the kernel |x - y|^-p (1 or 2)
+  int w32_leaf;  // leaf multipoles live in W32 only (W holds levels < h-1)
   LeafGeom geo;
   double* W;
   float* W32;

@@ -290,7 +290,7 @@ bool fmm_server_s::launch_batch() {
         [&](Request* r) { return int(r->plan->lev[r->h - 2 - s].ncell); },
         [&](Request* r) { return r->h - 2 - s; });
   add(kStepCast, 0, true, [&](Request* r) { return far(r) && mixed(r); },
-      [](Request* r) { return int(r->plan->ncell_total + 1 - r->plan->lev[2].off); }, lvl0);
+      [](Request* r) { return int(r->plan->tab_h[kTabCast].start[1]); }, lvl0);
   for (int L : orders)
     for (int f32 = 0; f32 < 2; ++f32)
       for (int cmp = 0; cmp < 2; ++cmp)
