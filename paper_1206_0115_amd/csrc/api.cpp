@@ -49,7 +49,8 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.ld = op->ld;
   J.mt = op->mt;
   J.kc = op->kc;
-  J.nmb = p->svd ? m2l_svd_nmb(op->mt) : m2l_nmb(op->mt);
+  const bool fp32 = p->precision == FMM_MIXED_FP32 || p->precision == FMM_MIXED_SVD;
+  J.nmb = p->svd ? m2l_svd_nmb(op->mt, fp32) : m2l_nmb(op->mt);
   J.kernel = p->kernel;
   J.w32_leaf = p->w32_leaf ? 1 : 0;
   J.svd = p->svd ? 1 : 0;

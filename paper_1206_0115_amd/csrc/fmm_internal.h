@@ -118,7 +118,7 @@ enum {
 };
 
 int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
-int m2l_svd_nmb(int mt);  // the same for the compressed M2L
+int m2l_svd_nmb(int mt, bool fp32);  // work items per tile for the compressed M2L
 // LDS bytes of one compressed-M2L workgroup for a slab stride of xs values
 size_t m2l_svd_lds_bytes(int xs, bool fp32);
 

@@ -668,23 +668,29 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
   return r;
 }
 
-// Target columns per workgroup of the compressed kernel: 16 * FMM_M2L_SVD_NT
-// (2: half a tile, which keeps two workgroups per CU; 4: the whole tile).
-#ifndef FMM_M2L_SVD_NT
-#define FMM_M2L_SVD_NT 2
+// Target columns per workgroup of the compressed kernel, 16 * NT, for FP32
+// and FP64.  Fewer columns than the tile's 64 cost operator re-reads (from
+// L2) but free registers for two wavefronts per SIMD; measured on gfx950 at
+// order 7: FP32 best at 32 columns (8.6 ms), FP64 at 16 (11.8 ms).
+#ifndef FMM_M2L_SVD_NT_F32
+#define FMM_M2L_SVD_NT_F32 2
 #endif
-constexpr int kSvdNT = FMM_M2L_SVD_NT;
-static_assert(kSvdNT == 1 || kSvdNT == 2 || kSvdNT == 4, "16, 32 or 64 target columns");
+#ifndef FMM_M2L_SVD_NT_F64
+#define FMM_M2L_SVD_NT_F64 1
+#endif
+constexpr int svd_nt(bool fp32) { return fp32 ? FMM_M2L_SVD_NT_F32 : FMM_M2L_SVD_NT_F64; }
+static_assert(svd_nt(true) == 1 || svd_nt(true) == 2 || svd_nt(true) == 4, "NT");
+static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "NT");
 // Whether phase 2 loads its U fragments one rank chunk ahead.
 #ifndef FMM_M2L_SVD_P2_PREFETCH
 #define FMM_M2L_SVD_P2_PREFETCH 0
 #endif
 // Wavefronts per SIMD the register allocation must allow, FP32 and FP64.
 #ifndef FMM_M2L_SVD_WAVES_F32
-#define FMM_M2L_SVD_WAVES_F32 1
+#define FMM_M2L_SVD_WAVES_F32 2
 #endif
 #ifndef FMM_M2L_SVD_WAVES_F64
-#define FMM_M2L_SVD_WAVES_F64 1
+#define FMM_M2L_SVD_WAVES_F64 2
 #endif
 
 // One workgroup = 4 wavefronts = one (tile, M-block, N-group) item, the
@@ -903,19 +909,19 @@ int m2l_svd_mtw(int mt) {
   return 6;
 }
 
-int m2l_svd_nmb(int mt) {
+int m2l_svd_nmb(int mt, bool fp32) {
   const int w = m2l_svd_mtw(mt);
-  return (mt + 4 * w - 1) / (4 * w) * (4 / kSvdNT);
+  return (mt + 4 * w - 1) / (4 * w) * (4 / svd_nt(fp32));
 }
 
 size_t m2l_svd_lds_bytes(int xs, bool fp32) {
-  return size_t(4) * 16 * kSvdNT * xs * (fp32 ? sizeof(float) : sizeof(double));
+  return size_t(4) * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 template <typename T, bool FOLD>
 static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid,
                            size_t lds, hipStream_t s) {
-  constexpr int NT = kSvdNT;
+  constexpr int NT = svd_nt(sizeof(T) == 4);
   switch (mtw) {
     case 1: m2l_svd_kernel<T, 1, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
     case 2: m2l_svd_kernel<T, 2, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
