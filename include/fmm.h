@@ -135,8 +135,10 @@ int fmm_plan_set_precision(fmm_plan_t plan, int mode);
  * branches may run at the same time and meet at the final sum.
  *   FMM_SCHEDULE_SERIAL  every operator in order on the caller's stream
  *   FMM_SCHEDULE_FORKED  (default) P2P on a stream owned by the plan, forked
- *                        from and joined back into the caller's stream with
- *                        events; the far chain stays on the caller's stream
+ *                        from the caller's stream after the M2L launch (so
+ *                        it runs beside L2L and L2P, which leave the GPU
+ *                        partly idle) and joined back before the final sum;
+ *                        the far chain stays on the caller's stream
  * Both schedules launch the same kernels on the same data: results are
  * bit-identical.  Stream capture of the caller's stream captures the fork
  * and the join.  Returns FMM_ERR_ARG for a null plan or unknown schedule. */

@@ -55,7 +55,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.w32_leaf = p->w32_leaf ? 1 : 0;
   J.svd = p->svd ? 1 : 0;
   if (p->svd) {
-    J.xs = p->svd->rmax_pad + 4;
+    J.xs = m2l_svd_xs(p->svd->rmax_pad, fp32);
     J.svd_rpad = p->svd->rpad;
     J.svd_off = p->svd->off;
     J.p1_64 = p->svd->p1_64;
@@ -300,8 +300,8 @@ static void apply_mode(fmm_plan_s* p, int mode) {
                              ? fmm::get_svd_ops(p->order, p->m2l_eps, p->kernel, p->last_stream)
                              : nullptr;
   if (sv) {
-    // the compressed kernel keeps four rank x 16*NT slabs in LDS
-    const size_t need = fmm::m2l_svd_lds_bytes(sv->rmax_pad + 4, mixed);
+    // the compressed kernel keeps two sets of four rank x 16*NT slabs in LDS
+    const size_t need = fmm::m2l_svd_lds_bytes(fmm::m2l_svd_xs(sv->rmax_pad, mixed), mixed);
     int have = 0;
     FMM_HIP_CHECK(hipDeviceGetAttribute(&have, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                         p->device));

@@ -653,7 +653,10 @@ struct Timed {
 
 // One plan: the step tables were built at plan time; every launch has one
 // block per item.  In the forked schedule the near field runs on the plan's
-// side stream between two events, concurrently with the far chain.
+// side stream, forked after the M2L launch and joined before the combine, so
+// it fills the GPU beside the L2L levels and L2P, which do not.  (Forked
+// earlier, its 64-thread blocks flood the GPU and delay P2M and M2M, and it
+// cannot share CUs with M2L, whose wavefronts hold the register files.)
 void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* phi_n,
               double* f_n, double* phi_f, double* f_f, hipStream_t s) {
   const int L = p->order, h = p->height;
@@ -663,7 +666,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   gather1_kernel<<<chunks, kChunk, 0, s>>>(J, q);
   FMM_HIP_CHECK(hipGetLastError());
   const bool forked = p->schedule == FMM_SCHEDULE_FORKED;
-  if (forked) {
+  auto fork_near = [&]() {
     FMM_HIP_CHECK(hipEventRecord(p->ev_fork, s));
     FMM_HIP_CHECK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
     {
@@ -671,7 +674,8 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
       launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), p->side);
     }
     FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
-  }
+  };
+  if (forked && h < 3) fork_near();
   if (h >= 3) {
     {
       Timed t(FMM_TIME_P2M, s);
@@ -689,6 +693,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
         launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
                     p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
     }
+    if (forked) fork_near();
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,
                   p->tab_h[kTabL2L + st].start[1], s);

@@ -121,6 +121,7 @@ int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
 int m2l_svd_nmb(int mt, bool fp32);  // work items per tile for the compressed M2L
 // LDS bytes of one compressed-M2L workgroup for a slab stride of xs values
 size_t m2l_svd_lds_bytes(int xs, bool fp32);
+int m2l_svd_xs(int rmax_pad, bool fp32);  // that slab stride for a padded rank
 
 }  // namespace fmm
 

@@ -702,8 +702,10 @@ static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "N
 //            in that order, so every wavefront sees the same X and the
 //            result does not depend on timing).  Wavefront w owns MTW
 //            16-row M-tiles of the output.
-// Two barriers per offset: after the partial sums, and before the slabs
-// are overwritten by the next offset.
+// The slabs are double-buffered, the buffer alternating with every offset
+// the workgroup processes (also across items), so one barrier per offset
+// suffices: a wavefront writes buffer b again only after the barrier of the
+// next offset, which every wavefront reaches after its reads of buffer b.
 template <typename T, int MTW, int NT, bool FOLD>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
                                                  : FMM_M2L_SVD_WAVES_F64) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
@@ -711,7 +713,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
   typedef typename Vec4<T>::type T4;
   constexpr int NC = 16 * NT, NG = 4 / NT;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* P = reinterpret_cast<T*>(lds_raw);
+  T* const lds = reinterpret_cast<T*>(lds_raw);
+  int buf = 0;
   const int total = step_total(*tab);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
@@ -738,7 +741,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
                                     : reinterpret_cast<const T*>(J.p1_64);
     const T* __restrict__ P2 = FOLD ? reinterpret_cast<const T*>(J.p2_32)
                                     : reinterpret_cast<const T*>(J.p2_64);
-    T* Pw = P + wave * NC * XS;
     T4 acc[MTW][NT];
     d4 acc64[FOLD ? MTW : 1][NT];
 #pragma unroll
@@ -758,6 +760,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
       const int kid = kidp[s];
       const int rp = J.svd_rpad[kid], nr = rp >> 4;
       const int64_t off = J.svd_off[kid];
+      T* const P = lds + buf * 4 * NC * XS;
+      T* const Pw = P + wave * NC * XS;
+      buf ^= 1;
       // ---- phase 1: this wavefront's share of X, into its slab ----
       const T* bp[NT];
 #pragma unroll
@@ -878,7 +883,6 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
             }
         }
       }
-      __syncthreads();
     }
 
     const double sc = J.scale[tl.level];
@@ -914,8 +918,12 @@ int m2l_svd_nmb(int mt, bool fp32) {
   return (mt + 4 * w - 1) / (4 * w) * (4 / svd_nt(fp32));
 }
 
+// Slab row stride: the padded rank plus 16 bytes, so that consecutive target
+// columns start 16 bytes apart modulo the LDS banks.
+int m2l_svd_xs(int rmax_pad, bool fp32) { return rmax_pad + (fp32 ? 4 : 2); }
+
 size_t m2l_svd_lds_bytes(int xs, bool fp32) {
-  return size_t(4) * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double));
+  return size_t(2) * 4 * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double));
 }
 
 template <typename T, bool FOLD>

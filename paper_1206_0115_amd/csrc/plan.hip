@@ -303,6 +303,68 @@ __global__ void set_int_kernel(int* __restrict__ p, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// ------------------------------------------------- all coarser levels at once
+// Leaf i of the sorted unique leaf keys k starts a new cell at level l exactly
+// when (k[i] >> 3(h-1-l)) != (k[i-1] >> 3(h-1-l)), i.e. at every level from
+// h-1-floor(t/3) on, t the highest bit in which k[i] and k[i-1] differ.  One
+// pass therefore gives the segment flags of every level l = 0 .. h-2, stored
+// level-major: flags[l * nl + i].
+__global__ void level_flags_kernel(const uint64_t* __restrict__ lk, int64_t nl, int h,
+                                   int64_t* __restrict__ flags) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  int first = 0;  // leaf 0 starts a cell at every level
+  if (i > 0) first = h - 1 - (63 - __clzll(lk[i] ^ lk[i - 1])) / 3;
+  for (int l = 0; l < h - 1; ++l) flags[int64_t(l) * nl + i] = l >= first ? 1 : 0;
+}
+
+struct LevelOut {
+  uint64_t* keys[kMaxHeight];
+  int* child_start[kMaxHeight];  // [ncell_l + 1] first child at level l+1
+  int* parent[kMaxHeight];       // [ncell_l] cell of level l-1 containing it
+};
+
+// After an exclusive scan S of the concatenated flags: ncell of every level,
+// count[l] = S[(l+1) nl] - S[l nl] (the last level up to the total).
+__global__ void level_counts_kernel(const int64_t* __restrict__ flags,
+                                    const int64_t* __restrict__ S, int64_t nl, int h,
+                                    int64_t* __restrict__ count) {
+  const int l = threadIdx.x;
+  if (l >= h - 1) return;
+  const int64_t end = l + 1 < h - 1 ? S[int64_t(l + 1) * nl]
+                                    : S[int64_t(h - 1) * nl - 1] + flags[int64_t(h - 1) * nl - 1];
+  count[l] = end - S[int64_t(l) * nl];
+}
+
+// Level l (grid y) and leaf i: the unique keys and child offsets of level l
+// and the parents of level l+1, all read off the flags and their scan.
+__global__ void level_emit_kernel(const uint64_t* __restrict__ lk, int64_t nl, int h,
+                                  const int64_t* __restrict__ flags,
+                                  const int64_t* __restrict__ S, LevelOut out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int l = blockIdx.y;
+  if (i >= nl) return;
+  const int64_t at = int64_t(l) * nl + i;
+  const int64_t f = flags[at];
+  const int64_t pos = S[at] - S[int64_t(l) * nl];
+  const bool leaf1 = l + 1 == h - 1;  // level l+1 is the leaf level
+  const bool f1 = leaf1 ? true : flags[at + nl] != 0;
+  const int64_t c1 = leaf1 ? i : S[at + nl] - S[int64_t(l + 1) * nl];
+  if (f) {
+    out.keys[l][pos] = lk[i] >> (3 * (h - 1 - l));
+    out.child_start[l][pos] = int(c1);  // a level-l boundary is one at l+1
+  }
+  if (f1) out.parent[l + 1][c1] = int(pos + f - 1);
+}
+
+// child_start[l][ncell_l] = ncell_{l+1} for every level l < h-1
+__global__ void level_ends_kernel(LevelOut out, const int64_t* __restrict__ count, int h,
+                                  int64_t nl) {
+  const int l = threadIdx.x;
+  if (l >= h - 1) return;
+  out.child_start[l][count[l]] = int(l + 1 < h - 1 ? count[l + 1] : nl);
+}
+
 // ------------------------------------------------------------ gathers
 __global__ void gather_pos_kernel(const double* __restrict__ pos,
                                   const int* __restrict__ perm, int64_t n,
@@ -341,10 +403,21 @@ __global__ void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void table_scatter_kernel(const uint64_t* __restrict__ keys,
-                                     int64_t nc, int* __restrict__ table) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < nc) table[keys[i]] = int(i);
+struct TableSet {
+  const uint64_t* keys[kMaxHeight];
+  int* table[kMaxHeight];
+  int64_t cum[kMaxHeight + 1];  // prefix sums of the cell counts of the levels
+  int nlev;
+};
+
+// table[l][key] = index, for the levels of the set (thread = one cell)
+__global__ void table_scatter_kernel(TableSet t) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= t.cum[t.nlev]) return;
+  int l = 0;
+  while (g >= t.cum[l + 1]) ++l;
+  const int64_t i = g - t.cum[l];
+  t.table[l][t.keys[l][i]] = int(i);
 }
 
 // ------------------------------------------------------------ near lists
@@ -372,33 +445,53 @@ __global__ void near_kernel(LevelDev leaves, const int* __restrict__ leaf_start,
 }
 
 // ------------------------------------------------------------ M2L tiles
-__global__ void parity_count_kernel(const uint64_t* __restrict__ keys,
-                                    int64_t nc, int* __restrict__ counts) {
-  __shared__ int h[8];
-  if (threadIdx.x < 8) h[threadIdx.x] = 0;
+struct CellLevels {
+  const uint64_t* keys[kMaxHeight];
+  int64_t off[kMaxHeight + 1];  // global id of each level's first cell
+};
+
+// Cells of levels >= 2 (global ids g from off[2]): sort key (level - 2, child
+// parity) for the M2L target order, the gid as value, and per-(level, parity)
+// counts.
+__global__ __launch_bounds__(256) void parity_keys_kernel(CellLevels c, int h,
+                                                          uint64_t* __restrict__ key,
+                                                          int* __restrict__ val,
+                                                          int* __restrict__ counts) {
+  __shared__ int hist[8 * kMaxHeight];
+  for (int e = threadIdx.x; e < 8 * kMaxHeight; e += blockDim.x) hist[e] = 0;
   __syncthreads();
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < nc) atomicAdd(&h[int(keys[i] & 7u)], 1);
+  const int64_t m = c.off[h] - c.off[2];
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < m) {
+    const int64_t g = c.off[2] + j;
+    int l = 2;
+    while (g >= c.off[l + 1]) ++l;
+    const int par = int(c.keys[l][g - c.off[l]] & 7u);
+    key[j] = uint64_t((l - 2) << 3 | par);
+    val[j] = int(g);
+    atomicAdd(&hist[8 * l + par], 1);
+  }
   __syncthreads();
-  if (threadIdx.x < 8 && h[threadIdx.x]) atomicAdd(&counts[threadIdx.x], h[threadIdx.x]);
+  for (int e = threadIdx.x; e < 8 * kMaxHeight; e += blockDim.x)
+    if (hist[e]) atomicAdd(&counts[e], hist[e]);
 }
 
-__global__ void iota_kernel(int* __restrict__ p, int64_t n, int base) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = base + int(i);
-}
+// One workgroup of four wavefronts per tile.  Lane j of every wavefront owns
+// target j; wavefront w looks up the source cells of the slots w, w+4, ...
+// (zero row if absent) and marks the slots with at least one source; then
+// the first thread lists the marked slots in slot order.
+constexpr int kTileThreads = 256;
 
-// One wavefront per tile.  Lane j owns target j; for each of the parity's
-// 189 offsets it finds the source cell (zero row if absent); slots with at
-// least one source are listed in order.
-__global__ __launch_bounds__(64) void tile_src_kernel(
+__global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
     const M2LTile* __restrict__ tiles, const int* __restrict__ tgt,
     const LevelDev* __restrict__ levels, const int64_t* __restrict__ lev_off,
     const signed char* __restrict__ slot_t,  // [8][189][3]
     int zero_row, int* __restrict__ tile_src, unsigned char* __restrict__ act,
     int* __restrict__ nact, unsigned long long* __restrict__ pairs_level,
-    const int* __restrict__ slot_kid, unsigned long long* __restrict__ pairs_kid) {
-  const int tile = blockIdx.x, j = threadIdx.x;
+    const int* __restrict__ slot_kid, unsigned long long* __restrict__ pairs_kid,
+    unsigned long long* __restrict__ active_total) {
+  __shared__ int npair[kSlots];
+  const int tile = blockIdx.x, j = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const M2LTile T = tiles[tile];
   const LevelDev L = levels[T.level];
   int c[3] = {0, 0, 0};
@@ -407,28 +500,29 @@ __global__ __launch_bounds__(64) void tile_src_kernel(
     const int local = tgt[T.first + j] - int(lev_off[T.level]);
     demorton3(L.keys[local], L.bits, c);
   }
-  int na = 0;
-  unsigned long long npairs = 0;
   int* out = tile_src + int64_t(tile) * kSlots * kTileN;
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = wave; s < kSlots; s += kTileThreads / 64) {
     const signed char* t = slot_t + (T.parity * kSlots + s) * 3;
     int b = -1;
     if (have) b = level_find_xyz(L, c[0] + t[0], c[1] + t[1], c[2] + t[2]);
     out[s * kTileN + j] = b >= 0 ? b + int(lev_off[T.level]) : zero_row;
     const uint64_t m = __ballot(b >= 0);
-    if (m) {
-      if (j == 0) {
-        act[int64_t(tile) * kSlots + na] = (unsigned char)s;
-        atomicAdd(&pairs_kid[slot_kid[T.parity * kSlots + s]],
-                  (unsigned long long)__popcll(m));
-      }
-      ++na;
-      npairs += __popcll(m);
-    }
+    if (j == 0) npair[s] = __popcll(m);
   }
-  if (j == 0) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int na = 0;
+    unsigned long long np = 0;
+    for (int s = 0; s < kSlots; ++s) {
+      const int k = npair[s];
+      if (!k) continue;
+      act[int64_t(tile) * kSlots + na++] = (unsigned char)s;
+      atomicAdd(&pairs_kid[slot_kid[T.parity * kSlots + s]], (unsigned long long)k);
+      np += k;
+    }
     nact[tile] = na;
-    atomicAdd(&pairs_level[T.level], npairs);
+    atomicAdd(&pairs_level[T.level], np);
+    atomicAdd(active_total, (unsigned long long)na);
   }
 }
 
@@ -533,19 +627,45 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   lev[h - 1].keys = static_cast<uint64_t*>(p->alloc(sizeof(uint64_t) * nl));
   FMM_HIP_CHECK(hipMemcpyAsync(lev[h - 1].keys, lk, sizeof(uint64_t) * nl,
                                hipMemcpyDeviceToDevice, s));
-  for (int l = h - 2; l >= 0; --l) {
-    const int64_t m = lev[l + 1].ncell;
-    lev[l + 1].parent = static_cast<int*>(p->alloc(sizeof(int) * m));
-    int* cs = static_cast<int*>(talloc(sizeof(int) * (m + 1)));
-    uint64_t* uk = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * m));
-    const int64_t c = unique(lev[l + 1].keys, m, 3, uk, cs, lev[l + 1].parent);
-    lev[l].ncell = c;
-    lev[l].keys = static_cast<uint64_t*>(p->alloc(sizeof(uint64_t) * c));
-    lev[l].child_start = static_cast<int*>(p->alloc(sizeof(int) * (c + 1)));
-    FMM_HIP_CHECK(hipMemcpyAsync(lev[l].keys, uk, sizeof(uint64_t) * c,
-                                 hipMemcpyDeviceToDevice, s));
-    FMM_HIP_CHECK(hipMemcpyAsync(lev[l].child_start, cs, sizeof(int) * (c + 1),
-                                 hipMemcpyDeviceToDevice, s));
+  if (h >= 2) {
+    // every coarser level from the leaf keys: flags, one scan, one count
+    // read-back, then keys, child offsets and parents in one pass
+    const int64_t tot = int64_t(h - 1) * nl;
+    int64_t* fl = static_cast<int64_t*>(talloc(sizeof(int64_t) * tot));
+    int64_t* S = static_cast<int64_t*>(talloc(sizeof(int64_t) * tot));
+    int64_t* cnt = static_cast<int64_t*>(talloc(sizeof(int64_t) * kMaxHeight));
+    level_flags_kernel<<<grid_for(nl, 256), 256, 0, s>>>(lk, nl, h, fl);
+    FMM_HIP_CHECK(hipGetLastError());
+    exclusive_scan<int64_t>(fl, S, tot, s, tmp);
+    level_counts_kernel<<<1, 64, 0, s>>>(fl, S, nl, h, cnt);
+    FMM_HIP_CHECK(hipGetLastError());
+    int64_t hcnt[kMaxHeight];
+    FMM_HIP_CHECK(hipMemcpyAsync(hcnt, cnt, sizeof(int64_t) * (h - 1), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    LevelOut out{};
+    // every count first: level l's loop iteration sizes level l+1's parents.
+    // A tree has one root and at most 8x (and at least as many) cells per
+    // level down to the leaves; anything else would make the kernels below
+    // write out of bounds.
+    for (int l = 0; l < h - 1; ++l) {
+      const int64_t below = l + 1 < h - 1 ? hcnt[l + 1] : nl;
+      if (hcnt[l] < 1 || hcnt[l] > below || (l == 0 && hcnt[l] != 1))
+        throw FmmError{FMM_ERR_HIP, "inconsistent octree level counts"};
+      lev[l].ncell = hcnt[l];
+    }
+    for (int l = 0; l < h - 1; ++l) {
+      lev[l].keys = static_cast<uint64_t*>(p->alloc(sizeof(uint64_t) * hcnt[l]));
+      lev[l].child_start = static_cast<int*>(p->alloc(sizeof(int) * (hcnt[l] + 1)));
+      lev[l + 1].parent = static_cast<int*>(p->alloc(sizeof(int) * lev[l + 1].ncell));
+      out.keys[l] = lev[l].keys;
+      out.child_start[l] = lev[l].child_start;
+      out.parent[l + 1] = lev[l + 1].parent;
+    }
+    level_emit_kernel<<<dim3(grid_for(nl, 256), unsigned(h - 1)), 256, 0, s>>>(lk, nl, h, fl, S,
+                                                                               out);
+    FMM_HIP_CHECK(hipGetLastError());
+    level_ends_kernel<<<1, 64, 0, s>>>(out, cnt, h, nl);
+    FMM_HIP_CHECK(hipGetLastError());
   }
   int64_t off = 0;
   for (int l = 0; l < h; ++l) {
@@ -555,23 +675,34 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   p->ncell_total = off;
   if (off >= (int64_t(1) << 31) - 1) throw FmmError{FMM_ERR_ARG, "too many cells"};
 
-  // dense lookup tables for levels with at most 2^24 key slots
+  // dense lookup tables for levels with at most 2^24 key slots, one block
   LevelDev ldev[kMaxHeight];
+  TableSet ts{};
+  int64_t tslots = 0;
   for (int l = 0; l < h; ++l) {
     ldev[l] = {lev[l].keys, nullptr, int(lev[l].ncell), l};
-    if (3 * l <= 24) {
-      const int64_t slots = int64_t(1) << (3 * l);
-      lev[l].lookup = static_cast<int*>(p->alloc(sizeof(int) * slots));
-      fill_int_kernel<<<grid_for(slots, 256), 256, 0, s>>>(lev[l].lookup, slots, -1);
-      table_scatter_kernel<<<grid_for(lev[l].ncell, 256), 256, 0, s>>>(
-          lev[l].keys, lev[l].ncell, lev[l].lookup);
-      FMM_HIP_CHECK(hipGetLastError());
-      ldev[l].table = lev[l].lookup;
-    }
+    if (3 * l <= 24) tslots += int64_t(1) << (3 * l);
+  }
+  int* tables = static_cast<int*>(p->alloc(sizeof(int) * tslots));
+  FMM_HIP_CHECK(hipMemsetAsync(tables, 0xff, sizeof(int) * tslots, s));  // all -1
+  tslots = 0;
+  for (int l = 0; l < h && 3 * l <= 24; ++l) {
+    lev[l].lookup = tables + tslots;
+    ldev[l].table = lev[l].lookup;
+    ts.keys[ts.nlev] = lev[l].keys;
+    ts.table[ts.nlev] = lev[l].lookup;
+    ts.cum[ts.nlev + 1] = ts.cum[ts.nlev] + lev[l].ncell;
+    ++ts.nlev;
+    tslots += int64_t(1) << (3 * l);
+  }
+  if (ts.cum[ts.nlev] > 0) {
+    table_scatter_kernel<<<grid_for(ts.cum[ts.nlev], 256), 256, 0, s>>>(ts);
+    FMM_HIP_CHECK(hipGetLastError());
   }
 
   // --- near lists ---
-  // counters: far pairs per level, near pairs, then far pairs per operator
+  // counters: far pairs per level, near pairs, active M2L slots, then far
+  // pairs per operator
   const size_t ncount = kMaxHeight + 2 + kOffsets;
   unsigned long long* counters =
       static_cast<unsigned long long*>(talloc(sizeof(unsigned long long) * ncount));
@@ -591,42 +722,36 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
 
   // --- M2L tiles: targets of each level >= 2 grouped by child parity ---
   if (h >= 3) {
-    int64_t ntgt = 0;
-    for (int l = 2; l < h; ++l) ntgt += lev[l].ncell;
+    const int64_t ntgt = p->ncell_total - lev[2].off;
     p->tgt = static_cast<int*>(p->alloc(sizeof(int) * ntgt));
+    // one stable radix pass by (level - 2, parity): within a group the
+    // cells stay in Morton order
+    CellLevels cl{};
+    for (int l = 0; l < h; ++l) {
+      cl.keys[l] = lev[l].keys;
+      cl.off[l] = lev[l].off;
+    }
+    cl.off[h] = p->ncell_total;
+    uint64_t* pk1 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * ntgt));
+    uint64_t* pk2 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * ntgt));
+    int* pv1 = static_cast<int*>(talloc(sizeof(int) * ntgt));
+    int* pv2 = static_cast<int*>(talloc(sizeof(int) * ntgt));
     int* pc = static_cast<int*>(talloc(sizeof(int) * 8 * kMaxHeight));
     FMM_HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(int) * 8 * kMaxHeight, s));
-    for (int l = 2; l < h; ++l)
-      parity_count_kernel<<<grid_for(lev[l].ncell, 256), 256, 0, s>>>(
-          lev[l].keys, lev[l].ncell, pc + 8 * l);
+    parity_keys_kernel<<<grid_for(ntgt, 256), 256, 0, s>>>(cl, h, pk1, pv1, pc);
     FMM_HIP_CHECK(hipGetLastError());
+    int kbits = 3;
+    while ((1 << (kbits - 3)) < h - 2) ++kbits;
+    radix_sort(pk1, pv1, pk2, pv2, ntgt, kbits, s, tmp);
+    FMM_HIP_CHECK(hipMemcpyAsync(p->tgt, pv1, sizeof(int) * ntgt, hipMemcpyDeviceToDevice, s));
     int hpc[8 * kMaxHeight];
     FMM_HIP_CHECK(hipMemcpyAsync(hpc, pc, sizeof(hpc), hipMemcpyDeviceToHost, s));
-    // stable partition by parity = one radix pass over the low 3 key bits
-    int64_t tbase = 0;
-    std::vector<M2LTile> tiles;
-    std::vector<int64_t> tgt_base(h, 0);
-    for (int l = 2; l < h; ++l) {
-      const int64_t m = lev[l].ncell;
-      uint64_t* pk1 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * m));
-      uint64_t* pk2 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * m));
-      int* pv1 = static_cast<int*>(talloc(sizeof(int) * m));
-      int* pv2 = static_cast<int*>(talloc(sizeof(int) * m));
-      FMM_HIP_CHECK(hipMemcpyAsync(pk1, lev[l].keys, sizeof(uint64_t) * m,
-                                   hipMemcpyDeviceToDevice, s));
-      iota_kernel<<<grid_for(m, 256), 256, 0, s>>>(pv1, m, int(lev[l].off));
-      FMM_HIP_CHECK(hipGetLastError());
-      radix_sort(pk1, pv1, pk2, pv2, m, 3, s, tmp);
-      FMM_HIP_CHECK(hipMemcpyAsync(p->tgt + tbase, pv1, sizeof(int) * m,
-                                   hipMemcpyDeviceToDevice, s));
-      tgt_base[l] = tbase;
-      tbase += m;
-    }
     FMM_HIP_CHECK(hipStreamSynchronize(s));
     // finest level first: the largest tiles' work is scheduled before the
     // coarse levels fill in the tail
+    std::vector<M2LTile> tiles;
     for (int l = h - 1; l >= 2; --l) {
-      int64_t start = tgt_base[l];
+      int64_t start = lev[l].off - lev[2].off;
       for (int par = 0; par < 8; ++par) {
         const int c = hpc[8 * l + par];
         for (int k = 0; k < c; k += kTileN)
@@ -650,10 +775,10 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
       FMM_HIP_CHECK(hipMemcpyAsync(ld_d, ldev, sizeof(LevelDev) * kMaxHeight,
                                    hipMemcpyHostToDevice, s));
       FMM_HIP_CHECK(hipMemcpyAsync(off_d, offs_h, sizeof(offs_h), hipMemcpyHostToDevice, s));
-      tile_src_kernel<<<unsigned(p->ntiles), 64, 0, s>>>(
+      tile_src_kernel<<<unsigned(p->ntiles), kTileThreads, 0, s>>>(
           p->tiles, p->tgt, ld_d, off_d, p->ops->slot_t,
           int(p->ncell_total), p->tile_src, p->tile_act, p->tile_nact, counters,
-          p->ops->slot_kid, counters + kMaxHeight + 2);
+          p->ops->slot_kid, counters + kMaxHeight + 2, counters + kMaxHeight + 1);
       FMM_HIP_CHECK(hipGetLastError());
     }
   }
@@ -669,13 +794,7 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     p->far_pairs_level[l] = int64_t(hc[l]);
     p->far_pairs += int64_t(hc[l]);
   }
-  if (p->ntiles > 0) {
-    std::vector<int> na(p->ntiles);
-    FMM_HIP_CHECK(hipMemcpy(na.data(), p->tile_nact, sizeof(int) * p->ntiles,
-                            hipMemcpyDeviceToHost));
-    p->active_slots = 0;
-    for (int v : na) p->active_slots += v;
-  }
+  p->active_slots = int64_t(hc[kMaxHeight + 1]);
 }
 
 }  // namespace fmm
