@@ -57,7 +57,8 @@ enum fmm_precision {
   FMM_MIXED_FP32 = 1,
   /* FMM_FP64 with the compressed M2L of Sec. 2.1.2 ("improved M2L"): each of
    * the 16 canonical operators factorised by one SVD, truncated at singular
-   * values s_k >= eps s_1 (eps from fmm_plan_set_m2l_tolerance, default 1e-8),
+   * values s_k >= eps s_1 (eps from fmm_plan_set_m2l_tolerance; default
+   * 10^-order as in the paper's accuracy setting, at most down to 1e-10),
    * applied as two skinny MFMA products per far offset */
   FMM_FP64_SVD = 2,
   /* FMM_MIXED_FP32 with the compressed M2L in FP32 MFMA (FP64 folding) */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -211,6 +212,10 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
     p->n = n;
     p->height = height;
     p->order = order;
+    // the paper's accuracy setting ties the tolerance to the order,
+    // eps = 10^-order (Sec. 2.1.2, Table 1); below 1e-10 the ranks would
+    // outgrow the compressed kernel's LDS
+    p->m2l_eps = std::pow(10.0, -double(std::min(order, 10)));
     p->ops = fmm::get_opset(order, p->kernel, stream);
     fmm::build_plan(p, positions, stream);
     const int ld = p->ops->ld;

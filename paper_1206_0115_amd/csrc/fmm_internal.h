@@ -131,7 +131,7 @@ struct fmm_plan_s {
   int height = 0, order = 0, precision = FMM_FP64;
   double lo[3] = {0, 0, 0}, L = 1.0;
   const fmm::OpSet* ops = nullptr;
-  double m2l_eps = 1e-8;              // truncation of the compressed M2L
+  double m2l_eps = 1e-8;              // truncation of the compressed M2L (set per order)
   const fmm::SvdOps* svd = nullptr;   // set when the precision mode compresses
 
   // particles

@@ -71,7 +71,11 @@ def test_mixed_compressed_full_size_gate(name, mixed_bound):
     pos, q = inputs.make(kind, n, seed)
     plan = fmm.Plan(dev(pos), h, l)
     p64, f64 = [host(t) for t in plan.evaluate(dev(q))]
-    for mode, gate in (("fp64_svd", 1e-7), ("mixed_svd", mixed_bound)):
+    # the default tolerance is the paper's 10^-order; the FP64 compressed
+    # mode is held to 10 x that
+    eps = plan.svd_info().eps
+    assert eps == pytest.approx(10.0 ** -min(l, 10))
+    for mode, gate in (("fp64_svd", 10 * eps), ("mixed_svd", mixed_bound)):
         plan.set_precision(mode)
         phi, f = [host(t) for t in plan.evaluate(dev(q))]
         e = max(rel(phi, p64), rel(f, f64))
