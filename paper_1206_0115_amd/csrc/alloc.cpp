@@ -8,6 +8,7 @@
 // retried once.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -81,6 +82,23 @@ void dev_free(void* p) {
   g_free.insert({{it->second.device, it->second.size}, p});
   g_cached += it->second.size;
   g_live.erase(it);
+}
+
+// Pinned host staging for the small transfers of plan construction: copies
+// between pinned memory and the device skip the driver's pageable staging.
+// One buffer per thread, grown on demand and kept for the process.
+void* pinned_staging(size_t bytes) {
+  thread_local void* buf = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (buf) FMM_HIP_CHECK(hipHostFree(buf));
+    buf = nullptr;
+    cap = 0;
+    size_t want = std::max<size_t>(bytes, size_t(1) << 16);
+    FMM_HIP_CHECK(hipHostMalloc(&buf, want, hipHostMallocDefault));
+    cap = want;
+  }
+  return buf;
 }
 
 size_t dev_cached_bytes() {

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -310,10 +311,12 @@ static void apply_mode(fmm_plan_s* p, int mode) {
     int have = 0;
     FMM_HIP_CHECK(hipDeviceGetAttribute(&have, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                         p->device));
+    char tol[32];
+    std::snprintf(tol, sizeof(tol), "%g", p->m2l_eps);
     if (need > size_t(have))
       throw fmm::FmmError{FMM_ERR_ARG,
                           "compressed M2L at order " + std::to_string(p->order) +
-                              " and tolerance " + std::to_string(p->m2l_eps) + " keeps rank " +
+                              " and tolerance " + tol + " keeps rank " +
                               std::to_string(sv->rmax_pad) + " and needs " +
                               std::to_string(need) + " B of LDS (device: " +
                               std::to_string(have) +

@@ -54,6 +54,10 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 size_t dev_cached_bytes();
 void dev_trim();
+// The calling thread's pinned host staging buffer, at least `bytes` long.
+// Growing it frees the previous one: callers finish every transfer through
+// it (a stream synchronisation) before asking for more.
+void* pinned_staging(size_t bytes);
 
 // ------------------------------------------------------ operator tables
 // Per-order tables shared by all plans on a device (built once, cached).

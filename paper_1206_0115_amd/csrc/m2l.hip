@@ -670,8 +670,10 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
 
 // Target columns per workgroup of the compressed kernel, 16 * NT, for FP32
 // and FP64.  Fewer columns than the tile's 64 cost operator re-reads (from
-// L2) but free registers for two wavefronts per SIMD; measured on gfx950 at
-// order 7: FP32 best at 32 columns (8.6 ms), FP64 at 16 (11.8 ms).
+// L2) but free registers for two wavefronts per SIMD.  Measured on gfx950
+// at order 7: FP32 best at 32 columns in 8 wavefronts (3 M-tiles each, no
+// spills); FP64 at 16 columns in 4 wavefronts (within 1% of 32 columns in
+// 8, and half the LDS, so order 9 at 1e-9 still fits).
 #ifndef FMM_M2L_SVD_NT_F32
 #define FMM_M2L_SVD_NT_F32 2
 #endif
@@ -692,12 +694,28 @@ static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "N
 #ifndef FMM_M2L_SVD_WAVES_F64
 #define FMM_M2L_SVD_WAVES_F64 2
 #endif
+// Wavefronts per workgroup (4 or 8), FP32 and FP64.  With 8, two wavefronts
+// share each K-group of phase 1 (one per N-tile half) and every wavefront
+// owns half as many output rows, which halves its accumulator registers.
+#ifndef FMM_M2L_SVD_NWV_F32
+#define FMM_M2L_SVD_NWV_F32 8
+#endif
+#ifndef FMM_M2L_SVD_NWV_F64
+#define FMM_M2L_SVD_NWV_F64 4
+#endif
+constexpr int svd_nwv(bool fp32) { return fp32 ? FMM_M2L_SVD_NWV_F32 : FMM_M2L_SVD_NWV_F64; }
+static_assert((svd_nwv(true) == 4 || svd_nwv(true) == 8) &&
+                  (svd_nwv(false) == 4 || svd_nwv(false) == 8),
+              "4 or 8 wavefronts per workgroup");
+static_assert(4 * svd_nt(true) % svd_nwv(true) == 0 && 4 * svd_nt(false) % svd_nwv(false) == 0,
+              "8 wavefronts need at least 2 N-tiles");
 
-// One workgroup = 4 wavefronts = one (tile, M-block, N-group) item, the
+// One workgroup = NWV wavefronts = one (tile, M-block, N-group) item, the
 // N-group being NC = 16 NT of the tile's 64 target columns.  Per far offset:
-//   phase 1  X(rp x NC) = (S V^T)_g W.  Wavefront w takes the K-chunks w,
-//            w+4, ... of the l^3 contraction for every rank tile (two per
-//            pass) and writes its partial sums to its own LDS slab P[w];
+//   phase 1  X(rp x NC) = (S V^T)_g W.  K-group kg = w % 4 takes the
+//            K-chunks kg, kg+4, ... of the l^3 contraction for every rank
+//            tile (two per pass); its NWV/4 wavefronts split the N-tiles.
+//            Partial sums go to the K-group's LDS slab P[kg];
 //   phase 2  Y(l^3 x NC) += U_g X, X read as P[0]+P[1]+P[2]+P[3] (always
 //            in that order, so every wavefront sees the same X and the
 //            result does not depend on timing).  Wavefront w owns MTW
@@ -706,12 +724,13 @@ static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "N
 // the workgroup processes (also across items), so one barrier per offset
 // suffices: a wavefront writes buffer b again only after the barrier of the
 // next offset, which every wavefront reaches after its reads of buffer b.
-template <typename T, int MTW, int NT, bool FOLD>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
-                                                 : FMM_M2L_SVD_WAVES_F64) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
+template <typename T, int MTW, int NT, int NWV, bool FOLD>
+__global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
+                                                      : FMM_M2L_SVD_WAVES_F64) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
                                                          const StepTab* __restrict__ tab) {
   typedef typename Vec4<T>::type T4;
   constexpr int NC = 16 * NT, NG = 4 / NT;
+  constexpr int NTW = NT * 4 / NWV;  // N-tiles per wavefront in phase 1
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* const lds = reinterpret_cast<T*>(lds_raw);
   int buf = 0;
@@ -733,8 +752,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
     const M2LTile tl = J.tiles[tile];
     if (col0 >= tl.count) continue;  // the same for the whole workgroup
     const int MT = J.mt, KC = J.kc, ld = J.ld, XS = J.xs;
-    const int mt0 = (mb * 4 + wave) * MTW;
+    const int mt0 = (mb * NWV + wave) * MTW;
     const int nmt = mt0 < MT ? min(MTW, MT - mt0) : 0;
+    const int kg = wave & 3, jn0 = (wave >> 2) * NTW;
     const T* __restrict__ Wp = FOLD ? reinterpret_cast<const T*>(J.W32)
                                     : reinterpret_cast<const T*>(J.W);
     const T* __restrict__ P1 = FOLD ? reinterpret_cast<const T*>(J.p1_32)
@@ -761,34 +781,34 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
       const int rp = J.svd_rpad[kid], nr = rp >> 4;
       const int64_t off = J.svd_off[kid];
       T* const P = lds + buf * 4 * NC * XS;
-      T* const Pw = P + wave * NC * XS;
+      T* const Pw = P + kg * NC * XS;
       buf ^= 1;
-      // ---- phase 1: this wavefront's share of X, into its slab ----
-      const T* bp[NT];
+      // ---- phase 1: this wavefront's share of X, into its K-group's slab ----
+      const T* bp[NTW];
 #pragma unroll
-      for (int j = 0; j < NT; ++j)
-        bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+      for (int j = 0; j < NTW; ++j)
+        bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * (jn0 + j) + c16]) * ld + 4 * g;
       for (int i0 = 0; i0 < nr; i0 += 2) {
         const int np = min(2, nr - i0);
         const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
-        T4 x[2][NT];
+        T4 x[2][NTW];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) x[0][j] = x[1][j] = T4{0, 0, 0, 0};
-        T4 bv[NT], av[2];
-        if (wave < KC) {
+        for (int j = 0; j < NTW; ++j) x[0][j] = x[1][j] = T4{0, 0, 0, 0};
+        T4 bv[NTW], av[2];
+        if (kg < KC) {
 #pragma unroll
-          for (int j = 0; j < NT; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * wave);
+          for (int j = 0; j < NTW; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * kg);
 #pragma unroll
           for (int i = 0; i < 2; ++i)
-            av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + wave) * 256)
+            av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256)
                            : T4{0, 0, 0, 0};
         }
-        for (int c = wave; c < KC; c += 4) {
-          T4 bn[NT], an[2];
+        for (int c = kg; c < KC; c += 4) {
+          T4 bn[NTW], an[2];
           const bool more = c + 4 < KC;
           if (more) {
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
+            for (int j = 0; j < NTW; ++j)
               bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -800,11 +820,11 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-              for (int j = 0; j < NT; ++j)
+              for (int j = 0; j < NTW; ++j)
                 if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
           if (more) {
 #pragma unroll
-            for (int j = 0; j < NT; ++j) bv[j] = bn[j];
+            for (int j = 0; j < NTW; ++j) bv[j] = bn[j];
 #pragma unroll
             for (int i = 0; i < 2; ++i) av[i] = an[i];
           }
@@ -813,9 +833,9 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < NT; ++j) {
+          for (int j = 0; j < NTW; ++j) {
             if (i >= np) continue;
-            T* xrow = Pw + (16 * j + c16) * XS + 16 * (i0 + i);
+            T* xrow = Pw + (16 * (jn0 + j) + c16) * XS + 16 * (i0 + i);
             if (f64) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) xrow[4 * r + g] = x[i][j][r];
@@ -906,16 +926,17 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 }
 
 // M-tiles per wavefront for the compressed kernel: the whole output in one
-// M-block when it fits 4 x 6 tiles (phase 1 then runs once per N-group).
-int m2l_svd_mtw(int mt) {
+// M-block when it fits NWV x 6 tiles (phase 1 then runs once per N-group).
+static int m2l_svd_mtw(int mt, bool fp32) {
+  const int nw = svd_nwv(fp32);
   for (int w = 1; w <= 6; ++w)
-    if (4 * w >= mt) return w;
+    if (nw * w >= mt) return w;
   return 6;
 }
 
 int m2l_svd_nmb(int mt, bool fp32) {
-  const int w = m2l_svd_mtw(mt);
-  return (mt + 4 * w - 1) / (4 * w) * (4 / svd_nt(fp32));
+  const int w = m2l_svd_mtw(mt, fp32), nw = svd_nwv(fp32);
+  return (mt + nw * w - 1) / (nw * w) * (4 / svd_nt(fp32));
 }
 
 // Slab row stride: the padded rank plus 16 bytes, so that consecutive target
@@ -929,21 +950,21 @@ size_t m2l_svd_lds_bytes(int xs, bool fp32) {
 template <typename T, bool FOLD>
 static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid,
                            size_t lds, hipStream_t s) {
-  constexpr int NT = svd_nt(sizeof(T) == 4);
+  constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
   switch (mtw) {
-    case 1: m2l_svd_kernel<T, 1, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 2: m2l_svd_kernel<T, 2, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 3: m2l_svd_kernel<T, 3, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 4: m2l_svd_kernel<T, 4, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    case 5: m2l_svd_kernel<T, 5, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
-    default: m2l_svd_kernel<T, 6, NT, FOLD><<<grid, 256, lds, s>>>(jobs, tab); break;
+    case 1: m2l_svd_kernel<T, 1, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 2: m2l_svd_kernel<T, 2, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 3: m2l_svd_kernel<T, 3, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 4: m2l_svd_kernel<T, 4, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 5: m2l_svd_kernel<T, 5, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    default: m2l_svd_kernel<T, 6, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
   }
 }
 
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
                          int xs, hipStream_t s) {
   const int l3 = order * order * order;
-  const int mtw = m2l_svd_mtw((l3 + 15) / 16);
+  const int mtw = m2l_svd_mtw((l3 + 15) / 16, fp32);
   const size_t lds = m2l_svd_lds_bytes(xs, fp32);
   if (fp32)
     launch_svd_mtw<float, true>(mtw, jobs, tab, grid, lds, s);

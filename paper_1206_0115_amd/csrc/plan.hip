@@ -153,15 +153,24 @@ __global__ __launch_bounds__(256) void bbox_final_kernel(const double* __restric
 // -------------------------------------------------------------- Morton keys
 // k_d = min(floor((x_d - lo_d) / L * 2^(h-1)), 2^(h-1) - 1): IEEE divide, an
 // exact scaling by a power of two and floor -- no contraction is possible.
+// The root box comes from the device (per-axis min in box[0..2], max in
+// box[3..5]); the cube side L = max extent (1 if zero) is formed here in the
+// same FP64 operations as on the host.
+__device__ __host__ inline double root_side(const double* box) {
+  double L = 0.0;
+  for (int d = 0; d < 3; ++d) L = fmax(L, box[3 + d] - box[d]);
+  return L == 0.0 ? 1.0 : L;
+}
+
 __global__ void keys_kernel(const double* __restrict__ pos, int64_t n,
-                            double lo0, double lo1, double lo2, double L,
-                            int bits, uint64_t* __restrict__ keys,
-                            int* __restrict__ idx) {
+                            const double* __restrict__ box, int bits,
+                            uint64_t* __restrict__ keys, int* __restrict__ idx) {
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double side = double(int64_t(1) << bits);
   const int64_t kmax = (int64_t(1) << bits) - 1;
-  const double lo[3] = {lo0, lo1, lo2};
+  const double lo[3] = {box[0], box[1], box[2]};
+  const double L = root_side(box);
   uint32_t k3[3];
   for (int d = 0; d < 3; ++d) {
     double u = (pos[3 * i + d] - lo[d]) / L;
@@ -476,11 +485,11 @@ __global__ __launch_bounds__(256) void parity_keys_kernel(CellLevels c, int h,
     if (hist[e]) atomicAdd(&counts[e], hist[e]);
 }
 
-// One workgroup of four wavefronts per tile.  Lane j of every wavefront owns
-// target j; wavefront w looks up the source cells of the slots w, w+4, ...
+// One workgroup of eight wavefronts per tile.  Lane j of every wavefront owns
+// target j; wavefront w looks up the source cells of the slots w, w+8, ...
 // (zero row if absent) and marks the slots with at least one source; then
 // the first thread lists the marked slots in slot order.
-constexpr int kTileThreads = 256;
+constexpr int kTileThreads = 512;
 
 __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
     const M2LTile* __restrict__ tiles, const int* __restrict__ tgt,
@@ -559,27 +568,20 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   FMM_HIP_CHECK(hipGetLastError());
   bbox_final_kernel<<<1, 256, 0, s>>>(part, nb, box);
   FMM_HIP_CHECK(hipGetLastError());
-  double hb[6];
-  int hbad = 0;
-  FMM_HIP_CHECK(hipMemcpyAsync(hb, box, sizeof(hb), hipMemcpyDeviceToHost, s));
-  FMM_HIP_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-  FMM_HIP_CHECK(hipStreamSynchronize(s));
-  if (hbad) throw FmmError{FMM_ERR_ARG, "positions contain NaN or Inf"};
-  double L = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    p->lo[d] = hb[d];
-    L = std::max(L, hb[3 + d] - hb[d]);
-  }
-  if (L == 0.0) L = 1.0;
-  p->L = L;
+  // the box stays on the device until the leaf count comes back: keys are
+  // formed from it there (non-finite positions give clamped keys, and the
+  // plan is rejected at that first read-back)
+  // pinned staging: [0] box (6 doubles), [6] bad flag and leaf count
+  char* stage = static_cast<char*>(pinned_staging(4096));
+  double* hb = reinterpret_cast<double*>(stage);
+  int* hcount = reinterpret_cast<int*>(stage + 64);
 
   // --- keys and the stable sort ---
   uint64_t* k1 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * n));
   uint64_t* k2 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * n));
   int* v1 = static_cast<int*>(talloc(sizeof(int) * n));
   int* v2 = static_cast<int*>(talloc(sizeof(int) * n));
-  keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(pos, n, p->lo[0], p->lo[1], p->lo[2], L,
-                                               bits, k1, v1);
+  keys_kernel<<<grid_for(n, 256), 256, 0, s>>>(pos, n, box, bits, k1, v1);
   FMM_HIP_CHECK(hipGetLastError());
   radix_sort(k1, v1, k2, v2, n, 3 * bits, s, tmp);
 
@@ -593,32 +595,32 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   gather_pos_kernel<<<grid_for(n, 256), 256, 0, s>>>(pos, p->perm, n, p->px, p->py, p->pz);
   FMM_HIP_CHECK(hipGetLastError());
 
-  // --- leaves and coarser levels ---
+  // --- leaves: the unique keys of the sorted particles ---
   int* flags = static_cast<int*>(talloc(sizeof(int) * n));
   int* scn = static_cast<int*>(talloc(sizeof(int) * n));
   int* cnt_d = static_cast<int*>(talloc(sizeof(int) * 4));
-  auto unique = [&](const uint64_t* keys, int64_t m, int shift, uint64_t* ukeys,
-                    int* first, int* seg) -> int64_t {
-    seg_flags_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys, m, shift, flags);
-    FMM_HIP_CHECK(hipGetLastError());
-    exclusive_scan<int>(flags, scn, m, s, tmp);
-    seg_emit_kernel<<<grid_for(m, 256), 256, 0, s>>>(keys, m, shift, flags, scn, ukeys,
-                                                     first, seg);
-    FMM_HIP_CHECK(hipGetLastError());
-    seg_count_kernel<<<1, 64, 0, s>>>(flags, scn, m, cnt_d);
-    FMM_HIP_CHECK(hipGetLastError());
-    int c = 0;
-    FMM_HIP_CHECK(hipMemcpyAsync(&c, cnt_d, sizeof(int), hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
-    set_int_kernel<<<1, 64, 0, s>>>(first + c, int(m));
-    FMM_HIP_CHECK(hipGetLastError());
-    return c;
-  };
-
   uint64_t* lk = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * n));
   int* ls = static_cast<int*>(talloc(sizeof(int) * (n + 1)));
-  p->nleaf = unique(p->keys, n, 0, lk, ls, nullptr);
+  seg_flags_kernel<<<grid_for(n, 256), 256, 0, s>>>(p->keys, n, 0, flags);
+  FMM_HIP_CHECK(hipGetLastError());
+  exclusive_scan<int>(flags, scn, n, s, tmp);
+  seg_emit_kernel<<<grid_for(n, 256), 256, 0, s>>>(p->keys, n, 0, flags, scn, lk, ls, nullptr);
+  FMM_HIP_CHECK(hipGetLastError());
+  seg_count_kernel<<<1, 64, 0, s>>>(flags, scn, n, cnt_d);
+  FMM_HIP_CHECK(hipGetLastError());
+  // first read-back: the root box, the non-finite flag and the leaf count
+  FMM_HIP_CHECK(hipMemcpyAsync(hb, box, sizeof(double) * 6, hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipMemcpyAsync(hcount, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipMemcpyAsync(hcount + 1, cnt_d, sizeof(int), hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipStreamSynchronize(s));
+  if (hcount[0]) throw FmmError{FMM_ERR_ARG, "positions contain NaN or Inf"};
+  for (int d = 0; d < 3; ++d) p->lo[d] = hb[d];
+  const double L = root_side(hb);
+  p->L = L;
+  p->nleaf = hcount[1];
   const int64_t nl = p->nleaf;
+  set_int_kernel<<<1, 64, 0, s>>>(ls + nl, int(n));
+  FMM_HIP_CHECK(hipGetLastError());
   p->leaf_start = static_cast<int*>(p->alloc(sizeof(int) * (nl + 1)));
   FMM_HIP_CHECK(hipMemcpyAsync(p->leaf_start, ls, sizeof(int) * (nl + 1),
                                hipMemcpyDeviceToDevice, s));
@@ -639,7 +641,7 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     exclusive_scan<int64_t>(fl, S, tot, s, tmp);
     level_counts_kernel<<<1, 64, 0, s>>>(fl, S, nl, h, cnt);
     FMM_HIP_CHECK(hipGetLastError());
-    int64_t hcnt[kMaxHeight];
+    int64_t* hcnt = reinterpret_cast<int64_t*>(stage + 128);  // pinned
     FMM_HIP_CHECK(hipMemcpyAsync(hcnt, cnt, sizeof(int64_t) * (h - 1), hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipStreamSynchronize(s));
     LevelOut out{};
@@ -744,8 +746,8 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     while ((1 << (kbits - 3)) < h - 2) ++kbits;
     radix_sort(pk1, pv1, pk2, pv2, ntgt, kbits, s, tmp);
     FMM_HIP_CHECK(hipMemcpyAsync(p->tgt, pv1, sizeof(int) * ntgt, hipMemcpyDeviceToDevice, s));
-    int hpc[8 * kMaxHeight];
-    FMM_HIP_CHECK(hipMemcpyAsync(hpc, pc, sizeof(hpc), hipMemcpyDeviceToHost, s));
+    int* hpc = reinterpret_cast<int*>(stage + 512);  // pinned, 8 x kMaxHeight
+    FMM_HIP_CHECK(hipMemcpyAsync(hpc, pc, sizeof(int) * 8 * kMaxHeight, hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipStreamSynchronize(s));
     // finest level first: the largest tiles' work is scheduled before the
     // coarse levels fill in the tail
@@ -762,19 +764,32 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     p->ntiles = int64_t(tiles.size());
     p->tiles_host = tiles;
     if (p->ntiles > 0) {
-      p->tiles = static_cast<M2LTile*>(p->alloc(sizeof(M2LTile) * tiles.size()));
-      FMM_HIP_CHECK(hipMemcpyAsync(p->tiles, tiles.data(), sizeof(M2LTile) * tiles.size(),
-                                   hipMemcpyHostToDevice, s));
+      // every earlier transfer through the staging buffer has completed (the
+      // synchronisation above), so it may grow here; layout from 4 KiB on:
+      // level tables, level offsets, then the tiles
+      const size_t tbytes = sizeof(M2LTile) * tiles.size();
+      stage = static_cast<char*>(pinned_staging(4096 + 2048 + tbytes));
+      LevelDev* hld = reinterpret_cast<LevelDev*>(stage + 4096);
+      int64_t* hoff = reinterpret_cast<int64_t*>(stage + 4096 + 1024);
+      M2LTile* htiles = reinterpret_cast<M2LTile*>(stage + 4096 + 2048);
+      static_assert(sizeof(LevelDev) * kMaxHeight <= 1024 && sizeof(int64_t) * kMaxHeight <= 1024,
+                    "staging layout");
+      std::memcpy(htiles, tiles.data(), tbytes);
+      p->tiles = static_cast<M2LTile*>(p->alloc(tbytes));
+      FMM_HIP_CHECK(hipMemcpyAsync(p->tiles, htiles, tbytes, hipMemcpyHostToDevice, s));
       p->tile_src = static_cast<int*>(p->alloc(sizeof(int) * size_t(p->ntiles) * kSlots * kTileN));
       p->tile_act = static_cast<unsigned char*>(p->alloc(size_t(p->ntiles) * kSlots));
       p->tile_nact = static_cast<int*>(p->alloc(sizeof(int) * p->ntiles));
       LevelDev* ld_d = static_cast<LevelDev*>(talloc(sizeof(LevelDev) * kMaxHeight));
       int64_t* off_d = static_cast<int64_t*>(talloc(sizeof(int64_t) * kMaxHeight));
-      int64_t offs_h[kMaxHeight];
-      for (int l = 0; l < kMaxHeight; ++l) offs_h[l] = l < h ? lev[l].off : 0;
-      FMM_HIP_CHECK(hipMemcpyAsync(ld_d, ldev, sizeof(LevelDev) * kMaxHeight,
+      for (int l = 0; l < kMaxHeight; ++l) {
+        hoff[l] = l < h ? lev[l].off : 0;
+        hld[l] = ldev[l];
+      }
+      FMM_HIP_CHECK(hipMemcpyAsync(ld_d, hld, sizeof(LevelDev) * kMaxHeight,
                                    hipMemcpyHostToDevice, s));
-      FMM_HIP_CHECK(hipMemcpyAsync(off_d, offs_h, sizeof(offs_h), hipMemcpyHostToDevice, s));
+      FMM_HIP_CHECK(hipMemcpyAsync(off_d, hoff, sizeof(int64_t) * kMaxHeight,
+                                   hipMemcpyHostToDevice, s));
       tile_src_kernel<<<unsigned(p->ntiles), kTileThreads, 0, s>>>(
           p->tiles, p->tgt, ld_d, off_d, p->ops->slot_t,
           int(p->ncell_total), p->tile_src, p->tile_act, p->tile_nact, counters,
@@ -784,8 +799,12 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   }
 
   // --- statistics ---
-  unsigned long long hc[kMaxHeight + 2 + kOffsets];
-  FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(hc), hipMemcpyDeviceToHost, s));
+  // statistics in the staging buffer's first 4 KiB (the box and counts
+  // there are no longer needed)
+  static_assert(sizeof(unsigned long long) * (kMaxHeight + 2 + kOffsets) <= 4096, "staging");
+  unsigned long long* hc = reinterpret_cast<unsigned long long*>(stage);
+  FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(unsigned long long) * (kMaxHeight + 2 + kOffsets),
+                               hipMemcpyDeviceToHost, s));
   FMM_HIP_CHECK(hipStreamSynchronize(s));
   for (int k = 0; k < kOffsets; ++k) p->pairs_by_kid[k] = int64_t(hc[kMaxHeight + 2 + k]);
   p->near_pairs = int64_t(hc[kMaxHeight]);
