@@ -82,8 +82,17 @@ def cpu_baseline(kind, n, h, l, seed, budget_s):
         n_s, h_s = n, h
         dt = run(n_s, h_s)
         what = "the full workload"
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n_s / dt, "unit": "particles/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model,
             "sample": f"{what}: {kind} N={n_s} height={h_s} order={l} seed={seed}, "
                       f"plan+evaluate in {dt:.1f}s"}
 
@@ -265,7 +274,7 @@ def main():
                     help="the program to run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/m2l_traffic.json from the two counter CSVs")
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-precision", default="mixed_svd",
                     choices=["fp64", "mixed", "fp64_svd", "mixed_svd"])

@@ -683,9 +683,20 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
 constexpr int svd_nt(bool fp32) { return fp32 ? FMM_M2L_SVD_NT_F32 : FMM_M2L_SVD_NT_F64; }
 static_assert(svd_nt(true) == 1 || svd_nt(true) == 2 || svd_nt(true) == 4, "NT");
 static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "NT");
-// Whether phase 2 loads its U fragments one rank chunk ahead.
-#ifndef FMM_M2L_SVD_P2_PREFETCH
-#define FMM_M2L_SVD_P2_PREFETCH 0
+// Whether phase 2 loads its U fragments one rank chunk ahead (FP32, FP64).
+#ifndef FMM_M2L_SVD_P2_PREFETCH_F32
+#define FMM_M2L_SVD_P2_PREFETCH_F32 0
+#endif
+#ifndef FMM_M2L_SVD_P2_PREFETCH_F64
+#define FMM_M2L_SVD_P2_PREFETCH_F64 0
+#endif
+// Rank tiles per pass of phase 1 over the l^3 contraction (each pass reads
+// its share of the gathered multipoles once), FP32 and FP64.
+#ifndef FMM_M2L_SVD_RPASS_F32
+#define FMM_M2L_SVD_RPASS_F32 2
+#endif
+#ifndef FMM_M2L_SVD_RPASS_F64
+#define FMM_M2L_SVD_RPASS_F64 2
 #endif
 // Wavefronts per SIMD the register allocation must allow, FP32 and FP64.
 #ifndef FMM_M2L_SVD_WAVES_F32
@@ -731,6 +742,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
   typedef typename Vec4<T>::type T4;
   constexpr int NC = 16 * NT, NG = 4 / NT;
   constexpr int NTW = NT * 4 / NWV;  // N-tiles per wavefront in phase 1
+  constexpr int kRP = sizeof(T) == 4 ? FMM_M2L_SVD_RPASS_F32 : FMM_M2L_SVD_RPASS_F64;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* const lds = reinterpret_cast<T*>(lds_raw);
   int buf = 0;
@@ -788,37 +800,39 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #pragma unroll
       for (int j = 0; j < NTW; ++j)
         bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * (jn0 + j) + c16]) * ld + 4 * g;
-      for (int i0 = 0; i0 < nr; i0 += 2) {
-        const int np = min(2, nr - i0);
+      for (int i0 = 0; i0 < nr; i0 += kRP) {
+        const int np = min(kRP, nr - i0);
         const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
-        T4 x[2][NTW];
+        T4 x[kRP][NTW];
 #pragma unroll
-        for (int j = 0; j < NTW; ++j) x[0][j] = x[1][j] = T4{0, 0, 0, 0};
-        T4 bv[NTW], av[2];
+        for (int i = 0; i < kRP; ++i)
+#pragma unroll
+          for (int j = 0; j < NTW; ++j) x[i][j] = T4{0, 0, 0, 0};
+        T4 bv[NTW], av[kRP];
         if (kg < KC) {
 #pragma unroll
           for (int j = 0; j < NTW; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * kg);
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < kRP; ++i)
             av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256)
                            : T4{0, 0, 0, 0};
         }
         for (int c = kg; c < KC; c += 4) {
-          T4 bn[NTW], an[2];
+          T4 bn[NTW], an[kRP];
           const bool more = c + 4 < KC;
           if (more) {
 #pragma unroll
             for (int j = 0; j < NTW; ++j)
               bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < kRP; ++i)
               an[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256)
                              : T4{0, 0, 0, 0};
           }
 #pragma unroll
           for (int st = 0; st < 4; ++st)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < kRP; ++i)
 #pragma unroll
               for (int j = 0; j < NTW; ++j)
                 if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
@@ -826,12 +840,12 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #pragma unroll
             for (int j = 0; j < NTW; ++j) bv[j] = bn[j];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = an[i];
+            for (int i = 0; i < kRP; ++i) av[i] = an[i];
           }
         }
         // D rows: FP32 item r -> row 4g + r, FP64 item r -> row 4r + g
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < kRP; ++i)
 #pragma unroll
           for (int j = 0; j < NTW; ++j) {
             if (i >= np) continue;
@@ -848,7 +862,8 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
       // ---- phase 2: Loc rows of this wavefront's M-tiles ----
       if (nmt > 0) {
         const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
-        constexpr bool kPre = FMM_M2L_SVD_P2_PREFETCH;
+        constexpr bool kPre = sizeof(T) == 4 ? FMM_M2L_SVD_P2_PREFETCH_F32
+                                             : FMM_M2L_SVD_P2_PREFETCH_F64;
         T4 av[MTW];
         if (kPre) {
 #pragma unroll
