@@ -99,3 +99,18 @@ def test_tolerance_rejects_bad_values():
     for bad in (0.0, 1.0, -1e-3, float("nan")):
         with pytest.raises(fmm.FMMError):
             plan.set_m2l_tolerance(bad)
+
+
+def test_tolerance_beyond_lds_is_rejected_and_rolled_back():
+    # order 9 at 1e-14 keeps ranks whose slabs exceed the 160 KiB of LDS per
+    # workgroup: the call fails, the plan keeps its tolerance and results
+    pos, q = inputs.uniform_cube(3000, 52)
+    plan = fmm.Plan(dev(pos), 3, 9, "mixed_svd")
+    ref = [host(t) for t in plan.evaluate(dev(q))]
+    eps0 = plan.svd_info().eps
+    with pytest.raises(fmm.FMMError) as err:
+        plan.set_m2l_tolerance(1e-14)
+    assert "LDS" in str(err.value)
+    assert plan.svd_info().eps == eps0
+    again = [host(t) for t in plan.evaluate(dev(q))]
+    assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
