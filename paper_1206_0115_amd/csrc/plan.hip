@@ -407,11 +407,6 @@ __global__ void rel_coords_kernel(const double* __restrict__ px,
 }
 
 // ---------------------------------------------------------- lookup tables
-__global__ void fill_int_kernel(int* __restrict__ p, int64_t n, int v) {
-  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 struct TableSet {
   const uint64_t* keys[kMaxHeight];
   int* table[kMaxHeight];
