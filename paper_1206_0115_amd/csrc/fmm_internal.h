@@ -183,6 +183,7 @@ struct fmm_plan_s {
   int kernel = FMM_KERNEL_INV_R;   // exponent p of the kernel |x - y|^-p
   int64_t w64_rows = 0;            // rows allocated in W (all cells + 1, or levels < h-1)
   bool w32_leaf = false;           // mixed modes: leaf multipoles only in W32
+  int m2l_fold = 0;                // compressed FP32 fold interval (0: by order)
   hipStream_t side = nullptr;      // the near-field branch of the forked schedule
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool in_flight = false;

@@ -40,6 +40,7 @@ struct JobDev {
   int n, nleaf, height, order, ld, mt, kc, nmb, ntiles, has_far;
   int kernel;  // p of the kernel |x - y|^-p (1 or 2)
   int w32_leaf;  // leaf multipoles live in W32 only (W holds levels < h-1)
+  int fold_every;  // compressed FP32 M2L: far offsets between FP64 folds
   LeafGeom geo;
   double* W;
   float* W32;

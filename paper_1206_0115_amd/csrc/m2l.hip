@@ -698,12 +698,16 @@ static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "N
 #ifndef FMM_M2L_SVD_RPASS_F64
 #define FMM_M2L_SVD_RPASS_F64 2
 #endif
-// FP32 mode: far offsets accumulated in FP32 between two folds into the
-// FP64 sums (1 = fold after every offset).  Measured at order 7: folding
-// every 4 offsets saves 1.5% of the launch and raises the error against
-// FP64 from 2.3e-7 to 2.9e-7, so the default folds every offset.
-#ifndef FMM_M2L_SVD_FOLD_EVERY
-#define FMM_M2L_SVD_FOLD_EVERY 1
+// FP32 mode: where the FP32 accumulators are folded into FP64 sums, every
+// J.fold_every far offsets (the plan's fold interval):
+//   0  nowhere (FP32 across all far offsets)
+//   1  FP64 registers (acc64)
+//   2  the item's own FP64 rows of the local expansions in global memory
+// Measured at order 7 (fold every 8): mode 2 runs in 5.5 ms where mode 1
+// runs in 8.0 ms, because without the FP64 registers two 4-wavefront
+// workgroups fit per CU without spills.
+#ifndef FMM_M2L_SVD_F32_FOLD_MODE
+#define FMM_M2L_SVD_F32_FOLD_MODE 2
 #endif
 // Wavefronts per SIMD the register allocation must allow, FP32 and FP64.
 #ifndef FMM_M2L_SVD_WAVES_F32
@@ -716,7 +720,7 @@ static_assert(svd_nt(false) == 1 || svd_nt(false) == 2 || svd_nt(false) == 4, "N
 // share each K-group of phase 1 (one per N-tile half) and every wavefront
 // owns half as many output rows, which halves its accumulator registers.
 #ifndef FMM_M2L_SVD_NWV_F32
-#define FMM_M2L_SVD_NWV_F32 8
+#define FMM_M2L_SVD_NWV_F32 4
 #endif
 #ifndef FMM_M2L_SVD_NWV_F64
 #define FMM_M2L_SVD_NWV_F64 4
@@ -742,11 +746,12 @@ static_assert(4 * svd_nt(true) % svd_nwv(true) == 0 && 4 * svd_nt(false) % svd_n
 // the workgroup processes (also across items), so one barrier per offset
 // suffices: a wavefront writes buffer b again only after the barrier of the
 // next offset, which every wavefront reaches after its reads of buffer b.
-template <typename T, int MTW, int NT, int NWV, bool FOLD>
+template <typename T, int MTW, int NT, int NWV, int FM>
 __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
                                                       : FMM_M2L_SVD_WAVES_F64) void m2l_svd_kernel(const JobDev* __restrict__ jobs,
                                                          const StepTab* __restrict__ tab) {
   typedef typename Vec4<T>::type T4;
+  constexpr bool FOLD = FM == 1;  // FP64 register sums
   constexpr int NC = 16 * NT, NG = 4 / NT;
   constexpr int NTW = NT * 4 / NWV;  // N-tiles per wavefront in phase 1
   constexpr int kRP = sizeof(T) == 4 ? FMM_M2L_SVD_RPASS_F32 : FMM_M2L_SVD_RPASS_F64;
@@ -774,12 +779,13 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
     const int mt0 = (mb * NWV + wave) * MTW;
     const int nmt = mt0 < MT ? min(MTW, MT - mt0) : 0;
     const int kg = wave & 3, jn0 = (wave >> 2) * NTW;
-    const T* __restrict__ Wp = FOLD ? reinterpret_cast<const T*>(J.W32)
-                                    : reinterpret_cast<const T*>(J.W);
-    const T* __restrict__ P1 = FOLD ? reinterpret_cast<const T*>(J.p1_32)
-                                    : reinterpret_cast<const T*>(J.p1_64);
-    const T* __restrict__ P2 = FOLD ? reinterpret_cast<const T*>(J.p2_32)
-                                    : reinterpret_cast<const T*>(J.p2_64);
+    constexpr bool F32 = sizeof(T) == 4;
+    const T* __restrict__ Wp = F32 ? reinterpret_cast<const T*>(J.W32)
+                                   : reinterpret_cast<const T*>(J.W);
+    const T* __restrict__ P1 = F32 ? reinterpret_cast<const T*>(J.p1_32)
+                                   : reinterpret_cast<const T*>(J.p1_64);
+    const T* __restrict__ P2 = F32 ? reinterpret_cast<const T*>(J.p2_32)
+                                   : reinterpret_cast<const T*>(J.p2_64);
     T4 acc[MTW][NT];
     d4 acc64[FOLD ? MTW : 1][NT];
 #pragma unroll
@@ -790,6 +796,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
         if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
       }
     const int nact = J.tile_nact[tile];
+    bool folded = false;  // FM == 2: Loc rows written once already
     const unsigned char* act = J.tile_act + int64_t(tile) * kSlots;
     const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN + col0;
     const int* kidp = J.slot_kid + tl.parity * kSlots;
@@ -914,7 +921,8 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
             for (int i = 0; i < MTW; ++i) av[i] = an[kPre ? i : 0];
           }
         }
-        if (FOLD && (ia % FMM_M2L_SVD_FOLD_EVERY == FMM_M2L_SVD_FOLD_EVERY - 1 || ia == nact - 1)) {
+        const bool fold_now = (ia + 1) % J.fold_every == 0 || ia == nact - 1;
+        if (FOLD && fold_now) {
 #pragma unroll
           for (int i = 0; i < MTW; ++i)
 #pragma unroll
@@ -924,9 +932,35 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
               acc[i][j] = T4{0, 0, 0, 0};
             }
         }
+        if (FM == 2 && fold_now) {
+          // fold into this item's rows of Loc (scaled; the first fold
+          // stores, later ones add): no other workgroup touches these rows
+          const double sc = J.scale[tl.level];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int col = col0 + 16 * j + c16;
+            if (col < tl.count) {
+              double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+#pragma unroll
+              for (int i = 0; i < MTW; ++i) {
+                if (i >= nmt) continue;
+                d4* o = reinterpret_cast<d4*>(out + 16 * (mt0 + i) + 4 * g);  // rows 4g..4g+3
+                d4 v;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = sc * double(acc[i][j][r]);
+                if (folded) v += *o;
+                *o = v;
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < MTW; ++i) acc[i][j] = T4{0, 0, 0, 0};
+          }
+          folded = true;
+        }
       }
     }
 
+    if (FM == 2 && folded) continue;  // the folds wrote the rows
     const double sc = J.scale[tl.level];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -969,7 +1003,7 @@ size_t m2l_svd_lds_bytes(int xs, bool fp32) {
   return size_t(2) * 4 * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double));
 }
 
-template <typename T, bool FOLD>
+template <typename T, int FOLD>
 static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid,
                            size_t lds, hipStream_t s) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
@@ -989,9 +1023,9 @@ void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab
   const int mtw = m2l_svd_mtw((l3 + 15) / 16, fp32);
   const size_t lds = m2l_svd_lds_bytes(xs, fp32);
   if (fp32)
-    launch_svd_mtw<float, true>(mtw, jobs, tab, grid, lds, s);
+    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(mtw, jobs, tab, grid, lds, s);
   else
-    launch_svd_mtw<double, false>(mtw, jobs, tab, grid, lds, s);
+    launch_svd_mtw<double, 0>(mtw, jobs, tab, grid, lds, s);
   FMM_HIP_CHECK(hipGetLastError());
 }
 

@@ -102,6 +102,7 @@ def lib():
     L.fmm_plan_set_schedule.argtypes = [vp, i32]
     L.fmm_plan_set_kernel.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
+    L.fmm_plan_set_m2l_fold_interval.argtypes = [vp, i32]
     L.fmm_plan_svd_info.argtypes = [vp, ctypes.POINTER(SvdInfo)]
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
     L.fmm_plan_export.argtypes = [vp, i32, i32, vp, sz]
@@ -197,6 +198,11 @@ class Plan:
 
     def set_m2l_tolerance(self, eps: float):
         _check(lib().fmm_plan_set_m2l_tolerance(self._h, float(eps)))
+
+    def set_m2l_fold_interval(self, offsets: int):
+        """Far offsets between FP64 folds in the compressed mixed mode (0 =
+        the default for the order)."""
+        _check(lib().fmm_plan_set_m2l_fold_interval(self._h, int(offsets)))
 
     def svd_info(self) -> SvdInfo:
         out = SvdInfo()

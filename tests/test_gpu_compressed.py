@@ -114,3 +114,24 @@ def test_tolerance_beyond_lds_is_rejected_and_rolled_back():
     assert plan.svd_info().eps == eps0
     again = [host(t) for t in plan.evaluate(dev(q))]
     assert np.array_equal(again[0], ref[0]) and np.array_equal(again[1], ref[1])
+
+
+def test_fold_interval_trades_accuracy_and_is_checked():
+    # a tolerance far below the FP32 error, so that the fold is what varies
+    # (at this order's default 1e-5 the truncation itself errs ~8e-6)
+    pos, q = inputs.uniform_cube(20000, 1001)
+    plan = fmm.Plan(dev(pos), 4, 5)
+    p64, f64 = [host(t) for t in plan.evaluate(dev(q))]
+    plan.set_m2l_tolerance(1e-9)
+    plan.set_precision("mixed_svd")
+    for g in (1, 4, 16, 189, 0):
+        plan.set_m2l_fold_interval(g)
+        phi, f = [host(t) for t in plan.evaluate(dev(q))]
+        again = [host(t) for t in plan.evaluate(dev(q))]
+        assert np.array_equal(phi, again[0]) and np.array_equal(f, again[1])
+        e = max(rel(phi, p64), rel(f, f64))
+        print(f"  fold every {g}: {e:.2e}", flush=True)
+        assert e <= 1e-6
+    for bad in (-1, 190):
+        with pytest.raises(fmm.FMMError):
+            plan.set_m2l_fold_interval(bad)
