@@ -111,7 +111,8 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
     p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb);
     for (int st = 0; st + 4 <= h; ++st) {
       p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
-      p->tab_h[kTabL2L + st] = one_job(int(p->lev[3 + st].ncell), 3 + st);
+      // L2L items are the parents (level 2 + st) of the cells it updates
+      p->tab_h[kTabL2L + st] = one_job(int(p->lev[2 + st].ncell), 3 + st);
     }
   }
   if (!p->job_d) p->job_d = static_cast<JobDev*>(p->alloc(sizeof(JobDev)));

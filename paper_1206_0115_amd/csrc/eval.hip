@@ -103,12 +103,40 @@ __global__ __launch_bounds__(256) void p2m_kernel(const JobDev* __restrict__ job
 constexpr int kTransThreads = 256;
 constexpr int kTransMaxR = (kMaxOrder * kMaxOrder * kMaxOrder + kTransThreads - 1) / kTransThreads;
 
+// Children are staged in LDS, up to 8 x l^3 values per buffer: all children
+// of a cell at once when they fit (l <= 8), else one at a time.  Every
+// contraction below is written out in the same order as the one-child-at-a-
+// time form, and children are summed in key order, so the grouping changes
+// no bit of the result.
+constexpr int kStage = 4096;
+
+__host__ __device__ inline int child_group(int L3) { return 8 * L3 <= kStage ? 8 : 1; }
+
+// Dynamic LDS of the two kernels (doubles): M2M two staging buffers of G
+// children; L2L the parent's expansion plus the two buffers.
+size_t m2m_lds_bytes(int L) {
+  const int L3 = L * L * L;
+  return sizeof(double) * size_t(2) * child_group(L3) * L3;
+}
+size_t l2l_lds_bytes(int L) {
+  const int L3 = L * L * L;
+  return sizeof(double) * (size_t(1) + 2 * child_group(L3)) * L3;
+}
+// A launch may cover plans of several orders up to `max_order` (0: any).
+template <typename F>
+static size_t lds_up_to(int max_order, F bytes) {
+  const int top = max_order > 0 ? std::min(max_order, kMaxOrder) : kMaxOrder;
+  size_t b = 0;
+  for (int L = 1; L <= top; ++L) b = std::max(b, bytes(L));
+  return b;
+}
+
 // Item = parent cell at level tab->level[k].
 __global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __restrict__ jobs,
                                                             const StepTab* __restrict__ tab) {
   __shared__ double Sc[2 * kMaxOrder * kMaxOrder];
-  __shared__ double b0[kMaxOrder * kMaxOrder * kMaxOrder];
-  __shared__ double b1[kMaxOrder * kMaxOrder * kMaxOrder];
+  __shared__ int oct[8];
+  extern __shared__ double dyn_lds[];
   const int t = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
@@ -116,45 +144,59 @@ __global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __rest
     const int lv = tab->level[k];
     const int p = it_ - tab->start[k];
     const int L = J.order, L2 = L * L, L3 = L2 * L, ld = J.ld;
+    double* const A = dyn_lds;
+    double* const B = dyn_lds + child_group(L3) * L3;
     for (int e = t; e < 2 * L2; e += kTransThreads) Sc[e] = J.child[e];
     double acc[kTransMaxR];
     for (int r = 0; r < kTransMaxR; ++r) acc[r] = 0.0;
     const int c0 = J.child_start[lv][p], c1 = J.child_start[lv][p + 1];
     const uint64_t* ckeys = J.keys[lv + 1];
-    for (int c = c0; c < c1; ++c) {
-      const int o = int(ckeys[c] & 7u);
-      const double* Sx = Sc + ((o & 1) ? L2 : 0);
-      const double* Sy = Sc + (((o >> 1) & 1) ? L2 : 0);
-      const double* Sz = Sc + (((o >> 2) & 1) ? L2 : 0);
-      const int64_t crow = (J.lev_off[lv + 1] + c) * int64_t(ld);
+    const bool leaf_children = J.w32_leaf && lv + 1 == J.height - 1;
+    const int G = child_group(L3);
+    for (int g0 = c0; g0 < c1; g0 += G) {
+      const int nc = min(G, c1 - g0);
       __syncthreads();
-      if (J.w32_leaf && lv + 1 == J.height - 1) {
-        // leaf children stored in FP32 (mixed modes); the contraction is FP64
-        for (int e = t; e < L3; e += kTransThreads) b0[e] = double(J.W32[crow + e]);
-      } else {
-        for (int e = t; e < L3; e += kTransThreads) b0[e] = J.W[crow + e];
+      if (t < nc) oct[t] = int(ckeys[g0 + t] & 7u);
+      for (int e = t; e < nc * L3; e += kTransThreads) {
+        const int cc = e / L3, r = e - cc * L3;
+        const int64_t crow = (J.lev_off[lv + 1] + g0 + cc) * int64_t(ld);
+        // leaf children of the mixed modes are stored in FP32; the
+        // contraction is FP64
+        A[e] = leaf_children ? double(J.W32[crow + r]) : J.W[crow + r];
       }
       __syncthreads();
-      for (int e = t; e < L3; e += kTransThreads) {  // along z
-        const int ab = e / L, m3 = e % L;
+      for (int e = t; e < nc * L3; e += kTransThreads) {  // along z
+        const int cc = e / L3, r = e - cc * L3;
+        const double* Sz = Sc + (((oct[cc] >> 2) & 1) ? L2 : 0);
+        const int ab = r / L, m3 = r % L;
+        const double* a = A + cc * L3 + ab * L;
         double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sz[m3 * L + q] * b0[ab * L + q];
-        b1[e] = v;
+        for (int q = 0; q < L; ++q) v += Sz[m3 * L + q] * a[q];
+        B[e] = v;
       }
       __syncthreads();
-      for (int e = t; e < L3; e += kTransThreads) {  // along y
-        const int a1 = e / L2, m2 = (e / L) % L, m3 = e % L;
+      for (int e = t; e < nc * L3; e += kTransThreads) {  // along y
+        const int cc = e / L3, r = e - cc * L3;
+        const double* Sy = Sc + (((oct[cc] >> 1) & 1) ? L2 : 0);
+        const int a1 = r / L2, m2 = (r / L) % L, m3 = r % L;
+        const double* bb = B + cc * L3;
         double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sy[m2 * L + q] * b1[(a1 * L + q) * L + m3];
-        b0[e] = v;
+        for (int q = 0; q < L; ++q) v += Sy[m2 * L + q] * bb[(a1 * L + q) * L + m3];
+        A[e] = v;
       }
       __syncthreads();
-      for (int r = 0, e = t; e < L3; ++r, e += kTransThreads) {  // along x
-        const int m1 = e / L2, rest = e % L2;
+      for (int e = t; e < nc * L3; e += kTransThreads) {  // along x, per child
+        const int cc = e / L3, r = e - cc * L3;
+        const double* Sx = Sc + ((oct[cc] & 1) ? L2 : 0);
+        const int m1 = r / L2, rest = r % L2;
+        const double* aa = A + cc * L3;
         double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sx[m1 * L + q] * b0[q * L2 + rest];
-        acc[r] += v;
+        for (int q = 0; q < L; ++q) v += Sx[m1 * L + q] * aa[q * L2 + rest];
+        B[e] = v;
       }
+      __syncthreads();
+      for (int r = 0, e = t; e < L3; ++r, e += kTransThreads)  // children summed in key order
+        for (int cc = 0; cc < nc; ++cc) acc[r] += B[cc * L3 + e];
     }
     double* out = J.W + (J.lev_off[lv] + p) * ld;
     for (int r = 0, e = t; e < L3; ++r, e += kTransThreads) out[e] = acc[r];
@@ -163,48 +205,62 @@ __global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __rest
   }
 }
 
-// Item = child cell at level tab->level[k]; Loc_child += transposed
-// interpolation of the parent's local expansion.
+// Item = parent cell at level tab->level[k] - 1; every child at level
+// tab->level[k] gets Loc_child += transposed interpolation of the parent's
+// local expansion.
 __global__ __launch_bounds__(kTransThreads) void l2l_kernel(const JobDev* __restrict__ jobs,
                                                             const StepTab* __restrict__ tab) {
   __shared__ double Sc[2 * kMaxOrder * kMaxOrder];
-  __shared__ double b0[kMaxOrder * kMaxOrder * kMaxOrder];
-  __shared__ double b1[kMaxOrder * kMaxOrder * kMaxOrder];
+  __shared__ int oct[8];
+  extern __shared__ double dyn_lds[];
   const int t = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
-    const int lv = tab->level[k];
-    const int c = it_ - tab->start[k];
+    const int lv = tab->level[k];  // children's level
+    const int p = it_ - tab->start[k];
     const int L = J.order, L2 = L * L, L3 = L2 * L, ld = J.ld;
+    double* const P = dyn_lds;
+    double* const A = dyn_lds + L3;
+    double* const B = A + child_group(L3) * L3;
     for (int e = t; e < 2 * L2; e += kTransThreads) Sc[e] = J.child[e];
-    const int o = int(J.keys[lv][c] & 7u);
-    const double* lp = J.Loc + (J.lev_off[lv - 1] + J.parent[lv][c]) * ld;
-    for (int e = t; e < L3; e += kTransThreads) b0[e] = lp[e];
-    __syncthreads();
-    const double* Sx = Sc + ((o & 1) ? L2 : 0);
-    const double* Sy = Sc + (((o >> 1) & 1) ? L2 : 0);
-    const double* Sz = Sc + (((o >> 2) & 1) ? L2 : 0);
-    for (int e = t; e < L3; e += kTransThreads) {  // along z, transposed
-      const int ab = e / L, m3 = e % L;
-      double v = 0.0;
-      for (int q = 0; q < L; ++q) v += Sz[q * L + m3] * b0[ab * L + q];
-      b1[e] = v;
-    }
-    __syncthreads();
-    for (int e = t; e < L3; e += kTransThreads) {  // along y
-      const int a1 = e / L2, m2 = (e / L) % L, m3 = e % L;
-      double v = 0.0;
-      for (int q = 0; q < L; ++q) v += Sy[q * L + m2] * b1[(a1 * L + q) * L + m3];
-      b0[e] = v;
-    }
-    __syncthreads();
-    double* lc = J.Loc + (J.lev_off[lv] + c) * ld;
-    for (int e = t; e < L3; e += kTransThreads) {  // along x, accumulate
-      const int m1 = e / L2, rest = e % L2;
-      double v = 0.0;
-      for (int q = 0; q < L; ++q) v += Sx[q * L + m1] * b0[q * L2 + rest];
-      lc[e] += v;
+    const double* lp = J.Loc + (J.lev_off[lv - 1] + p) * ld;
+    for (int e = t; e < L3; e += kTransThreads) P[e] = lp[e];
+    const int c0 = J.child_start[lv - 1][p], c1 = J.child_start[lv - 1][p + 1];
+    const int G = child_group(L3);
+    for (int g0 = c0; g0 < c1; g0 += G) {
+      const int nc = min(G, c1 - g0);
+      __syncthreads();
+      if (t < nc) oct[t] = int(J.keys[lv][g0 + t] & 7u);
+      __syncthreads();
+      for (int e = t; e < nc * L3; e += kTransThreads) {  // along z, transposed
+        const int cc = e / L3, r = e - cc * L3;
+        const double* Sz = Sc + (((oct[cc] >> 2) & 1) ? L2 : 0);
+        const int ab = r / L, m3 = r % L;
+        double v = 0.0;
+        for (int q = 0; q < L; ++q) v += Sz[q * L + m3] * P[ab * L + q];
+        B[e] = v;
+      }
+      __syncthreads();
+      for (int e = t; e < nc * L3; e += kTransThreads) {  // along y
+        const int cc = e / L3, r = e - cc * L3;
+        const double* Sy = Sc + (((oct[cc] >> 1) & 1) ? L2 : 0);
+        const int a1 = r / L2, m2 = (r / L) % L, m3 = r % L;
+        const double* bb = B + cc * L3;
+        double v = 0.0;
+        for (int q = 0; q < L; ++q) v += Sy[q * L + m2] * bb[(a1 * L + q) * L + m3];
+        A[e] = v;
+      }
+      __syncthreads();
+      for (int e = t; e < nc * L3; e += kTransThreads) {  // along x, accumulate
+        const int cc = e / L3, r = e - cc * L3;
+        const double* Sx = Sc + ((oct[cc] & 1) ? L2 : 0);
+        const int m1 = r / L2, rest = r % L2;
+        const double* aa = A + cc * L3;
+        double v = 0.0;
+        for (int q = 0; q < L; ++q) v += Sx[q * L + m1] * aa[q * L2 + rest];
+        J.Loc[(J.lev_off[lv] + g0 + cc) * int64_t(ld) + r] += v;
+      }
     }
     __syncthreads();
   }
@@ -605,7 +661,7 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       break;
     }
     case kStepM2M:
-      m2m_kernel<<<g, kTransThreads, 0, s>>>(jobs, tab);
+      m2m_kernel<<<g, kTransThreads, lds_up_to(L, m2m_lds_bytes), s>>>(jobs, tab);
       break;
     case kStepCast:
       cast_kernel<<<g, 256, 0, s>>>(jobs, tab);
@@ -617,7 +673,7 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       launch_m2l_svd_step(L, fp32, jobs, tab, grid, xs, s);
       break;
     case kStepL2L:
-      l2l_kernel<<<g, kTransThreads, 0, s>>>(jobs, tab);
+      l2l_kernel<<<g, kTransThreads, lds_up_to(L, l2l_lds_bytes), s>>>(jobs, tab);
       break;
     case kStepL2P:
 #define L2P_CALL(LL) l2p_kernel<LL><<<g, 64, 0, s>>>(jobs, tab)
@@ -634,6 +690,13 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
   }
   FMM_HIP_CHECK(hipGetLastError());
 }
+
+// Where the forked schedule starts the near field: 0 = just before the M2L
+// launch, 1 = just after it.  Measured (1M cube, order 7, compressed mixed
+// mode, evaluate only): after 6.84 ms, serial 6.90 ms, before 6.98 ms.
+#ifndef FMM_FORK_AFTER_M2L
+#define FMM_FORK_AFTER_M2L 1
+#endif
 
 namespace {
 // the step's timing events, if set, around a launch on stream s
@@ -687,13 +750,14 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
     if (mixed && p->tab_h[kTabCast].start[1] > 0)
       launch_step(kStepCast, L, true, J, p->tab_d + kTabCast, nullptr,
                   p->tab_h[kTabCast].start[1], s);
+    if (forked && !FMM_FORK_AFTER_M2L) fork_near();
     {
       Timed t(FMM_TIME_M2L, s);
       if (p->ntiles > 0)
         launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
                     p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
     }
-    if (forked) fork_near();
+    if (forked && FMM_FORK_AFTER_M2L) fork_near();
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,
                   p->tab_h[kTabL2L + st].start[1], s);

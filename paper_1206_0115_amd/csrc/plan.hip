@@ -505,13 +505,28 @@ __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
     demorton3(L.keys[local], L.bits, c);
   }
   int* out = tile_src + int64_t(tile) * kSlots * kTileN;
-  for (int s = wave; s < kSlots; s += kTileThreads / 64) {
-    const signed char* t = slot_t + (T.parity * kSlots + s) * 3;
-    int b = -1;
-    if (have) b = level_find_xyz(L, c[0] + t[0], c[1] + t[1], c[2] + t[2]);
-    out[s * kTileN + j] = b >= 0 ? b + int(lev_off[T.level]) : zero_row;
-    const uint64_t m = __ballot(b >= 0);
-    if (j == 0) npair[s] = __popcll(m);
+  // the lookups of 8 slots are issued before any is used (independent loads
+  // in flight instead of one table access at a time)
+  constexpr int kStride = kTileThreads / 64, kBatch = 8;
+  for (int s0 = wave; s0 < kSlots; s0 += kStride * kBatch) {
+    int bs[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int s = s0 + u * kStride;
+      bs[u] = -1;
+      if (have && s < kSlots) {
+        const signed char* t = slot_t + (T.parity * kSlots + s) * 3;
+        bs[u] = level_find_xyz(L, c[0] + t[0], c[1] + t[1], c[2] + t[2]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int s = s0 + u * kStride;
+      if (s >= kSlots) continue;  // the same for the whole wavefront
+      out[s * kTileN + j] = bs[u] >= 0 ? bs[u] + int(lev_off[T.level]) : zero_row;
+      const uint64_t m = __ballot(bs[u] >= 0);
+      if (j == 0) npair[s] = __popcll(m);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {

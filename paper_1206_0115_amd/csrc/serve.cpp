@@ -285,8 +285,11 @@ bool fmm_server_s::launch_batch() {
   for (int L : orders)
     add(kStepP2M, L, false, [&](Request* r) { return far(r) && r->order == L; },
         [](Request* r) { return int(r->plan->nleaf); }, lvl0);
+  // M2M and L2L take every order in one launch; their LDS is sized for the
+  // batch's highest order
+  const int maxo = orders.empty() ? 0 : orders.back();
   for (int s = 0; s < steps; ++s)
-    add(kStepM2M, 0, false, [&](Request* r) { return r->h - 4 >= s; },
+    add(kStepM2M, maxo, false, [&](Request* r) { return r->h - 4 >= s; },
         [&](Request* r) { return int(r->plan->lev[r->h - 2 - s].ncell); },
         [&](Request* r) { return r->h - 2 - s; });
   add(kStepCast, 0, true, [&](Request* r) { return far(r) && mixed(r); },
@@ -300,8 +303,8 @@ bool fmm_server_s::launch_batch() {
             },
             [](Request* r) { return int(r->plan->ntiles) * r->plan->job_h.nmb; }, lvl0);
   for (int s = 0; s < steps; ++s)
-    add(kStepL2L, 0, false, [&](Request* r) { return r->h - 4 >= s; },
-        [&](Request* r) { return int(r->plan->lev[3 + s].ncell); },
+    add(kStepL2L, maxo, false, [&](Request* r) { return r->h - 4 >= s; },
+        [&](Request* r) { return int(r->plan->lev[2 + s].ncell); },
         [&](Request*) { return 3 + s; });
   for (int L : orders)
     add(kStepL2P, L, false, [&](Request* r) { return far(r) && r->order == L; },
