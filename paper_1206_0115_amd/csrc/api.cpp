@@ -63,6 +63,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   if (p->svd) {
     J.xs = m2l_svd_xs(p->svd->rmax_pad, fp32);
     J.svd_rpad = p->svd->rpad;
+    J.svd_rank = p->svd->rk;
     J.svd_off = p->svd->off;
     J.p1_64 = p->svd->p1_64;
     J.p1_32 = p->svd->p1_32;

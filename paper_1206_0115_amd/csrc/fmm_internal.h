@@ -84,6 +84,7 @@ struct SvdOps {
   double weighted_rank = 0; // sum over the 316 offsets of the rank / 316
   int64_t flops_per_pair_weighted = 0;  // sum_t 4 l^3 rpad_t / 316, rounded
   int* rpad = nullptr;      // [316] padded rank per packed operator
+  int* rk = nullptr;        // [316] kept rank per packed operator
   int64_t* off = nullptr;   // [316] element offset of its factors
   std::vector<int> rpad_h;
   double* p1_64 = nullptr;  // S V^T factors in fragment order

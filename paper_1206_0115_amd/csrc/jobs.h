@@ -58,10 +58,11 @@ struct JobDev {
   double scale[kMaxHeightJ];  // a_l^-p, the M2L level factor
   const double* kp64;
   const float* kp32;
-  // compressed M2L (svd != 0): per packed operator kid, the padded rank and
-  // the element offset of its two factors in the packs below
+  // compressed M2L (svd != 0): per packed operator kid, the padded rank, the
+  // kept rank and the element offset of its two factors in the packs below
   int svd, xs;
   const int* svd_rpad;
+  const int* svd_rank;
   const int64_t* svd_off;
   const double* p1_64;  // S V^T (rank x l^3) in MFMA fragment order
   const float* p1_32;

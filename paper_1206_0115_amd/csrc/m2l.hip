@@ -495,6 +495,15 @@ namespace {
 // rocSOLVER works column-major: it factorises M = Kc^T (the row-major buffer
 // read column-major) as M = U_M S V_M^T and returns U_M and V_M^T, so
 // Uc[a][k] = Vt[a*n + k] and Vc[b][k] = U[k*n + b].
+// Rank held by position p of the packed factors: inside each block of 16
+// the 4 x 4 transpose, so that K-step st of a phase-2 MFMA chunk (positions
+// 4g + st over the four lane groups g) takes the four consecutive ranks
+// 4 st .. 4 st + 3, and the steps past the kept rank hold only zeros.  The
+// order of the ranks in a sum over them is free; both factors use the same.
+__host__ __device__ inline int rank_slot(int p) {
+  return (p & ~15) | ((p & 3) << 2) | ((p >> 2) & 3);
+}
+
 __global__ void svd_pack_kernel(const double* __restrict__ U, const double* __restrict__ Vt,
                                 const double* __restrict__ S, const int* __restrict__ info,
                                 const int* __restrict__ rank, const int* __restrict__ rpad,
@@ -519,17 +528,17 @@ __global__ void svd_pack_kernel(const double* __restrict__ U, const double* __re
        e += int64_t(gridDim.x) * blockDim.x) {
     const int s = int(e & 3), lane = int((e >> 2) & 63);
     const int64_t q = e >> 8;
-    {  // phase-1 factor: rows k (rp), columns n (ld)
+    {  // phase-1 factor: rows k (rp, in rank_slot order), columns n (ld)
       const int cc = int(q % kc), i = int(q / kc);
-      const int k = 16 * i + (lane & 15), n = 16 * cc + 4 * (lane >> 4) + s;
+      const int k = rank_slot(16 * i + (lane & 15)), n = 16 * cc + 4 * (lane >> 4) + s;
       double v = 0.0;
       if (k < r && n < l3) v = Sc[k] * Uc[int64_t(k) * l3 + gmap(n)];
       p1_64[off[kid] + e] = v;
       p1_32[off[kid] + e] = float(v);
     }
-    {  // phase-2 factor: rows m (ld), columns k (rp)
+    {  // phase-2 factor: rows m (ld), columns k (rp, in rank_slot order)
       const int cc = int(q % nr), i = int(q / nr);
-      const int m = 16 * i + (lane & 15), k = 16 * cc + 4 * (lane >> 4) + s;
+      const int m = 16 * i + (lane & 15), k = rank_slot(16 * cc + 4 * (lane >> 4) + s);
       double v = 0.0;
       if (m < l3 && k < r) v = Vc[int64_t(gmap(m)) * l3 + k];
       p2_64[off[kid] + e] = v;
@@ -625,6 +634,7 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
       sv->rank[c] = rank_h[c];
     }
     sv->rpad_h.resize(kOffsets);
+    std::vector<int> rk_h(kOffsets);
     std::vector<int64_t> off(kOffsets);
     int64_t tot = 0;
     double wr = 0.0, wf = 0.0;
@@ -632,6 +642,7 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
       const int r = rank_h[T.offs[k].canon];
       const int rp = 16 * ((r + 15) / 16);
       sv->rpad_h[k] = rp;
+      rk_h[k] = r;
       sv->rmax_pad = std::max(sv->rmax_pad, rp);
       off[k] = tot;
       tot += int64_t(rp) * op->ld;
@@ -648,6 +659,9 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
                                  hipMemcpyHostToDevice, s));
     FMM_HIP_CHECK(hipMemcpyAsync(sv->off, off.data(), sizeof(int64_t) * kOffsets,
                                  hipMemcpyHostToDevice, s));
+    sv->rk = static_cast<int*>(dev_alloc(sizeof(int) * kOffsets));
+    FMM_HIP_CHECK(hipMemcpyAsync(sv->rk, rk_h.data(), sizeof(int) * kOffsets,
+                                 hipMemcpyHostToDevice, s));
     sv->p1_64 = static_cast<double*>(dev_alloc(sizeof(double) * tot));
     sv->p2_64 = static_cast<double*>(dev_alloc(sizeof(double) * tot));
     sv->p1_32 = static_cast<float*>(dev_alloc(sizeof(float) * tot));
@@ -660,6 +674,9 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
   } catch (...) {
     (void)hipStreamSynchronize(s);
     for (void* q : tmp) dev_free(q);
+    for (void* q : {(void*)sv->rpad, (void*)sv->rk, (void*)sv->off, (void*)sv->p1_64,
+                    (void*)sv->p1_32, (void*)sv->p2_64, (void*)sv->p2_32})
+      if (q) dev_free(q);
     throw;
   }
   for (void* q : tmp) dev_free(q);
@@ -805,6 +822,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
       const int s = act[ia];
       const int kid = kidp[s];
       const int rp = J.svd_rpad[kid], nr = rp >> 4;
+      const int nst = (J.svd_rank[kid] - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
       const int64_t off = J.svd_off[kid];
       T* const P = lds + buf * 4 * NC * XS;
       T* const Pw = P + kg * NC * XS;
@@ -907,8 +925,11 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
             for (int w = 1; w < 4; ++w) v += *reinterpret_cast<const T4*>(P + w * NC * XS + o);
             bv[j] = v;
           }
+          // K-steps past the kept rank hold zeros in both operands
+          const int ns = c + 1 < nr ? 4 : nst;
 #pragma unroll
-          for (int st = 0; st < 4; ++st)
+          for (int st = 0; st < 4; ++st) {
+            if (st >= ns) continue;
 #pragma unroll
             for (int i = 0; i < MTW; ++i) {
               if (i >= nmt) continue;
@@ -916,6 +937,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
               for (int j = 0; j < NT; ++j)
                 acc[i][j] = mfma16x16x4(av[i][st], bv[j][st], acc[i][j]);
             }
+          }
           if (kPre && c + 1 < nr) {
 #pragma unroll
             for (int i = 0; i < MTW; ++i) av[i] = an[kPre ? i : 0];
@@ -981,6 +1003,359 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
   }
 }
 
+// Warp-specialised form of the same computation, 8 wavefronts: 0-3 are the
+// four K-groups of phase 1 (producers), 4-7 own the M-tiles of phase 2
+// (consumers, MTW each, as the 4-wavefront kernel).  Iteration ia of an
+// item: the producers write X of offset ia into slab buffer ia % 2 while the
+// consumers apply X of offset ia - 1 from the other buffer; one barrier ends
+// the iteration, so phase 1 of one offset runs beside phase 2 of the
+// previous one, and a buffer is written again only after the barrier that
+// follows its last read.  Both roles walk the same items and pass nact + 1
+// barriers per item; the role is taken on a wavefront-uniform branch, and
+// each role keeps only its own registers live.  The arithmetic, including
+// its order, is that of m2l_svd_kernel with 4 wavefronts: FP32 folds into
+// the item's FP64 Loc rows every J.fold_every offsets; FP64 accumulates in
+// registers and writes once.
+#ifndef FMM_M2L_SVD_WS_WAVES
+#define FMM_M2L_SVD_WS_WAVES 4
+#endif
+// Producer stage depth D, FP32 and FP64: where every K-group has at most D
+// chunks of the l^3 contraction (ceil(KC / 4) <= D), the kernel built for D
+// loads each K-group's chunks all at once; otherwise (or D = 0) they stream
+// one chunk ahead.
+#ifndef FMM_M2L_SVD_WS_STAGE_F32
+#define FMM_M2L_SVD_WS_STAGE_F32 0
+#endif
+#ifndef FMM_M2L_SVD_WS_STAGE_F64
+#define FMM_M2L_SVD_WS_STAGE_F64 0
+#endif
+#ifndef FMM_M2L_SVD_WS_APRE_F32
+#define FMM_M2L_SVD_WS_APRE_F32 0
+#endif
+#ifndef FMM_M2L_SVD_WS_APRE_F64
+#define FMM_M2L_SVD_WS_APRE_F64 0
+#endif
+
+struct SvdItem {
+  const JobDev* J;
+  M2LTile tl;
+  int tile, mb, col0;
+};
+
+// Item `it` of the launch; false when its N-group holds no target column
+// (the same for the whole workgroup).
+template <int NT>
+__device__ inline bool svd_item(const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab,
+                                int it, int total, SvdItem& I) {
+  constexpr int NC = 16 * NT, NG = 4 / NT;
+  int b = it;
+  if (int(gridDim.x) == total) {
+    const int n8 = (total / 8) * 8;
+    if (b < n8) b = (b % 8) * (n8 / 8) + b / 8;
+  }
+  const int k = step_find(*tab, b);
+  const JobDev& J = jobs[tab->job[k]];
+  const int local = b - tab->start[k];
+  I.J = &J;
+  I.tile = local / J.nmb;
+  const int rem = local % J.nmb;
+  I.mb = rem / NG;
+  I.col0 = NC * (rem % NG);
+  I.tl = J.tiles[I.tile];
+  return I.col0 < I.tl.count;
+}
+
+template <typename T, int NT, int D>
+__device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
+                                      const StepTab* __restrict__ tab, T* const lds, int kg) {
+  typedef typename Vec4<T>::type T4;
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int NC = 16 * NT;
+  constexpr int kRP = F32 ? FMM_M2L_SVD_RPASS_F32 : FMM_M2L_SVD_RPASS_F64;
+  // staged path: the next rank tile's factor fragments load while this one
+  // computes (1) or after it (0)
+  constexpr bool kAPre = F32 ? FMM_M2L_SVD_WS_APRE_F32 : FMM_M2L_SVD_WS_APRE_F64;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+  const int total = step_total(*tab);
+  int buf = 0;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    SvdItem I;
+    if (!svd_item<NT>(jobs, tab, it, total, I)) continue;
+    const JobDev& J = *I.J;
+    const int KC = J.kc, ld = J.ld, XS = J.xs;
+    const int nck = KC > kg ? (KC - kg + 3) / 4 : 0;  // chunks kg, kg + 4, ...
+    const T* __restrict__ Wp = F32 ? reinterpret_cast<const T*>(J.W32)
+                                   : reinterpret_cast<const T*>(J.W);
+    const T* __restrict__ P1 = F32 ? reinterpret_cast<const T*>(J.p1_32)
+                                   : reinterpret_cast<const T*>(J.p1_64);
+    const int nact = J.tile_nact[I.tile];
+    const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
+    const int* srcb = J.tile_src + int64_t(I.tile) * kSlots * kTileN + I.col0;
+    const int* kidp = J.slot_kid + I.tl.parity * kSlots;
+    for (int ia = 0; ia <= nact; ++ia) {
+      if (ia < nact) {
+        // phase 1 of offset ia: this K-group's partial X into its slab
+        const int s = act[ia];
+        const int kid = kidp[s];
+        const int nr = J.svd_rpad[kid] >> 4;
+        const int64_t off = J.svd_off[kid];
+        T* const Pw = lds + buf * 4 * NC * XS + kg * NC * XS;
+        const T* bp[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+        if (D > 0) {  // the host launches D > 0 only where nck <= D
+          // the K-group's whole share of the gathered multipoles in
+          // registers at once (one memory latency per offset, not per
+          // chunk), then one rank tile after the other with the next
+          // tile's factor fragments in flight
+          T4 wv[D > 0 ? D : 1][NT], an[D > 0 ? D : 1];
+          const T* a0 = P1 + off + lane * 4;
+#pragma unroll
+          for (int u = 0; u < D; ++u) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+              wv[u][j] = u < nck ? *reinterpret_cast<const T4*>(bp[j] + 16 * (kg + 4 * u))
+                                 : T4{0, 0, 0, 0};
+            an[u] = u < nck ? *reinterpret_cast<const T4*>(a0 + int64_t(kg + 4 * u) * 256)
+                            : T4{0, 0, 0, 0};
+          }
+          for (int i = 0; i < nr; ++i) {
+            T4 av[D > 0 ? D : 1];
+#pragma unroll
+            for (int u = 0; u < D; ++u) av[u] = an[u];
+            if (kAPre && i + 1 < nr) {
+              const T* an0 = a0 + int64_t(i + 1) * KC * 256;
+#pragma unroll
+              for (int u = 0; u < D; ++u)
+                an[u] = u < nck ? *reinterpret_cast<const T4*>(an0 + int64_t(kg + 4 * u) * 256)
+                                : T4{0, 0, 0, 0};
+            }
+            T4 x[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) x[j] = T4{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+              if (u >= nck) continue;
+#pragma unroll
+              for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) x[j] = mfma16x16x4(av[u][st], wv[u][j][st], x[j]);
+            }
+            if (!kAPre && i + 1 < nr) {
+              const T* an0 = a0 + int64_t(i + 1) * KC * 256;
+#pragma unroll
+              for (int u = 0; u < D; ++u)
+                an[u] = u < nck ? *reinterpret_cast<const T4*>(an0 + int64_t(kg + 4 * u) * 256)
+                                : T4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+              T* xrow = Pw + (16 * j + c16) * XS + 16 * i;
+              if (!F32) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xrow[4 * r + g] = x[j][r];
+              } else {
+                *reinterpret_cast<T4*>(xrow + 4 * g) = x[j];
+              }
+            }
+          }
+        } else
+        for (int i0 = 0; i0 < nr; i0 += kRP) {
+          const int np = min(kRP, nr - i0);
+          const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
+          T4 x[kRP][NT];
+#pragma unroll
+          for (int i = 0; i < kRP; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) x[i][j] = T4{0, 0, 0, 0};
+          T4 bv[NT], av[kRP];
+          if (kg < KC) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * kg);
+#pragma unroll
+            for (int i = 0; i < kRP; ++i)
+              av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256)
+                             : T4{0, 0, 0, 0};
+          }
+          for (int c = kg; c < KC; c += 4) {
+            T4 bn[NT], an[kRP];
+            const bool more = c + 4 < KC;
+            if (more) {
+#pragma unroll
+              for (int j = 0; j < NT; ++j)
+                bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
+#pragma unroll
+              for (int i = 0; i < kRP; ++i)
+                an[i] = i < np
+                            ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256)
+                            : T4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+              for (int i = 0; i < kRP; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                  if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
+            if (more) {
+#pragma unroll
+              for (int j = 0; j < NT; ++j) bv[j] = bn[j];
+#pragma unroll
+              for (int i = 0; i < kRP; ++i) av[i] = an[i];
+            }
+          }
+          // D rows: FP32 item r -> row 4g + r, FP64 item r -> row 4r + g
+#pragma unroll
+          for (int i = 0; i < kRP; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+              if (i >= np) continue;
+              T* xrow = Pw + (16 * j + c16) * XS + 16 * (i0 + i);
+              if (!F32) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xrow[4 * r + g] = x[i][j][r];
+              } else {
+                *reinterpret_cast<T4*>(xrow + 4 * g) = x[i][j];
+              }
+            }
+        }
+      }
+      buf ^= 1;
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, int MTW, int NT>
+__device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
+                                      const StepTab* __restrict__ tab, const T* const lds,
+                                      int wg) {
+  typedef typename Vec4<T>::type T4;
+  constexpr bool F32 = sizeof(T) == 4;
+  constexpr int NC = 16 * NT;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
+  const int total = step_total(*tab);
+  int buf = 0;
+  for (int it = blockIdx.x; it < total; it += gridDim.x) {
+    SvdItem I;
+    if (!svd_item<NT>(jobs, tab, it, total, I)) continue;
+    const JobDev& J = *I.J;
+    const M2LTile tl = I.tl;
+    const int MT = J.mt, ld = J.ld, XS = J.xs;
+    const int mt0 = (I.mb * 4 + wg) * MTW;
+    const int nmt = mt0 < MT ? min(MTW, MT - mt0) : 0;
+    const T* __restrict__ P2 = F32 ? reinterpret_cast<const T*>(J.p2_32)
+                                   : reinterpret_cast<const T*>(J.p2_64);
+    T4 acc[MTW][NT];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acc[i][j] = T4{0, 0, 0, 0};
+    const int nact = J.tile_nact[I.tile];
+    bool folded = false;
+    const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
+    const int* kidp = J.slot_kid + tl.parity * kSlots;
+    for (int ia = 0; ia <= nact; ++ia) {
+      if (ia > 0 && nmt > 0) {
+        // phase 2 of offset ia - 1 from the buffer the producers filled
+        const int ic = ia - 1;
+        const int kid = kidp[act[ic]];
+        const int nr = J.svd_rpad[kid] >> 4;
+        const int nst = (J.svd_rank[kid] - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
+        const int64_t off = J.svd_off[kid];
+        const T* const P = lds + (buf ^ 1) * 4 * NC * XS;
+        const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
+        for (int c = 0; c < nr; ++c) {
+          T4 bv[NT];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int o = (16 * j + c16) * XS + 16 * c + 4 * g;
+            T4 v = *reinterpret_cast<const T4*>(P + o);
+#pragma unroll
+            for (int w = 1; w < 4; ++w) v += *reinterpret_cast<const T4*>(P + w * NC * XS + o);
+            bv[j] = v;
+          }
+          // one U fragment live at a time; each accumulator still takes the
+          // K-steps in order, and the steps past the kept rank (zeros in
+          // both operands) are skipped
+          const int ns = c + 1 < nr ? 4 : nst;
+#pragma unroll
+          for (int i = 0; i < MTW; ++i) {
+            if (i >= nmt) continue;
+            const T4 av = *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256);
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+              if (st >= ns) continue;
+#pragma unroll
+              for (int j = 0; j < NT; ++j)
+                acc[i][j] = mfma16x16x4(av[st], bv[j][st], acc[i][j]);
+            }
+          }
+        }
+        if (F32 && ((ic + 1) % J.fold_every == 0 || ic == nact - 1)) {
+          // fold into this item's rows of Loc (scaled; the first fold
+          // stores, later ones add): no other workgroup touches these rows
+          const double sc = J.scale[tl.level];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int col = I.col0 + 16 * j + c16;
+            if (col < tl.count) {
+              double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+#pragma unroll
+              for (int i = 0; i < MTW; ++i) {
+                if (i >= nmt) continue;
+                d4* o = reinterpret_cast<d4*>(out + 16 * (mt0 + i) + 4 * g);  // rows 4g..4g+3
+                d4 v;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = sc * double(acc[i][j][r]);
+                if (folded) v += *o;
+                *o = v;
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < MTW; ++i) acc[i][j] = T4{0, 0, 0, 0};
+          }
+          folded = true;
+        }
+      }
+      buf ^= 1;
+      __syncthreads();
+    }
+    if (nmt == 0 || (F32 && folded)) continue;
+    const double sc = J.scale[tl.level];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int col = I.col0 + 16 * j + c16;
+      if (col >= tl.count) continue;
+      double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+#pragma unroll
+      for (int i = 0; i < MTW; ++i) {
+        if (i >= nmt) continue;
+        const int base = 16 * (mt0 + i);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = F32 ? 4 * g + r : 4 * r + g;
+          out[base + row] = sc * double(acc[i][j][r]);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int MTW, int NT, int D>
+__global__ __launch_bounds__(512, FMM_M2L_SVD_WS_WAVES) void m2l_svd_ws_kernel(
+    const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* const lds = reinterpret_cast<T*>(lds_raw);
+  // the role is uniform per wavefront: a scalar branch, no lane masking
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  if (wave < 4)
+    svd_ws_produce<T, NT, D>(jobs, tab, lds, wave);
+  else
+    svd_ws_consume<T, MTW, NT>(jobs, tab, lds, wave - 4);
+}
+
 // M-tiles per wavefront for the compressed kernel: the whole output in one
 // M-block when it fits NWV x 6 tiles (phase 1 then runs once per N-group).
 static int m2l_svd_mtw(int mt, bool fp32) {
@@ -1003,10 +1378,45 @@ size_t m2l_svd_lds_bytes(int xs, bool fp32) {
   return size_t(2) * 4 * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double));
 }
 
+// Whether the warp-specialised kernel runs (FP32, FP64); it needs the
+// 4-wavefront M-blocking (NWV 4).
+#ifndef FMM_M2L_SVD_WS_F32
+#define FMM_M2L_SVD_WS_F32 0
+#endif
+#ifndef FMM_M2L_SVD_WS_F64
+#define FMM_M2L_SVD_WS_F64 1
+#endif
+static_assert(!FMM_M2L_SVD_WS_F32 || svd_nwv(true) == 4, "warp-specialised FP32 needs NWV 4");
+static_assert(!FMM_M2L_SVD_WS_F64 || svd_nwv(false) == 4, "warp-specialised FP64 needs NWV 4");
+
 template <typename T, int FOLD>
-static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int grid,
+static void launch_svd_mtw(int mtw, int kc, const JobDev* jobs, const StepTab* tab, int grid,
                            size_t lds, hipStream_t s) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
+  constexpr bool WS = sizeof(T) == 4 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
+  if (WS) {
+    constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
+    if (D > 0 && (kc + 3) / 4 <= D) {
+      switch (mtw) {
+        case 1: m2l_svd_ws_kernel<T, 1, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+        case 2: m2l_svd_ws_kernel<T, 2, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+        case 3: m2l_svd_ws_kernel<T, 3, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+        case 4: m2l_svd_ws_kernel<T, 4, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+        case 5: m2l_svd_ws_kernel<T, 5, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+        default: m2l_svd_ws_kernel<T, 6, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+      }
+      return;
+    }
+    switch (mtw) {
+      case 1: m2l_svd_ws_kernel<T, 1, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+      case 2: m2l_svd_ws_kernel<T, 2, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+      case 3: m2l_svd_ws_kernel<T, 3, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+      case 4: m2l_svd_ws_kernel<T, 4, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+      case 5: m2l_svd_ws_kernel<T, 5, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+      default: m2l_svd_ws_kernel<T, 6, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+    }
+    return;
+  }
   switch (mtw) {
     case 1: m2l_svd_kernel<T, 1, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
     case 2: m2l_svd_kernel<T, 2, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
@@ -1020,12 +1430,12 @@ static void launch_svd_mtw(int mtw, const JobDev* jobs, const StepTab* tab, int 
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
                          int xs, hipStream_t s) {
   const int l3 = order * order * order;
-  const int mtw = m2l_svd_mtw((l3 + 15) / 16, fp32);
+  const int mtw = m2l_svd_mtw((l3 + 15) / 16, fp32), kc = (l3 + 15) / 16;
   const size_t lds = m2l_svd_lds_bytes(xs, fp32);
   if (fp32)
-    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(mtw, jobs, tab, grid, lds, s);
+    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(mtw, kc, jobs, tab, grid, lds, s);
   else
-    launch_svd_mtw<double, 0>(mtw, jobs, tab, grid, lds, s);
+    launch_svd_mtw<double, 0>(mtw, kc, jobs, tab, grid, lds, s);
   FMM_HIP_CHECK(hipGetLastError());
 }
 
