@@ -62,4 +62,37 @@ __device__ inline int level_find_xyz(const LevelDev& L, int x, int y, int z) {
 
 inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
 
+// Global-memory access through pointers the compiler cannot place (loaded
+// from a job descriptor): without the address space it emits flat
+// instructions, which count against both the vector-memory and the LDS
+// wait counters, so every LDS wait also waits for the HBM loads in flight.
+#define FMM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const FMM_GLOBAL T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, const T& v) {
+  *(FMM_GLOBAL T*)(p) = v;
+}
+
+// A value known to be the same in every lane of the wavefront, as a scalar:
+// branches on it are scalar branches (no lane masking) and loops on it run
+// on the scalar unit.
+__device__ __forceinline__ int wuni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t wuni(int64_t v) {
+  const uint64_t u = uint64_t(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(u));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(u >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ const T* wuni(const T* p) {
+  return reinterpret_cast<const T*>(wuni(int64_t(reinterpret_cast<uintptr_t>(p))));
+}
+template <typename T>
+__device__ __forceinline__ T* wuni(T* p) {
+  return reinterpret_cast<T*>(wuni(int64_t(reinterpret_cast<uintptr_t>(p))));
+}
+
 }  // namespace fmm

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
     const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   typedef typename Vec4<T>::type T4;
   const int total = step_total(*tab);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wuni(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
     // with one block per item, blocks are dealt round-robin to the 8 XCDs:
@@ -349,17 +349,17 @@ __global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
         if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
       }
 
-    const int nact = J.tile_nact[tile];
+    const int nact = wuni(gld(J.tile_nact + tile));
     const unsigned char* act = J.tile_act + int64_t(tile) * kSlots;
     const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN;
     const int* kidp = J.slot_kid + tl.parity * kSlots;
 
     for (int ia = 0; ia < nact; ++ia) {
-      const int s = act[ia];
-      const int kid = kidp[s];
+      const int s = wuni(int(gld(act + ia)));
+      const int kid = wuni(gld(kidp + s));
       const T* bptr[4];
       for (int j = 0; j < 4; ++j)
-        bptr[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+        bptr[j] = Wp + int64_t(gld(srcb + s * kTileN + 16 * j + c16)) * ld + 4 * g;
       const T* aptr = Kp + (int64_t(kid) * MT + mt0) * KC * 256 + lane * 4;
 
       // The A and B fragments are double-buffered one chunk ahead.  In FP64
@@ -367,21 +367,21 @@ __global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
       // (36.8 vs 42.7 ms for the 1M-particle order-7 M2L on gfx950).
       constexpr bool kPrefetchB = sizeof(T) == 4 || FMM_M2L_F64_PREFETCH_B;
       T4 bv[4], av[MTW];
-      for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j]);
+      for (int j = 0; j < 4; ++j) bv[j] = gld(reinterpret_cast<const T4*>(bptr[j]));
       for (int i = 0; i < MTW; ++i)
-        av[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + int64_t(i) * KC * 256)
+        av[i] = i < nmt ? gld(reinterpret_cast<const T4*>(aptr + int64_t(i) * KC * 256))
                         : T4{0, 0, 0, 0};
       for (int c = 0; c < KC; ++c) {
         T4 bn[kPrefetchB ? 4 : 1], an[MTW];
         const bool more = c + 1 < KC;
         if (!kPrefetchB && c > 0)
-          for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const T4*>(bptr[j] + 16 * c);
+          for (int j = 0; j < 4; ++j) bv[j] = gld(reinterpret_cast<const T4*>(bptr[j] + 16 * c));
         if (more) {
           if (kPrefetchB)
             for (int j = 0; j < 4; ++j)
-              bn[kPrefetchB ? j : 0] = *reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1));
+              bn[kPrefetchB ? j : 0] = gld(reinterpret_cast<const T4*>(bptr[j] + 16 * (c + 1)));
           for (int i = 0; i < MTW; ++i)
-            an[i] = i < nmt ? *reinterpret_cast<const T4*>(aptr + (int64_t(i) * KC + c + 1) * 256)
+            an[i] = i < nmt ? gld(reinterpret_cast<const T4*>(aptr + (int64_t(i) * KC + c + 1) * 256))
                             : T4{0, 0, 0, 0};
         }
 #pragma unroll
@@ -413,19 +413,20 @@ __global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
     for (int j = 0; j < 4; ++j) {
       const int col = 16 * j + c16;
       if (col >= tl.count) continue;
-      double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+      double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         if (i >= nmt) continue;  // constant trip count keeps acc[] in registers
         const int base = 16 * (mt0 + i);
         if (f64) {
           for (int r = 0; r < 4; ++r)
-            out[base + 4 * r + g] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+            gst(out + base + 4 * r + g,
+                sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r])));
         } else {
           d4 v;
           for (int r = 0; r < 4; ++r)
             v[r] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
-          *reinterpret_cast<d4*>(out + base + 4 * g) = v;
+          gst(reinterpret_cast<d4*>(out + base + 4 * g), v);
         }
       }
     }
@@ -776,7 +777,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
   T* const lds = reinterpret_cast<T*>(lds_raw);
   int buf = 0;
   const int total = step_total(*tab);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = wuni(int(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
   const bool f64 = sizeof(T) == 8;
   for (int it = blockIdx.x; it < total; it += gridDim.x) {
@@ -812,18 +813,18 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
         acc[i][j] = T4{0, 0, 0, 0};
         if (FOLD) acc64[FOLD ? i : 0][j] = d4{0, 0, 0, 0};
       }
-    const int nact = J.tile_nact[tile];
+    const int nact = wuni(gld(J.tile_nact + tile));
     bool folded = false;  // FM == 2: Loc rows written once already
     const unsigned char* act = J.tile_act + int64_t(tile) * kSlots;
     const int* srcb = J.tile_src + int64_t(tile) * kSlots * kTileN + col0;
     const int* kidp = J.slot_kid + tl.parity * kSlots;
 
     for (int ia = 0; ia < nact; ++ia) {
-      const int s = act[ia];
-      const int kid = kidp[s];
-      const int rp = J.svd_rpad[kid], nr = rp >> 4;
-      const int nst = (J.svd_rank[kid] - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
-      const int64_t off = J.svd_off[kid];
+      const int s = wuni(int(gld(act + ia)));
+      const int kid = wuni(gld(kidp + s));
+      const int rp = wuni(gld(J.svd_rpad + kid)), nr = rp >> 4;
+      const int nst = (wuni(gld(J.svd_rank + kid)) - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
+      const int64_t off = wuni(gld(J.svd_off + kid));
       T* const P = lds + buf * 4 * NC * XS;
       T* const Pw = P + kg * NC * XS;
       buf ^= 1;
@@ -831,7 +832,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
       const T* bp[NTW];
 #pragma unroll
       for (int j = 0; j < NTW; ++j)
-        bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * (jn0 + j) + c16]) * ld + 4 * g;
+        bp[j] = Wp + int64_t(gld(srcb + s * kTileN + 16 * (jn0 + j) + c16)) * ld + 4 * g;
       for (int i0 = 0; i0 < nr; i0 += kRP) {
         const int np = min(kRP, nr - i0);
         const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
@@ -843,10 +844,10 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
         T4 bv[NTW], av[kRP];
         if (kg < KC) {
 #pragma unroll
-          for (int j = 0; j < NTW; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * kg);
+          for (int j = 0; j < NTW; ++j) bv[j] = gld(reinterpret_cast<const T4*>(bp[j] + 16 * kg));
 #pragma unroll
           for (int i = 0; i < kRP; ++i)
-            av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256)
+            av[i] = i < np ? gld(reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256))
                            : T4{0, 0, 0, 0};
         }
         for (int c = kg; c < KC; c += 4) {
@@ -855,10 +856,10 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
           if (more) {
 #pragma unroll
             for (int j = 0; j < NTW; ++j)
-              bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
+              bn[j] = gld(reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4)));
 #pragma unroll
             for (int i = 0; i < kRP; ++i)
-              an[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256)
+              an[i] = i < np ? gld(reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256))
                              : T4{0, 0, 0, 0};
           }
 #pragma unroll
@@ -900,7 +901,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
         if (kPre) {
 #pragma unroll
           for (int i = 0; i < MTW; ++i)
-            av[i] = i < nmt ? *reinterpret_cast<const T4*>(a2 + int64_t(i) * nr * 256)
+            av[i] = i < nmt ? gld(reinterpret_cast<const T4*>(a2 + int64_t(i) * nr * 256))
                             : T4{0, 0, 0, 0};
         }
         for (int c = 0; c < nr; ++c) {
@@ -908,13 +909,13 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
           if (!kPre) {
 #pragma unroll
             for (int i = 0; i < MTW; ++i)
-              av[i] = i < nmt ? *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256)
+              av[i] = i < nmt ? gld(reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256))
                               : T4{0, 0, 0, 0};
           } else if (c + 1 < nr) {
 #pragma unroll
             for (int i = 0; i < MTW; ++i)
               an[kPre ? i : 0] =
-                  i < nmt ? *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c + 1) * 256)
+                  i < nmt ? gld(reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c + 1) * 256))
                           : T4{0, 0, 0, 0};
           }
 #pragma unroll
@@ -962,7 +963,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
           for (int j = 0; j < NT; ++j) {
             const int col = col0 + 16 * j + c16;
             if (col < tl.count) {
-              double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+              double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
 #pragma unroll
               for (int i = 0; i < MTW; ++i) {
                 if (i >= nmt) continue;
@@ -970,8 +971,8 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
                 d4 v;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = sc * double(acc[i][j][r]);
-                if (folded) v += *o;
-                *o = v;
+                if (folded) v += gld(o);
+                gst(o, v);
               }
             }
 #pragma unroll
@@ -988,7 +989,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
     for (int j = 0; j < NT; ++j) {
       const int col = col0 + 16 * j + c16;
       if (col >= tl.count) continue;
-      double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+      double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         if (i >= nmt) continue;
@@ -996,7 +997,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = f64 ? 4 * r + g : 4 * g + r;
-          out[base + row] = sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r]));
+          gst(out + base + row, sc * (FOLD ? acc64[FOLD ? i : 0][j][r] : double(acc[i][j][r])));
         }
       }
     }
@@ -1088,22 +1089,22 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
                                    : reinterpret_cast<const T*>(J.W);
     const T* __restrict__ P1 = F32 ? reinterpret_cast<const T*>(J.p1_32)
                                    : reinterpret_cast<const T*>(J.p1_64);
-    const int nact = J.tile_nact[I.tile];
+    const int nact = wuni(gld(J.tile_nact + I.tile));
     const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
     const int* srcb = J.tile_src + int64_t(I.tile) * kSlots * kTileN + I.col0;
     const int* kidp = J.slot_kid + I.tl.parity * kSlots;
     for (int ia = 0; ia <= nact; ++ia) {
       if (ia < nact) {
         // phase 1 of offset ia: this K-group's partial X into its slab
-        const int s = act[ia];
-        const int kid = kidp[s];
-        const int nr = J.svd_rpad[kid] >> 4;
-        const int64_t off = J.svd_off[kid];
+        const int s = wuni(int(gld(act + ia)));
+        const int kid = wuni(gld(kidp + s));
+        const int nr = wuni(gld(J.svd_rpad + kid)) >> 4;
+        const int64_t off = wuni(gld(J.svd_off + kid));
         T* const Pw = lds + buf * 4 * NC * XS + kg * NC * XS;
         const T* bp[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j)
-          bp[j] = Wp + int64_t(srcb[s * kTileN + 16 * j + c16]) * ld + 4 * g;
+          bp[j] = Wp + int64_t(gld(srcb + s * kTileN + 16 * j + c16)) * ld + 4 * g;
         if (D > 0) {  // the host launches D > 0 only where nck <= D
           // the K-group's whole share of the gathered multipoles in
           // registers at once (one memory latency per offset, not per
@@ -1115,9 +1116,9 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
           for (int u = 0; u < D; ++u) {
 #pragma unroll
             for (int j = 0; j < NT; ++j)
-              wv[u][j] = u < nck ? *reinterpret_cast<const T4*>(bp[j] + 16 * (kg + 4 * u))
+              wv[u][j] = u < nck ? gld(reinterpret_cast<const T4*>(bp[j] + 16 * (kg + 4 * u)))
                                  : T4{0, 0, 0, 0};
-            an[u] = u < nck ? *reinterpret_cast<const T4*>(a0 + int64_t(kg + 4 * u) * 256)
+            an[u] = u < nck ? gld(reinterpret_cast<const T4*>(a0 + int64_t(kg + 4 * u) * 256))
                             : T4{0, 0, 0, 0};
           }
           for (int i = 0; i < nr; ++i) {
@@ -1128,7 +1129,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
               const T* an0 = a0 + int64_t(i + 1) * KC * 256;
 #pragma unroll
               for (int u = 0; u < D; ++u)
-                an[u] = u < nck ? *reinterpret_cast<const T4*>(an0 + int64_t(kg + 4 * u) * 256)
+                an[u] = u < nck ? gld(reinterpret_cast<const T4*>(an0 + int64_t(kg + 4 * u) * 256))
                                 : T4{0, 0, 0, 0};
             }
             T4 x[NT];
@@ -1146,7 +1147,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
               const T* an0 = a0 + int64_t(i + 1) * KC * 256;
 #pragma unroll
               for (int u = 0; u < D; ++u)
-                an[u] = u < nck ? *reinterpret_cast<const T4*>(an0 + int64_t(kg + 4 * u) * 256)
+                an[u] = u < nck ? gld(reinterpret_cast<const T4*>(an0 + int64_t(kg + 4 * u) * 256))
                                 : T4{0, 0, 0, 0};
             }
 #pragma unroll
@@ -1172,23 +1173,24 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
           T4 bv[NT], av[kRP];
           if (kg < KC) {
 #pragma unroll
-            for (int j = 0; j < NT; ++j) bv[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * kg);
+            for (int j = 0; j < NT; ++j) bv[j] = gld(reinterpret_cast<const T4*>(bp[j] + 16 * kg));
 #pragma unroll
             for (int i = 0; i < kRP; ++i)
-              av[i] = i < np ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256)
+              av[i] = i < np ? gld(reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256))
                              : T4{0, 0, 0, 0};
           }
           for (int c = kg; c < KC; c += 4) {
             T4 bn[NT], an[kRP];
-            const bool more = c + 4 < KC;
+            const int cn = c + 4;
+            const bool more = cn < KC;
             if (more) {
 #pragma unroll
               for (int j = 0; j < NT; ++j)
-                bn[j] = *reinterpret_cast<const T4*>(bp[j] + 16 * (c + 4));
+                bn[j] = gld(reinterpret_cast<const T4*>(bp[j] + 16 * cn));
 #pragma unroll
               for (int i = 0; i < kRP; ++i)
                 an[i] = i < np
-                            ? *reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + c + 4) * 256)
+                            ? gld(reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + cn) * 256))
                             : T4{0, 0, 0, 0};
             }
 #pragma unroll
@@ -1227,7 +1229,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
   }
 }
 
-template <typename T, int MTW, int NT>
+template <typename T, int MTW, int NT, int NCW>
 __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
                                       const StepTab* __restrict__ tab, const T* const lds,
                                       int wg) {
@@ -1243,7 +1245,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     const JobDev& J = *I.J;
     const M2LTile tl = I.tl;
     const int MT = J.mt, ld = J.ld, XS = J.xs;
-    const int mt0 = (I.mb * 4 + wg) * MTW;
+    const int mt0 = (I.mb * NCW + wg) * MTW;
     const int nmt = mt0 < MT ? min(MTW, MT - mt0) : 0;
     const T* __restrict__ P2 = F32 ? reinterpret_cast<const T*>(J.p2_32)
                                    : reinterpret_cast<const T*>(J.p2_64);
@@ -1252,7 +1254,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     for (int i = 0; i < MTW; ++i)
 #pragma unroll
       for (int j = 0; j < NT; ++j) acc[i][j] = T4{0, 0, 0, 0};
-    const int nact = J.tile_nact[I.tile];
+    const int nact = wuni(gld(J.tile_nact + I.tile));
     bool folded = false;
     const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
     const int* kidp = J.slot_kid + tl.parity * kSlots;
@@ -1260,10 +1262,10 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
       if (ia > 0 && nmt > 0) {
         // phase 2 of offset ia - 1 from the buffer the producers filled
         const int ic = ia - 1;
-        const int kid = kidp[act[ic]];
-        const int nr = J.svd_rpad[kid] >> 4;
-        const int nst = (J.svd_rank[kid] - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
-        const int64_t off = J.svd_off[kid];
+        const int kid = wuni(gld(kidp + gld(act + ic)));
+        const int nr = wuni(gld(J.svd_rpad + kid)) >> 4;
+        const int nst = (wuni(gld(J.svd_rank + kid)) - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
+        const int64_t off = wuni(gld(J.svd_off + kid));
         const T* const P = lds + (buf ^ 1) * 4 * NC * XS;
         const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
         for (int c = 0; c < nr; ++c) {
@@ -1283,7 +1285,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
 #pragma unroll
           for (int i = 0; i < MTW; ++i) {
             if (i >= nmt) continue;
-            const T4 av = *reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256);
+            const T4 av = gld(reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256));
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
               if (st >= ns) continue;
@@ -1301,7 +1303,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
           for (int j = 0; j < NT; ++j) {
             const int col = I.col0 + 16 * j + c16;
             if (col < tl.count) {
-              double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+              double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
 #pragma unroll
               for (int i = 0; i < MTW; ++i) {
                 if (i >= nmt) continue;
@@ -1309,8 +1311,8 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
                 d4 v;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = sc * double(acc[i][j][r]);
-                if (folded) v += *o;
-                *o = v;
+                if (folded) v += gld(o);
+                gst(o, v);
               }
             }
 #pragma unroll
@@ -1328,7 +1330,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     for (int j = 0; j < NT; ++j) {
       const int col = I.col0 + 16 * j + c16;
       if (col >= tl.count) continue;
-      double* out = J.Loc + int64_t(J.tgt[tl.first + col]) * ld;
+      double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         if (i >= nmt) continue;
@@ -1336,24 +1338,24 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = F32 ? 4 * g + r : 4 * r + g;
-          out[base + row] = sc * double(acc[i][j][r]);
+          gst(out + base + row, sc * double(acc[i][j][r]));
         }
       }
     }
   }
 }
 
-template <typename T, int MTW, int NT, int D>
-__global__ __launch_bounds__(512, FMM_M2L_SVD_WS_WAVES) void m2l_svd_ws_kernel(
+template <typename T, int MTW, int NT, int D, int NCW>
+__global__ __launch_bounds__(64 * (4 + NCW), FMM_M2L_SVD_WS_WAVES) void m2l_svd_ws_kernel(
     const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* const lds = reinterpret_cast<T*>(lds_raw);
   // the role is uniform per wavefront: a scalar branch, no lane masking
-  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int wave = wuni(int(threadIdx.x >> 6));
   if (wave < 4)
     svd_ws_produce<T, NT, D>(jobs, tab, lds, wave);
   else
-    svd_ws_consume<T, MTW, NT>(jobs, tab, lds, wave - 4);
+    svd_ws_consume<T, MTW, NT, NCW>(jobs, tab, lds, wave - 4);
 }
 
 // M-tiles per wavefront for the compressed kernel: the whole output in one
@@ -1381,13 +1383,12 @@ size_t m2l_svd_lds_bytes(int xs, bool fp32) {
 // Whether the warp-specialised kernel runs (FP32, FP64); it needs the
 // 4-wavefront M-blocking (NWV 4).
 #ifndef FMM_M2L_SVD_WS_F32
-#define FMM_M2L_SVD_WS_F32 0
+#define FMM_M2L_SVD_WS_F32 1
 #endif
 #ifndef FMM_M2L_SVD_WS_F64
 #define FMM_M2L_SVD_WS_F64 1
 #endif
-static_assert(!FMM_M2L_SVD_WS_F32 || svd_nwv(true) == 4, "warp-specialised FP32 needs NWV 4");
-static_assert(!FMM_M2L_SVD_WS_F64 || svd_nwv(false) == 4, "warp-specialised FP64 needs NWV 4");
+// With it, NWV counts the consumer wavefronts (the workgroup has 4 more).
 
 template <typename T, int FOLD>
 static void launch_svd_mtw(int mtw, int kc, const JobDev* jobs, const StepTab* tab, int grid,
@@ -1396,24 +1397,25 @@ static void launch_svd_mtw(int mtw, int kc, const JobDev* jobs, const StepTab* t
   constexpr bool WS = sizeof(T) == 4 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
   if (WS) {
     constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
+    constexpr int WB = 64 * (4 + NW);
     if (D > 0 && (kc + 3) / 4 <= D) {
       switch (mtw) {
-        case 1: m2l_svd_ws_kernel<T, 1, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
-        case 2: m2l_svd_ws_kernel<T, 2, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
-        case 3: m2l_svd_ws_kernel<T, 3, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
-        case 4: m2l_svd_ws_kernel<T, 4, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
-        case 5: m2l_svd_ws_kernel<T, 5, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
-        default: m2l_svd_ws_kernel<T, 6, NT, D><<<grid, 512, lds, s>>>(jobs, tab); break;
+        case 1: m2l_svd_ws_kernel<T, 1, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+        case 2: m2l_svd_ws_kernel<T, 2, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+        case 3: m2l_svd_ws_kernel<T, 3, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+        case 4: m2l_svd_ws_kernel<T, 4, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+        case 5: m2l_svd_ws_kernel<T, 5, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+        default: m2l_svd_ws_kernel<T, 6, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
       }
       return;
     }
     switch (mtw) {
-      case 1: m2l_svd_ws_kernel<T, 1, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
-      case 2: m2l_svd_ws_kernel<T, 2, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
-      case 3: m2l_svd_ws_kernel<T, 3, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
-      case 4: m2l_svd_ws_kernel<T, 4, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
-      case 5: m2l_svd_ws_kernel<T, 5, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
-      default: m2l_svd_ws_kernel<T, 6, NT, 0><<<grid, 512, lds, s>>>(jobs, tab); break;
+      case 1: m2l_svd_ws_kernel<T, 1, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 2: m2l_svd_ws_kernel<T, 2, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 3: m2l_svd_ws_kernel<T, 3, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 4: m2l_svd_ws_kernel<T, 4, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 5: m2l_svd_ws_kernel<T, 5, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
+      default: m2l_svd_ws_kernel<T, 6, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
     }
     return;
   }
