@@ -80,6 +80,21 @@ int fmm_plan_set_m2l_tolerance(fmm_plan_t plan, double eps);
  * deterministic for any interval.  Returns FMM_ERR_ARG outside 0..189. */
 int fmm_plan_set_m2l_fold_interval(fmm_plan_t plan, int offsets);
 
+/* Work split of the compressed M2L (both SVD modes): each 64-target tile's
+ * far offsets are taken in `parts` consecutive ranges, one work item each
+ * (1..4; 0 restores the default).  Part 0 accumulates into the local
+ * expansions, parts 1.. into partial FP64 buffers the plan allocates
+ * ((parts - 1) x the M2L levels' local expansions), added back in part order
+ * right after the M2L, so results are deterministic for a given split.  By
+ * default the split is chosen from the tile count and the workgroups the
+ * device holds at once, so that the last round of workgroups is not left
+ * mostly empty (1 when the tiles alone fill many rounds, or when the
+ * buffers would exceed 2 GiB).  Different splits sum in different orders:
+ * results agree to rounding.  Returns FMM_ERR_ARG outside 0..4. */
+int fmm_plan_set_m2l_split(fmm_plan_t plan, int parts);
+/* The split in use (1 in the dense modes). */
+int fmm_plan_m2l_split(fmm_plan_t plan, int* parts);
+
 /* Compressed-M2L facts of the plan's current order and tolerance (host
  * struct; computes the truncated operators if needed).  rank[c] is the number
  * of singular values kept for canonical operator c; weighted_rank the mean

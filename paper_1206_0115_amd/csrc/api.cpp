@@ -30,6 +30,28 @@ StepTab one_job(int items, int level = 0) {
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// Offset ranges per compressed-M2L tile.  Every tile's item runs all of its
+// far offsets, so with few items the last round of resident workgroups is
+// mostly empty (1M particles at order 7: 1184 items on 512 slots, the last
+// 30% of the launch at 30% occupancy).  K ranges per tile make K times as
+// many items of 1/K the length; K minimises the rounds ceil(items K / slots)
+// / K (in tile lengths), among K whose partial buffers fit the budget.
+static int auto_parts(int64_t items, int64_t slots, size_t part_bytes) {
+  if (items <= 0 || items >= 6 * slots) return 1;
+  constexpr size_t kBudget = size_t(2) << 30;
+  int best = 1;
+  double best_cost = double((items + slots - 1) / slots);
+  for (int k = 2; k <= 4; ++k) {
+    if (size_t(k - 1) * part_bytes > kBudget) break;
+    const double cost = double((items * k + slots - 1) / slots) / k;
+    if (cost < 0.98 * best_cost) {
+      best = k;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 void upload_job(fmm_plan_s* p, hipStream_t s) {
   const int h = p->height;
   const OpSet* op = p->ops;
@@ -72,6 +94,36 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   }
   J.ntiles = int(p->ntiles);
   J.has_far = h >= 3;
+  // compressed M2L split (targets are the cells of levels 2 .. h-1)
+  int parts = 1;
+  const int64_t lrows = h >= 3 ? int64_t(p->ncell_total) - int64_t(p->lev[2].off) : 0;
+  const size_t part_bytes = sizeof(double) * size_t(lrows) * op->ld;
+  if (p->svd && h >= 3 && m2l_svd_splits(fp32)) {
+    parts = p->m2l_split > 0 ? p->m2l_split
+                             : auto_parts(int64_t(p->ntiles) * J.nmb,
+                                          m2l_svd_slots(p->order, fp32, J.xs), part_bytes);
+  }
+  const size_t want = size_t(parts - 1) * part_bytes;
+  bool split_oom = false;  // reported once the job below is consistent
+  if (p->locx_bytes != want) {
+    if (p->LocX) p->free_block(p->LocX);
+    p->LocX = nullptr;
+    p->locx_bytes = 0;
+    if (want) {
+      try {
+        p->LocX = static_cast<double*>(p->alloc(want));
+        p->locx_bytes = want;
+      } catch (const FmmError&) {
+        parts = 1;
+        split_oom = p->m2l_split > 1;
+      }
+    }
+  }
+  p->m2l_parts = parts;
+  J.m2l_parts = parts;
+  J.locx_first = h >= 3 ? int64_t(p->lev[2].off) : 0;
+  J.locx_rows = lrows;
+  J.LocX = p->LocX;
   J.geo = {p->lo[0], p->lo[1], p->lo[2], p->L / double(int64_t(1) << (h - 1)), h - 1};
   J.W = p->W;
   J.W32 = p->W32;
@@ -109,7 +161,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
     // rows cast to FP32: levels 2 .. h-2 when P2M writes the leaves in FP32
     p->tab_h[kTabCast] = one_job(int((p->w32_leaf ? p->lev[h - 1].off : p->ncell_total + 1) -
                                      p->lev[2].off));
-    p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb);
+    p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb * parts);
     for (int st = 0; st + 4 <= h; ++st) {
       p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
       // L2L items are the parents (level 2 + st) of the cells it updates
@@ -121,6 +173,9 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   FMM_HIP_CHECK(hipMemcpyAsync(p->job_d, &p->job_h, sizeof(JobDev), hipMemcpyHostToDevice, s));
   FMM_HIP_CHECK(hipMemcpyAsync(p->tab_d, p->tab_h, sizeof(p->tab_h), hipMemcpyHostToDevice, s));
   FMM_HIP_CHECK(hipStreamSynchronize(s));
+  if (split_oom)
+    throw FmmError{FMM_ERR_OOM, "no device memory for the partial buffers of the M2L split; "
+                                "the plan runs unsplit"};
 }
 }  // namespace fmm
 
@@ -389,6 +444,32 @@ int fmm_plan_set_m2l_fold_interval(fmm_plan_t p, int offsets) {
     fmm::upload_job(p, p->last_stream);
     return FMM_OK;
   });
+}
+
+int fmm_plan_set_m2l_split(fmm_plan_t p, int parts) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (parts < 0 || parts > 4)
+    return fail(FMM_ERR_ARG, "M2L split must be in [0, 4], got " + std::to_string(parts));
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
+    const int prev = p->m2l_split;
+    p->m2l_split = parts;
+    try {
+      fmm::upload_job(p, p->last_stream);
+    } catch (...) {
+      p->m2l_split = prev;
+      throw;
+    }
+    return FMM_OK;
+  });
+}
+
+int fmm_plan_m2l_split(fmm_plan_t p, int* parts) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (!parts) return fail(FMM_ERR_ARG, "parts is NULL");
+  *parts = p->m2l_parts;
+  return FMM_OK;
 }
 
 int fmm_plan_set_m2l_tolerance(fmm_plan_t p, double eps) {

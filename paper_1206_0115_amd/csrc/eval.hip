@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_util.h"
 #include "fmm_internal.h"
@@ -53,20 +54,20 @@ __global__ __launch_bounds__(256) void p2m_kernel(const JobDev* __restrict__ job
     const double ia = 2.0 / J.geo.w;
     double acc[L];
     for (int e = 0; e < L; ++e) acc[e] = 0.0;
-    const int s0 = J.leaf_start[a], s1 = J.leaf_start[a + 1];
+    const int s0 = wuni(gld(J.leaf_start + a)), s1 = wuni(gld(J.leaf_start + a + 1));
     __syncthreads();
     for (int base = s0; base < s1; base += kP2MChunk) {
       const int cnt = min(kP2MChunk, s1 - base);
       for (int e = t; e < 3 * cnt; e += nt) {
         const int j = e / 3, d = e % 3;
         const int i = base + j;
-        const double x = d == 0 ? J.px[i] : (d == 1 ? J.py[i] : J.pz[i]);
+        const double x = gld(d == 0 ? J.px + i : (d == 1 ? J.py + i : J.pz + i));
         const double u = (x - c[d]) * ia;
         double T[L];
         T[0] = 1.0;
         if (L > 1) T[1] = u;
         for (int n = 2; n < L; ++n) T[n] = 2.0 * u * T[n - 1] - T[n - 2];
-        const double f = d == 0 ? J.qs[i] : 1.0;
+        const double f = d == 0 ? gld(J.qs + i) : 1.0;
         for (int m = 0; m < L; ++m) {
           double v = 0.0;
           for (int n = 0; n < L; ++n) v += C[m * L + n] * T[n];
@@ -86,13 +87,13 @@ __global__ __launch_bounds__(256) void p2m_kernel(const JobDev* __restrict__ job
       // mixed modes keep the leaf multipoles in FP32 only
       float* out = J.W32 + row;
       if (owner)
-        for (int m3 = 0; m3 < L; ++m3) out[(m1 * L + m2) * L + m3] = float(acc[m3]);
-      for (int e = L * L * L + t; e < J.ld; e += nt) out[e] = 0.f;
+        for (int m3 = 0; m3 < L; ++m3) gst(out + (m1 * L + m2) * L + m3, float(acc[m3]));
+      for (int e = L * L * L + t; e < J.ld; e += nt) gst(out + e, 0.f);
     } else {
       double* out = J.W + row;
       if (owner)
-        for (int m3 = 0; m3 < L; ++m3) out[(m1 * L + m2) * L + m3] = acc[m3];
-      for (int e = L * L * L + t; e < J.ld; e += nt) out[e] = 0.0;
+        for (int m3 = 0; m3 < L; ++m3) gst(out + (m1 * L + m2) * L + m3, acc[m3]);
+      for (int e = L * L * L + t; e < J.ld; e += nt) gst(out + e, 0.0);
     }
   }
 }
@@ -398,37 +399,107 @@ __device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float q, 
   fz += s * dz;
 }
 
-template <int KP>
-__device__ __forceinline__ void p2p_f64_leaf(const JobDev& J, int a, double* sx, double* sy,
-                                             double* sz, double* sq) {
+// Next chunk (up to 64 consecutive particles of one source leaf) of the near
+// list, in slot order: advances (sl, jb, j1) and returns false past the last
+// one.  Lane s < 27 holds the particle range [nj0, nj1) of near slot s (empty
+// for an absent neighbour).  Start from sl = -1, jb = j1 = 0.  No memory
+// access: the loads of the chunk in flight are not waited for.
+__device__ __forceinline__ bool near_next(int nj0, int nj1, int& sl, int& jb, int& j1) {
+  jb += 64;
+  while (jb >= j1) {
+    if (++sl >= 27) return false;
+    jb = __builtin_amdgcn_readlane(nj0, sl);
+    j1 = __builtin_amdgcn_readlane(nj1, sl);
+  }
+  return true;
+}
+
+// One target leaf.  The source chunks pass through LDS one at a time; the
+// next chunk's loads are in flight while the current one is computed.  FP32:
+// the pair difference is taken in FP64 and rounded once (a relative error of
+// 2^-24 of the distance itself, however close the pair), r^2, the reciprocal
+// (square) root and the products are FP32, and the partial sums over one
+// source leaf are kept in FP32 and folded into FP64 accumulators.  Pairs are
+// taken in the same order as one leaf, one chunk at a time.
+typedef double src4 __attribute__((ext_vector_type(4)));  // x, y, z, q of one source
+
+template <int KP, bool F32>
+__device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
   const int lane = threadIdx.x;
-  const double *px = J.px, *py = J.py, *pz = J.pz, *qs = J.qs;
-  const int t0 = J.leaf_start[a], nt = J.leaf_start[a + 1] - t0;
+  const double *px = J.px, *py = J.py, *pz = J.pz;
+  const int t0 = wuni(gld(J.leaf_start + a)), nt = wuni(gld(J.leaf_start + a + 1)) - t0;
   const int P = p2p_groups(nt);
   const int S = 64 / P;
   const int split = lane / P;
+  int nj0 = 0, nj1 = 0;
+  if (lane < 27) {
+    const int b = gld(J.near + 27 * a + lane);
+    if (b >= 0) {
+      nj0 = gld(J.leaf_start + b);
+      nj1 = gld(J.leaf_start + b + 1);
+    }
+  }
+  // the source charge as stored (FP32 or FP64), widened when staged
+  typedef typename std::conditional<F32, float, double>::type QT;
+  const QT* qsrc = F32 ? reinterpret_cast<const QT*>(J.prel) : reinterpret_cast<const QT*>(J.qs);
+  const int qstride = F32 ? 4 : 1, qoff = F32 ? 3 : 0;
   for (int tb = 0; tb < nt; tb += 64) {
     const int ti = tb + (lane % P);
     const bool valid = ti < nt;
     const int it = t0 + (valid ? ti : 0);
-    const double xi = px[it], yi = py[it], zi = pz[it];
+    const double xi = gld(px + it), yi = gld(py + it), zi = gld(pz + it);
     double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int sl = 0; sl < 27; ++sl) {
-      const int b = J.near[27 * a + sl];
-      if (b < 0) continue;
-      const int j0 = J.leaf_start[b], j1 = J.leaf_start[b + 1];
-      for (int jb = j0; jb < j1; jb += 64) {
-        const int cnt = min(64, j1 - jb);
-        __syncthreads();
-        if (lane < cnt) {
-          sx[lane] = px[jb + lane];
-          sy[lane] = py[jb + lane];
-          sz[lane] = pz[jb + lane];
-          sq[lane] = qs[jb + lane];
+    float p32 = 0.f, x32 = 0.f, y32 = 0.f, z32 = 0.f;
+    int sl = -1, jb = 0, j1 = 0;
+    bool have = near_next(nj0, nj1, sl, jb, j1);
+    int cnt = have ? min(64, j1 - jb) : 0;
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    QT rq = 0;
+    if (lane < cnt) {
+      rx = gld(px + jb + lane);
+      ry = gld(py + jb + lane);
+      rz = gld(pz + jb + lane);
+      rq = gld(qsrc + int64_t(jb + lane) * qstride + qoff);
+    }
+    while (have) {
+      const int ccnt = cnt, csl = sl;
+      __syncthreads();  // the previous chunk's reads are done
+      src[lane] = src4{rx, ry, rz, double(rq)};
+      __syncthreads();
+      have = near_next(nj0, nj1, sl, jb, j1);
+      cnt = have ? min(64, j1 - jb) : 0;
+      if (lane < cnt) {
+        rx = gld(px + jb + lane);
+        ry = gld(py + jb + lane);
+        rz = gld(pz + jb + lane);
+        rq = gld(qsrc + int64_t(jb + lane) * qstride + qoff);
+      }
+      if (F32) {
+        int kk = split;
+        for (; kk + S < ccnt; kk += 2 * S) {  // two sources per pass, same order
+          const src4 u = src[kk], v = src[kk + S];
+          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), float(u.w), p32, x32,
+                       y32, z32);
+          pair_f32<KP>(float(xi - v.x), float(yi - v.y), float(zi - v.z), float(v.w), p32, x32,
+                       y32, z32);
         }
-        __syncthreads();
-        for (int kk = split; kk < cnt; kk += S)
-          pair_f64<KP>(xi - sx[kk], yi - sy[kk], zi - sz[kk], sq[kk], ph, fx, fy, fz);
+        if (kk < ccnt) {
+          const src4 u = src[kk];
+          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), float(u.w), p32, x32,
+                       y32, z32);
+        }
+        if (!have || sl != csl) {  // the source leaf ends here
+          ph += double(p32);
+          fx += double(x32);
+          fy += double(y32);
+          fz += double(z32);
+          p32 = x32 = y32 = z32 = 0.f;
+        }
+      } else {
+        for (int kk = split; kk < ccnt; kk += S) {
+          const src4 u = src[kk];
+          pair_f64<KP>(xi - u.x, yi - u.y, zi - u.z, u.w, ph, fx, fy, fz);
+        }
       }
     }
     for (int o = P; o < 64; o <<= 1) {
@@ -439,104 +510,57 @@ __device__ __forceinline__ void p2p_f64_leaf(const JobDev& J, int a, double* sx,
     }
     if (valid && split == 0) {
       const int i = t0 + ti;
-      const double qi = qs[i];
-      J.phi_n[i] = ph;
-      J.f_n[3 * i] = qi * fx;
-      J.f_n[3 * i + 1] = qi * fy;
-      J.f_n[3 * i + 2] = qi * fz;
+      const double qi = gld(J.qs + i);
+      gst(J.phi_n + i, ph);
+      gst(J.f_n + 3 * i, qi * fx);
+      gst(J.f_n + 3 * i + 1, qi * fy);
+      gst(J.f_n + 3 * i + 2, qi * fz);
     }
   }
 }
 
 __global__ __launch_bounds__(64) void p2p_f64_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
-  __shared__ double sx[64], sy[64], sz[64], sq[64];
+  __shared__ src4 src[64];
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
     if (J.kernel == 2)
-      p2p_f64_leaf<2>(J, a, sx, sy, sz, sq);
+      p2p_leaf<2, false>(J, a, src);
     else
-      p2p_f64_leaf<1>(J, a, sx, sy, sz, sq);
+      p2p_leaf<1, false>(J, a, src);
     __syncthreads();
-  }
-}
-
-// FP32 near field.  The pair difference is taken in FP64 (full rate on this
-// chip) and rounded once, so it carries a relative error of 2^-24 of the
-// distance itself however close the pair is; r^2, the reciprocal (square)
-// root and the products are FP32; partial sums over one source leaf are kept
-// in FP32 and folded into FP64 accumulators.
-template <int KP>
-__device__ __forceinline__ void p2p_f32_leaf(const JobDev& J, int a, double* sx, double* sy,
-                                             double* sz, float* sq) {
-  const int lane = threadIdx.x;
-  const double *px = J.px, *py = J.py, *pz = J.pz;
-  const int t0 = J.leaf_start[a], nt = J.leaf_start[a + 1] - t0;
-  const int P = p2p_groups(nt);
-  const int S = 64 / P;
-  const int split = lane / P;
-  for (int tb = 0; tb < nt; tb += 64) {
-    const int ti = tb + (lane % P);
-    const bool valid = ti < nt;
-    const int it = t0 + (valid ? ti : 0);
-    const double xi = px[it], yi = py[it], zi = pz[it];
-    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int sl = 0; sl < 27; ++sl) {
-      const int b = J.near[27 * a + sl];
-      if (b < 0) continue;
-      const int j0 = J.leaf_start[b], j1 = J.leaf_start[b + 1];
-      float p32 = 0.f, x32 = 0.f, y32 = 0.f, z32 = 0.f;
-      for (int jb = j0; jb < j1; jb += 64) {
-        const int cnt = min(64, j1 - jb);
-        __syncthreads();
-        if (lane < cnt) {
-          sx[lane] = px[jb + lane];
-          sy[lane] = py[jb + lane];
-          sz[lane] = pz[jb + lane];
-          sq[lane] = J.prel[jb + lane].w;
-        }
-        __syncthreads();
-        for (int kk = split; kk < cnt; kk += S)
-          pair_f32<KP>(float(xi - sx[kk]), float(yi - sy[kk]), float(zi - sz[kk]), sq[kk], p32,
-                       x32, y32, z32);
-      }
-      ph += double(p32);
-      fx += double(x32);
-      fy += double(y32);
-      fz += double(z32);
-    }
-    for (int o = P; o < 64; o <<= 1) {
-      ph += __shfl_xor(ph, o, 64);
-      fx += __shfl_xor(fx, o, 64);
-      fy += __shfl_xor(fy, o, 64);
-      fz += __shfl_xor(fz, o, 64);
-    }
-    if (valid && split == 0) {
-      const int i = t0 + ti;
-      const double qi = J.qs[i];
-      J.phi_n[i] = ph;
-      J.f_n[3 * i] = qi * fx;
-      J.f_n[3 * i + 1] = qi * fy;
-      J.f_n[3 * i + 2] = qi * fz;
-    }
   }
 }
 
 __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
-  __shared__ double sx[64], sy[64], sz[64];
-  __shared__ float sq[64];
+  __shared__ src4 src[64];
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
     if (J.kernel == 2)
-      p2p_f32_leaf<2>(J, a, sx, sy, sz, sq);
+      p2p_leaf<2, true>(J, a, src);
     else
-      p2p_f32_leaf<1>(J, a, sx, sy, sz, sq);
+      p2p_leaf<1, true>(J, a, src);
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------- compressed M2L parts
+// Loc += the partial local expansions of M2L parts 1 .. K-1, added in part
+// order (one FP64 sum per element, the same order every run).
+__global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__ jobs) {
+  const JobDev& J = jobs[0];
+  const int64_t n = J.locx_rows * J.ld;
+  double* loc = J.Loc + J.locx_first * J.ld;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    double v = gld(loc + e);
+    for (int k = 1; k < J.m2l_parts; ++k) v += gld(J.LocX + (k - 1) * n + e);
+    gst(loc + e, v);
   }
 }
 
@@ -753,9 +777,15 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
     if (forked && !FMM_FORK_AFTER_M2L) fork_near();
     {
       Timed t(FMM_TIME_M2L, s);
-      if (p->ntiles > 0)
+      if (p->ntiles > 0) {
         launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
                     p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
+        if (p->m2l_parts > 1) {
+          const int64_t n = p->job_h.locx_rows * p->job_h.ld;
+          loc_sum_kernel<<<unsigned(std::min<int64_t>((n + 255) / 256, 8192)), 256, 0, s>>>(J);
+          FMM_HIP_CHECK(hipGetLastError());
+        }
+      }
     }
     if (forked && FMM_FORK_AFTER_M2L) fork_near();
     for (int st = 0; st + 4 <= h; ++st)

@@ -124,6 +124,8 @@ enum {
 
 int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
 int m2l_svd_nmb(int mt, bool fp32);  // work items per tile for the compressed M2L
+int m2l_svd_slots(int order, bool fp32, int xs);  // compressed M2L workgroups resident at once
+bool m2l_svd_splits(bool fp32);          // whether the compressed kernel takes m2l_parts
 // LDS bytes of one compressed-M2L workgroup for a slab stride of xs values
 size_t m2l_svd_lds_bytes(int xs, bool fp32);
 int m2l_svd_xs(int rmax_pad, bool fp32);  // that slab stride for a padded rank
@@ -185,6 +187,10 @@ struct fmm_plan_s {
   int64_t w64_rows = 0;            // rows allocated in W (all cells + 1, or levels < h-1)
   bool w32_leaf = false;           // mixed modes: leaf multipoles only in W32
   int m2l_fold = 0;                // compressed FP32 fold interval (0: by order)
+  int m2l_split = 0;               // compressed M2L offset ranges per tile (0: auto)
+  int m2l_parts = 1;               // the split in use
+  double* LocX = nullptr;          // partial local expansions of parts 1..
+  size_t locx_bytes = 0;
   hipStream_t side = nullptr;      // the near-field branch of the forked schedule
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool in_flight = false;

@@ -41,6 +41,12 @@ struct JobDev {
   int kernel;  // p of the kernel |x - y|^-p (1 or 2)
   int w32_leaf;  // leaf multipoles live in W32 only (W holds levels < h-1)
   int fold_every;  // compressed FP32 M2L: far offsets between FP64 folds
+  // compressed M2L split: each tile's far offsets in m2l_parts consecutive
+  // ranges, one work item each; part 0 writes Loc, part p > 0 the rows
+  // (p - 1) * locx_rows + (target row - locx_first) of LocX
+  int m2l_parts;
+  int64_t locx_first, locx_rows;
+  double* LocX;
   LeafGeom geo;
   double* W;
   float* W32;

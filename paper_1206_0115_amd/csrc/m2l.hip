@@ -1041,7 +1041,23 @@ struct SvdItem {
   const JobDev* J;
   M2LTile tl;
   int tile, mb, col0;
+  int part;  // offset range [ia0, ia1) of the tile's active offsets
 };
+
+__device__ inline void svd_part_range(const SvdItem& I, int nact, int& ia0, int& ia1) {
+  const int K = I.J->m2l_parts;
+  ia0 = int(int64_t(I.part) * nact / K);
+  ia1 = int(int64_t(I.part + 1) * nact / K);
+}
+
+// The FP64 row that target column col of the item accumulates into: the
+// cell's local expansion for part 0, else the part's own row of LocX.
+__device__ inline double* svd_out_row(const SvdItem& I, int col) {
+  const JobDev& J = *I.J;
+  const int64_t t = gld(J.tgt + I.tl.first + col);
+  if (I.part == 0) return J.Loc + t * J.ld;
+  return J.LocX + (int64_t(I.part - 1) * J.locx_rows + (t - J.locx_first)) * J.ld;
+}
 
 // Item `it` of the launch; false when its N-group holds no target column
 // (the same for the whole workgroup).
@@ -1058,8 +1074,11 @@ __device__ inline bool svd_item(const JobDev* __restrict__ jobs, const StepTab* 
   const JobDev& J = jobs[tab->job[k]];
   const int local = b - tab->start[k];
   I.J = &J;
-  I.tile = local / J.nmb;
-  const int rem = local % J.nmb;
+  const int per_tile = J.nmb * J.m2l_parts;
+  I.tile = local / per_tile;
+  const int rem0 = local % per_tile;
+  I.part = rem0 / J.nmb;
+  const int rem = rem0 % J.nmb;
   I.mb = rem / NG;
   I.col0 = NC * (rem % NG);
   I.tl = J.tiles[I.tile];
@@ -1093,8 +1112,10 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
     const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
     const int* srcb = J.tile_src + int64_t(I.tile) * kSlots * kTileN + I.col0;
     const int* kidp = J.slot_kid + I.tl.parity * kSlots;
-    for (int ia = 0; ia <= nact; ++ia) {
-      if (ia < nact) {
+    int ia0, ia1;
+    svd_part_range(I, nact, ia0, ia1);
+    for (int ia = ia0; ia <= ia1; ++ia) {
+      if (ia < ia1) {
         // phase 1 of offset ia: this K-group's partial X into its slab
         const int s = wuni(int(gld(act + ia)));
         const int kid = wuni(gld(kidp + s));
@@ -1258,8 +1279,10 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     bool folded = false;
     const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
     const int* kidp = J.slot_kid + tl.parity * kSlots;
-    for (int ia = 0; ia <= nact; ++ia) {
-      if (ia > 0 && nmt > 0) {
+    int ia0, ia1;
+    svd_part_range(I, nact, ia0, ia1);
+    for (int ia = ia0; ia <= ia1; ++ia) {
+      if (ia > ia0 && nmt > 0) {
         // phase 2 of offset ia - 1 from the buffer the producers filled
         const int ic = ia - 1;
         const int kid = wuni(gld(kidp + gld(act + ic)));
@@ -1295,7 +1318,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
             }
           }
         }
-        if (F32 && ((ic + 1) % J.fold_every == 0 || ic == nact - 1)) {
+        if (F32 && ((ic - ia0 + 1) % J.fold_every == 0 || ic == ia1 - 1)) {
           // fold into this item's rows of Loc (scaled; the first fold
           // stores, later ones add): no other workgroup touches these rows
           const double sc = J.scale[tl.level];
@@ -1303,7 +1326,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
           for (int j = 0; j < NT; ++j) {
             const int col = I.col0 + 16 * j + c16;
             if (col < tl.count) {
-              double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
+              double* out = svd_out_row(I, col);
 #pragma unroll
               for (int i = 0; i < MTW; ++i) {
                 if (i >= nmt) continue;
@@ -1330,7 +1353,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     for (int j = 0; j < NT; ++j) {
       const int col = I.col0 + 16 * j + c16;
       if (col >= tl.count) continue;
-      double* out = J.Loc + int64_t(gld(J.tgt + tl.first + col)) * ld;
+      double* out = svd_out_row(I, col);
 #pragma unroll
       for (int i = 0; i < MTW; ++i) {
         if (i >= nmt) continue;
@@ -1427,6 +1450,40 @@ static void launch_svd_mtw(int mtw, int kc, const JobDev* jobs, const StepTab* t
     case 5: m2l_svd_kernel<T, 5, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
     default: m2l_svd_kernel<T, 6, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
   }
+}
+
+bool m2l_svd_splits(bool fp32) { return fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64; }
+
+template <typename T>
+static const void* svd_ws_fn(int mtw, bool staged) {
+  constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4);
+  constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
+#define FMM_WS_FN(M)                                                                     \
+  return staged ? reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, M, NT, D, NW>)    \
+                : reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, M, NT, 0, NW>)
+  switch (mtw) {
+    case 1: FMM_WS_FN(1);
+    case 2: FMM_WS_FN(2);
+    case 3: FMM_WS_FN(3);
+    case 4: FMM_WS_FN(4);
+    case 5: FMM_WS_FN(5);
+    default: FMM_WS_FN(6);
+  }
+#undef FMM_WS_FN
+}
+
+int m2l_svd_slots(int order, bool fp32, int xs) {
+  const int l3 = order * order * order, kc = (l3 + 15) / 16;
+  const int mtw = m2l_svd_mtw(kc, fp32);
+  const int D = fp32 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
+  const bool staged = D > 0 && (kc + 3) / 4 <= D;
+  const void* f = fp32 ? svd_ws_fn<float>(mtw, staged) : svd_ws_fn<double>(mtw, staged);
+  int per_cu = 0, dev = 0, cus = 0;
+  FMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, f, 64 * (4 + svd_nwv(fp32)), m2l_svd_lds_bytes(xs, fp32)));
+  FMM_HIP_CHECK(hipGetDevice(&dev));
+  FMM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return std::max(1, per_cu) * std::max(1, cus);
 }
 
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,

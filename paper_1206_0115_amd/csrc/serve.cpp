@@ -236,6 +236,7 @@ bool fmm_server_s::launch_batch() {
   const int nj = int(reqs.size());
   for (int j = 0; j < nj; ++j) {
     jobs[j] = reqs[j]->plan->job_h;
+    jobs[j].m2l_parts = 1;  // a batch spreads its tiles over many plans already
     calls[j] = CallDev{reqs[j]->q, reqs[j]->phi, reqs[j]->f, nullptr, nullptr, nullptr, nullptr};
   }
 

@@ -103,6 +103,8 @@ def lib():
     L.fmm_plan_set_kernel.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
     L.fmm_plan_set_m2l_fold_interval.argtypes = [vp, i32]
+    L.fmm_plan_set_m2l_split.argtypes = [vp, i32]
+    L.fmm_plan_m2l_split.argtypes = [vp, ctypes.POINTER(i32)]
     L.fmm_plan_svd_info.argtypes = [vp, ctypes.POINTER(SvdInfo)]
     L.fmm_plan_info.argtypes = [vp, ctypes.POINTER(FmmInfo)]
     L.fmm_plan_export.argtypes = [vp, i32, i32, vp, sz]
@@ -203,6 +205,16 @@ class Plan:
         """Far offsets between FP64 folds in the compressed mixed mode (0 =
         the default for the order)."""
         _check(lib().fmm_plan_set_m2l_fold_interval(self._h, int(offsets)))
+
+    def set_m2l_split(self, parts: int):
+        """Far-offset ranges per tile of the compressed M2L (1..4; 0 = chosen
+        from the tile count and the device's resident workgroups)."""
+        _check(lib().fmm_plan_set_m2l_split(self._h, int(parts)))
+
+    def m2l_split(self) -> int:
+        out = ctypes.c_int(0)
+        _check(lib().fmm_plan_m2l_split(self._h, ctypes.byref(out)))
+        return int(out.value)
 
     def svd_info(self) -> SvdInfo:
         out = SvdInfo()

@@ -53,6 +53,8 @@ def test_calls_reject_null_plan():
     assert lib.fmm_plan_set_schedule(None, fmm.FMM_SCHEDULE_SERIAL) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_kernel(None, fmm.FMM_KERNEL_INV_R2) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_m2l_fold_interval(None, 4) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_set_m2l_split(None, 2) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_m2l_split(None, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_set_step_timing_events(9, None, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_set_step_timing_events(fmm.FMM_TIME_P2P, fake, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_set_step_timing_events(fmm.FMM_TIME_P2P, None, None) == fmm.FMM_OK

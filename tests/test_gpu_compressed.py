@@ -135,3 +135,44 @@ def test_fold_interval_trades_accuracy_and_is_checked():
     for bad in (-1, 190):
         with pytest.raises(fmm.FMMError):
             plan.set_m2l_fold_interval(bad)
+
+
+def test_m2l_split_agrees_with_unsplit_and_is_checked():
+    # each tile's far offsets in 1..4 ranges (parts 1.. accumulate in
+    # partial buffers added back in part order): the same sums regrouped, so
+    # FP64 agrees to rounding and FP32 within its folding error; every split
+    # is deterministic and matches the oracle's compressed FMM
+    pos, q = inputs.uniform_cube(40000, 1007)
+    h, l, eps = 5, 5, 1e-7
+    plan = fmm.Plan(dev(pos), h, l)
+    p64, f64 = [host(t) for t in plan.evaluate(dev(q))]
+    assert plan.m2l_split() == 1  # dense modes do not split
+    plan.set_m2l_tolerance(eps)
+    ops, _ = oracle.compressed_unit_ops(l, eps)
+    po, fo = oracle.Tree(pos, h).fmm(l, q, unit_ops=ops)
+    for mode, tol in (("fp64_svd", 1e-13), ("mixed_svd", 2e-7)):
+        plan.set_precision(mode)
+        plan.set_m2l_split(1)
+        assert plan.m2l_split() == 1
+        r1 = [host(t) for t in plan.evaluate(dev(q))]
+        for k in (2, 3, 4):
+            plan.set_m2l_split(k)
+            assert plan.m2l_split() == k
+            a = [host(t) for t in plan.evaluate(dev(q))]
+            b = [host(t) for t in plan.evaluate(dev(q))]
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            d = max(rel(a[0], r1[0]), rel(a[1], r1[1]))
+            eo = max(rel(a[0], po), rel(a[1], fo))
+            print(f"  {mode} split {k}: vs unsplit {d:.2e}, vs oracle {eo:.2e}", flush=True)
+            assert d <= tol
+            assert eo <= (1e-10 if mode == "fp64_svd" else 1e-6)
+        plan.set_m2l_split(0)
+        assert 1 <= plan.m2l_split() <= 4
+    for bad in (-1, 5):
+        with pytest.raises(fmm.FMMError):
+            plan.set_m2l_split(bad)
+    # switching back to a dense mode releases the split
+    plan.set_precision("fp64")
+    assert plan.m2l_split() == 1
+    again = [host(t) for t in plan.evaluate(dev(q))]
+    assert np.array_equal(again[0], p64) and np.array_equal(again[1], f64)
