@@ -73,7 +73,7 @@ int fmm_plan_set_m2l_tolerance(fmm_plan_t plan, double eps);
 
 /* Fold interval of the compressed mixed mode (FMM_MIXED_SVD): the FP32 MFMA
  * partial sums of a target tile are added into its FP64 local expansions
- * after every `offsets` far offsets (1..189; 0 restores the default, 8 up to
+ * after every `offsets` far offsets (1..189; 0 restores the default, 16 up to
  * order 7 and 2 above).  Shorter intervals are more accurate and slower:
  * at order 7 on the uniform cube, 1 / 4 / 8 / 16 give a relative L2 error
  * against FP64 of 2.3e-7 / 2.9e-7 / 3.5e-7 / 4.4e-7.  Results stay

@@ -550,17 +550,23 @@ __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ 
 }
 
 // ------------------------------------------------- compressed M2L parts
-// Loc += the partial local expansions of M2L parts 1 .. K-1, added in part
-// order (one FP64 sum per element, the same order every run).
-__global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__ jobs) {
-  const JobDev& J = jobs[0];
-  const int64_t n = J.locx_rows * J.ld;
-  double* loc = J.Loc + J.locx_first * J.ld;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    double v = gld(loc + e);
-    for (int k = 1; k < J.m2l_parts; ++k) v += gld(J.LocX + (k - 1) * n + e);
-    gst(loc + e, v);
+// Item = row of levels >= 2 of a job whose compressed M2L ran in parts:
+// Loc += the partial local expansions of parts 1 .. K-1, added in part order
+// (one FP64 sum per element, the same order every run).
+__global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__ jobs,
+                                                      const StepTab* __restrict__ tab) {
+  FOR_ITEMS(tab) {
+    const int k = step_find(*tab, it_);
+    const JobDev& J = jobs[tab->job[k]];
+    const int64_t r = it_ - tab->start[k];
+    const int64_t n = J.locx_rows * J.ld;
+    double* loc = J.Loc + (J.locx_first + r) * J.ld;
+    const double* x = J.LocX + r * J.ld;
+    for (int e = threadIdx.x; e < J.ld; e += 256) {
+      double v = gld(loc + e);
+      for (int p = 1; p < J.m2l_parts; ++p) v += gld(x + (p - 1) * n + e);
+      gst(loc + e, v);
+    }
   }
 }
 
@@ -690,6 +696,9 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
     case kStepCast:
       cast_kernel<<<g, 256, 0, s>>>(jobs, tab);
       break;
+    case kStepLocSum:
+      loc_sum_kernel<<<g, 256, 0, s>>>(jobs, tab);
+      break;
     case kStepM2L:
       launch_m2l_step(L, fp32, jobs, tab, grid, s);
       break;
@@ -780,11 +789,9 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
       if (p->ntiles > 0) {
         launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
                     p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
-        if (p->m2l_parts > 1) {
-          const int64_t n = p->job_h.locx_rows * p->job_h.ld;
-          loc_sum_kernel<<<unsigned(std::min<int64_t>((n + 255) / 256, 8192)), 256, 0, s>>>(J);
-          FMM_HIP_CHECK(hipGetLastError());
-        }
+        if (p->tab_h[kTabLocSum].start[1] > 0)
+          launch_step(kStepLocSum, L, false, J, p->tab_d + kTabLocSum, nullptr,
+                      p->tab_h[kTabLocSum].start[1], s);
       }
     }
     if (forked && FMM_FORK_AFTER_M2L) fork_near();

@@ -119,7 +119,8 @@ enum {
   kTabM2L = 2,   // one item per (M2L tile, M-block)
   kTabM2M = 3,   // + step s: parents at level h-2-s
   kTabL2L = 3 + kMaxHeight,  // + step s: children at level 3+s
-  kTabCount = 3 + 2 * kMaxHeight
+  kTabLocSum = 3 + 2 * kMaxHeight,  // M2L parts: one item per row of levels >= 2
+  kTabCount = 4 + 2 * kMaxHeight
 };
 
 int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)

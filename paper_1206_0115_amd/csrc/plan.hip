@@ -529,19 +529,34 @@ __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int na = 0;
-    unsigned long long np = 0;
-    for (int s = 0; s < kSlots; ++s) {
-      const int k = npair[s];
-      if (!k) continue;
-      act[int64_t(tile) * kSlots + na++] = (unsigned char)s;
+  // active slots in ascending order: wavefront w compacts slots 64w .. 64w+63
+  // (a ballot prefix within it, the earlier wavefronts' counts before it)
+  __shared__ int wave_active[(kSlots + 63) / 64];
+  constexpr int kSlotWaves = (kSlots + 63) / 64;
+  static_assert(kSlotWaves * 64 <= kTileThreads, "one thread per slot");
+  const int s = threadIdx.x;
+  const int k = s < kSlots ? npair[s] : 0;
+  const uint64_t m = __ballot(k > 0);
+  if (wave < kSlotWaves && j == 0) wave_active[wave] = __popcll(m);
+  __syncthreads();
+  if (wave < kSlotWaves) {
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wave_active[w];
+    if (k > 0) {
+      const int pos = base + __popcll(m & ((uint64_t(1) << j) - 1));
+      act[int64_t(tile) * kSlots + pos] = (unsigned char)s;
       atomicAdd(&pairs_kid[slot_kid[T.parity * kSlots + s]], (unsigned long long)k);
-      np += k;
     }
-    nact[tile] = na;
-    atomicAdd(&pairs_level[T.level], np);
-    atomicAdd(active_total, (unsigned long long)na);
+    // pairs of this wavefront's slots, summed across its lanes
+    unsigned long long np = (unsigned long long)k;
+    for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o, 64);
+    if (j == 0 && np) atomicAdd(&pairs_level[T.level], np);
+    if (threadIdx.x == 0) {
+      int na = 0;
+      for (int w = 0; w < kSlotWaves; ++w) na += wave_active[w];
+      nact[tile] = na;
+      atomicAdd(active_total, (unsigned long long)na);
+    }
   }
 }
 
@@ -760,16 +775,25 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     FMM_HIP_CHECK(hipMemcpyAsync(hpc, pc, sizeof(int) * 8 * kMaxHeight, hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipStreamSynchronize(s));
     // finest level first: the largest tiles' work is scheduled before the
-    // coarse levels fill in the tail
+    // coarse levels fill in the tail.  Within a level the parities take
+    // turns: the k-th tile of every parity covers about the same region of
+    // space, so the eight run side by side (on one XCD, whose L2 then serves
+    // the source multipoles they share) instead of one parity sweeping the
+    // whole level after another.
     std::vector<M2LTile> tiles;
     for (int l = h - 1; l >= 2; --l) {
-      int64_t start = lev[l].off - lev[2].off;
+      int64_t start[8];
+      int kmax = 0;
+      start[0] = lev[l].off - lev[2].off;
       for (int par = 0; par < 8; ++par) {
-        const int c = hpc[8 * l + par];
-        for (int k = 0; k < c; k += kTileN)
-          tiles.push_back({l, par, int(start + k), std::min(kTileN, c - k)});
-        start += c;
+        if (par > 0) start[par] = start[par - 1] + hpc[8 * l + par - 1];
+        kmax = std::max(kmax, hpc[8 * l + par]);
       }
+      for (int k = 0; k < kmax; k += kTileN)
+        for (int par = 0; par < 8; ++par) {
+          const int c = hpc[8 * l + par];
+          if (k < c) tiles.push_back({l, par, int(start[par] + k), std::min(kTileN, c - k)});
+        }
     }
     p->ntiles = int64_t(tiles.size());
     p->tiles_host = tiles;

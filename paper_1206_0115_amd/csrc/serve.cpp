@@ -236,7 +236,6 @@ bool fmm_server_s::launch_batch() {
   const int nj = int(reqs.size());
   for (int j = 0; j < nj; ++j) {
     jobs[j] = reqs[j]->plan->job_h;
-    jobs[j].m2l_parts = 1;  // a batch spreads its tiles over many plans already
     calls[j] = CallDev{reqs[j]->q, reqs[j]->phi, reqs[j]->f, nullptr, nullptr, nullptr, nullptr};
   }
 
@@ -302,7 +301,13 @@ bool fmm_server_s::launch_batch() {
             [&](Request* r) {
               return far(r) && r->order == L && mixed(r) == (f32 != 0) && svd(r) == (cmp != 0);
             },
-            [](Request* r) { return int(r->plan->ntiles) * r->plan->job_h.nmb; }, lvl0);
+            [](Request* r) {
+              return int(r->plan->ntiles) * r->plan->job_h.nmb * r->plan->job_h.m2l_parts;
+            },
+            lvl0);
+  // the compressed M2L of plans that split it: partial sums back into Loc
+  add(kStepLocSum, 0, false, [&](Request* r) { return far(r) && r->plan->job_h.m2l_parts > 1; },
+      [](Request* r) { return int(r->plan->job_h.locx_rows); }, lvl0);
   for (int s = 0; s < steps; ++s)
     add(kStepL2L, maxo, false, [&](Request* r) { return r->h - 4 >= s; },
         [&](Request* r) { return int(r->plan->lev[2 + s].ncell); },
