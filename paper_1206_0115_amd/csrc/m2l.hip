@@ -1030,6 +1030,24 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #ifndef FMM_M2L_SVD_WS_STAGE_F64
 #define FMM_M2L_SVD_WS_STAGE_F64 0
 #endif
+// Whether a producer loads the first chunk of its next offset before the
+// barrier that ends the current one (streamed path), FP32 and FP64 (the FP64
+// registers would spill).
+#ifndef FMM_M2L_SVD_WS_XPRE_F32
+#define FMM_M2L_SVD_WS_XPRE_F32 1
+#endif
+#ifndef FMM_M2L_SVD_WS_XPRE_F64
+#define FMM_M2L_SVD_WS_XPRE_F64 0
+#endif
+// U fragments (M-tiles of rank chunk 0) a consumer loads for its next offset
+// before the barrier, FP32 and FP64 (measured at order 7: 0 to 6 within
+// noise, so off).
+#ifndef FMM_M2L_SVD_WS_CPRE_F32
+#define FMM_M2L_SVD_WS_CPRE_F32 0
+#endif
+#ifndef FMM_M2L_SVD_WS_CPRE_F64
+#define FMM_M2L_SVD_WS_CPRE_F64 0
+#endif
 #ifndef FMM_M2L_SVD_WS_APRE_F32
 #define FMM_M2L_SVD_WS_APRE_F32 0
 #endif
@@ -1048,6 +1066,32 @@ __device__ inline void svd_part_range(const SvdItem& I, int nact, int& ia0, int&
   const int K = I.J->m2l_parts;
   ia0 = int(int64_t(I.part) * nact / K);
   ia1 = int(int64_t(I.part + 1) * nact / K);
+}
+
+// Per active offset of an item, what both roles look up: the factor offset,
+// the slot (for the source columns), the rank chunks and the K-steps of the
+// last one.  Filled once per item into LDS, after the slabs, by all threads.
+struct SvdMeta {
+  int64_t off;
+  int s;
+  int nr_nst;  // nr | nst << 16
+};
+constexpr size_t kSvdMetaBytes = sizeof(SvdMeta) * kSlots;
+
+__device__ inline void svd_meta_fill(const SvdItem& I, int nact, SvdMeta* meta) {
+  const JobDev& J = *I.J;
+  int ia0, ia1;
+  svd_part_range(I, nact, ia0, ia1);
+  const unsigned char* act = J.tile_act + int64_t(I.tile) * kSlots;
+  const int* kidp = J.slot_kid + I.tl.parity * kSlots;
+  for (int t = threadIdx.x; t < ia1 - ia0; t += blockDim.x) {
+    const int sl = gld(act + ia0 + t);
+    const int kid = gld(kidp + sl);
+    const int nr = gld(J.svd_rpad + kid) >> 4;
+    const int nst = (gld(J.svd_rank + kid) - 16 * (nr - 1) + 3) >> 2;
+    meta[t] = SvdMeta{gld(J.svd_off + kid), sl, nr | (nst << 16)};
+  }
+  __syncthreads();
 }
 
 // The FP64 row that target column col of the item accumulates into: the
@@ -1087,7 +1131,8 @@ __device__ inline bool svd_item(const JobDev* __restrict__ jobs, const StepTab* 
 
 template <typename T, int NT, int D>
 __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
-                                      const StepTab* __restrict__ tab, T* const lds, int kg) {
+                                      const StepTab* __restrict__ tab, T* const lds,
+                                      SvdMeta* const meta, int kg) {
   typedef typename Vec4<T>::type T4;
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int NC = 16 * NT;
@@ -1095,6 +1140,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
   // staged path: the next rank tile's factor fragments load while this one
   // computes (1) or after it (0)
   constexpr bool kAPre = F32 ? FMM_M2L_SVD_WS_APRE_F32 : FMM_M2L_SVD_WS_APRE_F64;
+  constexpr bool kXPre = F32 ? FMM_M2L_SVD_WS_XPRE_F32 : FMM_M2L_SVD_WS_XPRE_F64;
   const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
   const int total = step_total(*tab);
   int buf = 0;
@@ -1114,18 +1160,36 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
     const int* kidp = J.slot_kid + I.tl.parity * kSlots;
     int ia0, ia1;
     svd_part_range(I, nact, ia0, ia1);
+    svd_meta_fill(I, nact, meta);
+    // each lane's source cells, one offset ahead
+    int src_next[NT];
+    if (ia0 < ia1) {
+      const int s0 = wuni(meta[0].s);
+#pragma unroll
+      for (int j = 0; j < NT; ++j) src_next[j] = gld(srcb + s0 * kTileN + 16 * j + c16);
+    }
+    // the first chunk of the next offset, loaded before the barrier
+    T4 pre_bv[NT], pre_av[kRP];
+    bool have_pre = false;
     for (int ia = ia0; ia <= ia1; ++ia) {
       if (ia < ia1) {
         // phase 1 of offset ia: this K-group's partial X into its slab
-        const int s = wuni(int(gld(act + ia)));
-        const int kid = wuni(gld(kidp + s));
-        const int nr = wuni(gld(J.svd_rpad + kid)) >> 4;
-        const int64_t off = wuni(gld(J.svd_off + kid));
+        const SvdMeta md = meta[ia - ia0];
+        const int nr = wuni(md.nr_nst) & 0xffff;
+        const int64_t off = wuni(md.off);
+        int src[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) src[j] = src_next[j];
+        if (ia + 1 < ia1) {
+          const int sn = wuni(meta[ia + 1 - ia0].s);
+#pragma unroll
+          for (int j = 0; j < NT; ++j) src_next[j] = gld(srcb + sn * kTileN + 16 * j + c16);
+        }
         T* const Pw = lds + buf * 4 * NC * XS + kg * NC * XS;
         const T* bp[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j)
-          bp[j] = Wp + int64_t(gld(srcb + s * kTileN + 16 * j + c16)) * ld + 4 * g;
+          bp[j] = Wp + int64_t(src[j]) * ld + 4 * g;
         if (D > 0) {  // the host launches D > 0 only where nck <= D
           // the K-group's whole share of the gathered multipoles in
           // registers at once (one memory latency per offset, not per
@@ -1182,7 +1246,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
               }
             }
           }
-        } else
+        } else {
         for (int i0 = 0; i0 < nr; i0 += kRP) {
           const int np = min(kRP, nr - i0);
           const T* a0 = P1 + off + (int64_t(i0) * KC) * 256 + lane * 4;
@@ -1192,7 +1256,12 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
 #pragma unroll
             for (int j = 0; j < NT; ++j) x[i][j] = T4{0, 0, 0, 0};
           T4 bv[NT], av[kRP];
-          if (kg < KC) {
+          if (kXPre && i0 == 0 && have_pre) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bv[j] = pre_bv[j];
+#pragma unroll
+            for (int i = 0; i < kRP; ++i) av[i] = pre_av[i];
+          } else if (kg < KC) {
 #pragma unroll
             for (int j = 0; j < NT; ++j) bv[j] = gld(reinterpret_cast<const T4*>(bp[j] + 16 * kg));
 #pragma unroll
@@ -1243,6 +1312,22 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
               }
             }
         }
+        have_pre = false;
+        if (kXPre && ia + 1 < ia1 && kg < KC) {
+          const SvdMeta mn = meta[ia + 1 - ia0];
+          const int npn = min(kRP, wuni(mn.nr_nst) & 0xffff);
+          const T* an0 = P1 + wuni(mn.off) + lane * 4;
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            pre_bv[j] = gld(reinterpret_cast<const T4*>(Wp + int64_t(src_next[j]) * ld + 4 * g +
+                                                        16 * kg));
+#pragma unroll
+          for (int i = 0; i < kRP; ++i)
+            pre_av[i] = i < npn ? gld(reinterpret_cast<const T4*>(an0 + (int64_t(i) * KC + kg) * 256))
+                                : T4{0, 0, 0, 0};
+          have_pre = true;
+        }
+        }
       }
       buf ^= 1;
       __syncthreads();
@@ -1253,7 +1338,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
 template <typename T, int MTW, int NT, int NCW>
 __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
                                       const StepTab* __restrict__ tab, const T* const lds,
-                                      int wg) {
+                                      SvdMeta* const meta, int wg) {
   typedef typename Vec4<T>::type T4;
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int NC = 16 * NT;
@@ -1281,14 +1366,19 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     const int* kidp = J.slot_kid + tl.parity * kSlots;
     int ia0, ia1;
     svd_part_range(I, nact, ia0, ia1);
+    svd_meta_fill(I, nact, meta);
+    // the first U fragments (rank chunk 0) of the offset consumed next,
+    // loaded before the barrier that precedes it
+    constexpr int kCP = F32 ? FMM_M2L_SVD_WS_CPRE_F32 : FMM_M2L_SVD_WS_CPRE_F64;
+    T4 cpre[kCP > 0 ? kCP : 1];
     for (int ia = ia0; ia <= ia1; ++ia) {
       if (ia > ia0 && nmt > 0) {
         // phase 2 of offset ia - 1 from the buffer the producers filled
         const int ic = ia - 1;
-        const int kid = wuni(gld(kidp + gld(act + ic)));
-        const int nr = wuni(gld(J.svd_rpad + kid)) >> 4;
-        const int nst = (wuni(gld(J.svd_rank + kid)) - 16 * (nr - 1) + 3) >> 2;  // K-steps, last chunk
-        const int64_t off = wuni(gld(J.svd_off + kid));
+        const SvdMeta md = meta[ic - ia0];
+        const int nrs = wuni(md.nr_nst);
+        const int nr = nrs & 0xffff, nst = nrs >> 16;  // rank chunks; K-steps of the last
+        const int64_t off = wuni(md.off);
         const T* const P = lds + (buf ^ 1) * 4 * NC * XS;
         const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
         for (int c = 0; c < nr; ++c) {
@@ -1308,7 +1398,9 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
 #pragma unroll
           for (int i = 0; i < MTW; ++i) {
             if (i >= nmt) continue;
-            const T4 av = gld(reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256));
+            const T4 av = i < kCP && c == 0
+                              ? cpre[i < kCP ? i : 0]
+                              : gld(reinterpret_cast<const T4*>(a2 + (int64_t(i) * nr + c) * 256));
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
               if (st >= ns) continue;
@@ -1344,6 +1436,15 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
           folded = true;
         }
       }
+      if (kCP > 0 && ia < ia1 && nmt > 0) {
+        const SvdMeta mn = meta[ia - ia0];
+        const int nrn = wuni(mn.nr_nst) & 0xffff;
+        const T* a2n = P2 + wuni(mn.off) + int64_t(mt0) * nrn * 256 + lane * 4;
+#pragma unroll
+        for (int i = 0; i < kCP; ++i)
+          cpre[i] = i < nmt ? gld(reinterpret_cast<const T4*>(a2n + int64_t(i) * nrn * 256))
+                            : T4{0, 0, 0, 0};
+      }
       buf ^= 1;
       __syncthreads();
     }
@@ -1372,13 +1473,17 @@ template <typename T, int MTW, int NT, int D, int NCW>
 __global__ __launch_bounds__(64 * (4 + NCW), FMM_M2L_SVD_WS_WAVES) void m2l_svd_ws_kernel(
     const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* const lds = reinterpret_cast<T*>(lds_raw);
+  // the per-offset table first (a fixed size, so jobs of different slab
+  // widths share one launch), then the two sets of slabs
+  static_assert(kSvdMetaBytes % 16 == 0, "slabs stay 16-byte aligned");
+  SvdMeta* const meta = reinterpret_cast<SvdMeta*>(lds_raw);
+  T* const lds = reinterpret_cast<T*>(lds_raw + kSvdMetaBytes);
   // the role is uniform per wavefront: a scalar branch, no lane masking
   const int wave = wuni(int(threadIdx.x >> 6));
   if (wave < 4)
-    svd_ws_produce<T, NT, D>(jobs, tab, lds, wave);
+    svd_ws_produce<T, NT, D>(jobs, tab, lds, meta, wave);
   else
-    svd_ws_consume<T, MTW, NT, NCW>(jobs, tab, lds, wave - 4);
+    svd_ws_consume<T, MTW, NT, NCW>(jobs, tab, lds, meta, wave - 4);
 }
 
 // M-tiles per wavefront for the compressed kernel: the whole output in one
@@ -1400,7 +1505,8 @@ int m2l_svd_nmb(int mt, bool fp32) {
 int m2l_svd_xs(int rmax_pad, bool fp32) { return rmax_pad + (fp32 ? 4 : 2); }
 
 size_t m2l_svd_lds_bytes(int xs, bool fp32) {
-  return size_t(2) * 4 * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double));
+  return size_t(2) * 4 * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double)) +
+         kSvdMetaBytes;
 }
 
 // Whether the warp-specialised kernel runs (FP32, FP64); it needs the
