@@ -1039,6 +1039,14 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #ifndef FMM_M2L_SVD_WS_XPRE_F64
 #define FMM_M2L_SVD_WS_XPRE_F64 0
 #endif
+// Chunks a producer keeps in flight ahead of the one it computes (1 or 2),
+// FP32 and FP64.
+#ifndef FMM_M2L_SVD_WS_LOOK_F32
+#define FMM_M2L_SVD_WS_LOOK_F32 1
+#endif
+#ifndef FMM_M2L_SVD_WS_LOOK_F64
+#define FMM_M2L_SVD_WS_LOOK_F64 1
+#endif
 // U fragments (M-tiles of rank chunk 0) a consumer loads for its next offset
 // before the barrier, FP32 and FP64 (measured at order 7: 0 to 6 within
 // noise, so off).
@@ -1141,6 +1149,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
   // computes (1) or after it (0)
   constexpr bool kAPre = F32 ? FMM_M2L_SVD_WS_APRE_F32 : FMM_M2L_SVD_WS_APRE_F64;
   constexpr bool kXPre = F32 ? FMM_M2L_SVD_WS_XPRE_F32 : FMM_M2L_SVD_WS_XPRE_F64;
+  constexpr int kLook = F32 ? FMM_M2L_SVD_WS_LOOK_F32 : FMM_M2L_SVD_WS_LOOK_F64;
   const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
   const int total = step_total(*tab);
   int buf = 0;
@@ -1269,9 +1278,21 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
               av[i] = i < np ? gld(reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg) * 256))
                              : T4{0, 0, 0, 0};
           }
+          // chunks in flight: c + 4 (kLook = 1) or also c + 8 (kLook = 2)
+          T4 b1[kLook > 1 ? NT : 1], a1[kLook > 1 ? kRP : 1];
+          if (kLook > 1 && kg + 4 < KC) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+              b1[kLook > 1 ? j : 0] = gld(reinterpret_cast<const T4*>(bp[j] + 16 * (kg + 4)));
+#pragma unroll
+            for (int i = 0; i < kRP; ++i)
+              a1[kLook > 1 ? i : 0] =
+                  i < np ? gld(reinterpret_cast<const T4*>(a0 + (int64_t(i) * KC + kg + 4) * 256))
+                         : T4{0, 0, 0, 0};
+          }
           for (int c = kg; c < KC; c += 4) {
             T4 bn[NT], an[kRP];
-            const int cn = c + 4;
+            const int cn = c + 4 * kLook;
             const bool more = cn < KC;
             if (more) {
 #pragma unroll
@@ -1290,7 +1311,18 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
                   if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
-            if (more) {
+            if (kLook > 1) {
+#pragma unroll
+              for (int j = 0; j < NT; ++j) {
+                bv[j] = b1[kLook > 1 ? j : 0];
+                if (more) b1[kLook > 1 ? j : 0] = bn[j];
+              }
+#pragma unroll
+              for (int i = 0; i < kRP; ++i) {
+                av[i] = a1[kLook > 1 ? i : 0];
+                if (more) a1[kLook > 1 ? i : 0] = an[i];
+              }
+            } else if (more) {
 #pragma unroll
               for (int j = 0; j < NT; ++j) bv[j] = bn[j];
 #pragma unroll
