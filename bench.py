@@ -451,6 +451,34 @@ def main():
                     "64 B per particle read and written + l^3 x 8 B per leaf read"),
     }
 
+    def second_kernel(prec, steps):
+        """The 1/r^2 kernel on the same workload and mode: plan + evaluate +
+        release per step, and its error against its own FP64 evaluation."""
+        with torch.cuda.stream(stream):
+            ref = fmm.Plan(pos_d, h, l, "fp64", stream=stream, kernel="inv_r2")
+            pr, fr = ref.evaluate(q_d, stream=stream)
+            stream.synchronize()
+            pr, fr = pr.cpu().numpy(), fr.cpu().numpy()
+            ref.release()
+            p = fmm.Plan(pos_d, h, l, prec, stream=stream, kernel="inv_r2")
+            pm, fm = p.evaluate(q_d, stream=stream)
+            stream.synchronize()
+            err = max(rel(pm.cpu().numpy(), pr), rel(fm.cpu().numpy(), fr))
+            p.release()
+            for i in range(steps + 1):
+                if i == 1:
+                    stream.synchronize()
+                    t0 = time.perf_counter()
+                p = fmm.Plan(pos_d, h, l, prec, stream=stream, kernel="inv_r2")
+                p.evaluate(q_d, phi, frc, stream=stream)
+                p.release()
+            stream.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3 / steps
+        return {"kernel": "1/r^2", "precision": prec, "ms_per_step": round(dt, 4),
+                "particles_per_s": round(n / (dt / 1e3), 1), "rel_l2_vs_fp64": err}
+
+    kernel2 = second_kernel(precision, max(5, args.steps // 2))
+
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(kind, n, h, l, seed, args.cpu_budget)
@@ -487,6 +515,7 @@ def main():
         "svd_weighted_rank": round(svd.weighted_rank, 3),
         "roofline": roof,
         "kernels": kernels,
+        "second_kernel": kernel2,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

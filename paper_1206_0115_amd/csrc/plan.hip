@@ -318,13 +318,27 @@ __global__ void set_int_kernel(int* __restrict__ p, int v) {
 // h-1-floor(t/3) on, t the highest bit in which k[i] and k[i-1] differ.  One
 // pass therefore gives the segment flags of every level l = 0 .. h-2, stored
 // level-major: flags[l * nl + i].
-__global__ void level_flags_kernel(const uint64_t* __restrict__ lk, int64_t nl, int h,
-                                   int64_t* __restrict__ flags) {
+// Also counts the cells of every level >= 2 by child parity (the M2L tile
+// layout), so that one read-back after the scan brings both.
+__global__ __launch_bounds__(256) void level_flags_kernel(const uint64_t* __restrict__ lk,
+                                                          int64_t nl, int h,
+                                                          int64_t* __restrict__ flags,
+                                                          int* __restrict__ pcount) {
+  __shared__ int hist[8 * kMaxHeight];
+  for (int e = threadIdx.x; e < 8 * kMaxHeight; e += blockDim.x) hist[e] = 0;
+  __syncthreads();
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nl) return;
-  int first = 0;  // leaf 0 starts a cell at every level
-  if (i > 0) first = h - 1 - (63 - __clzll(lk[i] ^ lk[i - 1])) / 3;
-  for (int l = 0; l < h - 1; ++l) flags[int64_t(l) * nl + i] = l >= first ? 1 : 0;
+  if (i < nl) {
+    int first = 0;  // leaf 0 starts a cell at every level
+    if (i > 0) first = h - 1 - (63 - __clzll(lk[i] ^ lk[i - 1])) / 3;
+    for (int l = 0; l < h - 1; ++l) flags[int64_t(l) * nl + i] = l >= first ? 1 : 0;
+    // cells starting at this leaf, levels 2 .. h-1 (every leaf is a cell)
+    for (int l = first > 2 ? first : 2; l < h; ++l)
+      atomicAdd(&hist[8 * l + int((lk[i] >> (3 * (h - 1 - l))) & 7u)], 1);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 8 * kMaxHeight; e += blockDim.x)
+    if (hist[e]) atomicAdd(&pcount[e], hist[e]);
 }
 
 struct LevelOut {
@@ -455,15 +469,10 @@ struct CellLevels {
 };
 
 // Cells of levels >= 2 (global ids g from off[2]): sort key (level - 2, child
-// parity) for the M2L target order, the gid as value, and per-(level, parity)
-// counts.
+// parity) for the M2L target order, the gid as value.
 __global__ __launch_bounds__(256) void parity_keys_kernel(CellLevels c, int h,
                                                           uint64_t* __restrict__ key,
-                                                          int* __restrict__ val,
-                                                          int* __restrict__ counts) {
-  __shared__ int hist[8 * kMaxHeight];
-  for (int e = threadIdx.x; e < 8 * kMaxHeight; e += blockDim.x) hist[e] = 0;
-  __syncthreads();
+                                                          int* __restrict__ val) {
   const int64_t m = c.off[h] - c.off[2];
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j < m) {
@@ -473,11 +482,7 @@ __global__ __launch_bounds__(256) void parity_keys_kernel(CellLevels c, int h,
     const int par = int(c.keys[l][g - c.off[l]] & 7u);
     key[j] = uint64_t((l - 2) << 3 | par);
     val[j] = int(g);
-    atomicAdd(&hist[8 * l + par], 1);
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 8 * kMaxHeight; e += blockDim.x)
-    if (hist[e]) atomicAdd(&counts[e], hist[e]);
 }
 
 // One workgroup of eight wavefronts per tile.  Lane j of every wavefront owns
@@ -661,13 +666,18 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     int64_t* fl = static_cast<int64_t*>(talloc(sizeof(int64_t) * tot));
     int64_t* S = static_cast<int64_t*>(talloc(sizeof(int64_t) * tot));
     int64_t* cnt = static_cast<int64_t*>(talloc(sizeof(int64_t) * kMaxHeight));
-    level_flags_kernel<<<grid_for(nl, 256), 256, 0, s>>>(lk, nl, h, fl);
+    int* pc = static_cast<int*>(talloc(sizeof(int) * 8 * kMaxHeight));
+    FMM_HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(int) * 8 * kMaxHeight, s));
+    level_flags_kernel<<<grid_for(nl, 256), 256, 0, s>>>(lk, nl, h, fl, pc);
     FMM_HIP_CHECK(hipGetLastError());
     exclusive_scan<int64_t>(fl, S, tot, s, tmp);
     level_counts_kernel<<<1, 64, 0, s>>>(fl, S, nl, h, cnt);
     FMM_HIP_CHECK(hipGetLastError());
     int64_t* hcnt = reinterpret_cast<int64_t*>(stage + 128);  // pinned
     FMM_HIP_CHECK(hipMemcpyAsync(hcnt, cnt, sizeof(int64_t) * (h - 1), hipMemcpyDeviceToHost, s));
+    // per-(level, parity) cell counts for the M2L tiles, in the same read-back
+    FMM_HIP_CHECK(hipMemcpyAsync(stage + 512, pc, sizeof(int) * 8 * kMaxHeight,
+                                 hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipStreamSynchronize(s));
     LevelOut out{};
     // every count first: level l's loop iteration sizes level l+1's parents.
@@ -763,17 +773,14 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     uint64_t* pk2 = static_cast<uint64_t*>(talloc(sizeof(uint64_t) * ntgt));
     int* pv1 = static_cast<int*>(talloc(sizeof(int) * ntgt));
     int* pv2 = static_cast<int*>(talloc(sizeof(int) * ntgt));
-    int* pc = static_cast<int*>(talloc(sizeof(int) * 8 * kMaxHeight));
-    FMM_HIP_CHECK(hipMemsetAsync(pc, 0, sizeof(int) * 8 * kMaxHeight, s));
-    parity_keys_kernel<<<grid_for(ntgt, 256), 256, 0, s>>>(cl, h, pk1, pv1, pc);
+    parity_keys_kernel<<<grid_for(ntgt, 256), 256, 0, s>>>(cl, h, pk1, pv1);
     FMM_HIP_CHECK(hipGetLastError());
     int kbits = 3;
     while ((1 << (kbits - 3)) < h - 2) ++kbits;
     radix_sort(pk1, pv1, pk2, pv2, ntgt, kbits, s, tmp);
     FMM_HIP_CHECK(hipMemcpyAsync(p->tgt, pv1, sizeof(int) * ntgt, hipMemcpyDeviceToDevice, s));
-    int* hpc = reinterpret_cast<int*>(stage + 512);  // pinned, 8 x kMaxHeight
-    FMM_HIP_CHECK(hipMemcpyAsync(hpc, pc, sizeof(int) * 8 * kMaxHeight, hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    // counts read back with the level counts (level_flags_kernel)
+    const int* hpc = reinterpret_cast<const int*>(stage + 512);
     // finest level first: the largest tiles' work is scheduled before the
     // coarse levels fill in the tail.  Within a level the parities take
     // turns: the k-th tile of every parity covers about the same region of
@@ -799,7 +806,8 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     p->tiles_host = tiles;
     if (p->ntiles > 0) {
       // every earlier transfer through the staging buffer has completed (the
-      // synchronisation above), so it may grow here; layout from 4 KiB on:
+      // level-count read-back waited for them), so it may grow here; layout
+      // from 4 KiB on:
       // level tables, level offsets, then the tiles
       const size_t tbytes = sizeof(M2LTile) * tiles.size();
       stage = static_cast<char*>(pinned_staging(4096 + 2048 + tbytes));
