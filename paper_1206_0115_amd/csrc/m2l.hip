@@ -1520,16 +1520,40 @@ __global__ __launch_bounds__(64 * (4 + NCW), FMM_M2L_SVD_WS_WAVES) void m2l_svd_
 
 // M-tiles per wavefront for the compressed kernel: the whole output in one
 // M-block when it fits NWV x 6 tiles (phase 1 then runs once per N-group).
-static int m2l_svd_mtw(int mt, bool fp32) {
+// Whether the warp-specialised kernel runs (FP32, FP64).
+#ifndef FMM_M2L_SVD_WS_F32
+#define FMM_M2L_SVD_WS_F32 1
+#endif
+#ifndef FMM_M2L_SVD_WS_F64
+#define FMM_M2L_SVD_WS_F64 1
+#endif
+// Warp-specialised kernel: when NWV consumers of up to 6 M-tiles cannot
+// hold all l^3 rows (l >= 8), 8 consumers of up to 8 M-tiles take them in
+// one M-block instead of several, each of which would repeat phase 1.
+#ifndef FMM_M2L_SVD_WIDE
+#define FMM_M2L_SVD_WIDE 1
+#endif
+constexpr int kSvdWideMtw = 8;
+
+struct SvdShape {
+  int ncw, mtw;  // consumer wavefronts (compressed kernel: wavefronts), M-tiles each
+};
+
+static SvdShape m2l_svd_shape(int mt, bool fp32) {
   const int nw = svd_nwv(fp32);
   for (int w = 1; w <= 6; ++w)
-    if (nw * w >= mt) return w;
-  return 6;
+    if (nw * w >= mt) return {nw, w};
+  const bool ws = fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
+  if (ws && FMM_M2L_SVD_WIDE && nw < 8)
+    for (int w = 4; w <= kSvdWideMtw; ++w)
+      if (8 * w >= mt) return {8, w};
+  return ws && FMM_M2L_SVD_WIDE && nw < 8 ? SvdShape{8, kSvdWideMtw} : SvdShape{nw, 6};
 }
 
+
 int m2l_svd_nmb(int mt, bool fp32) {
-  const int w = m2l_svd_mtw(mt, fp32), nw = svd_nwv(fp32);
-  return (mt + nw * w - 1) / (nw * w) * (4 / svd_nt(fp32));
+  const SvdShape sh = m2l_svd_shape(mt, fp32);
+  return (mt + sh.ncw * sh.mtw - 1) / (sh.ncw * sh.mtw) * (4 / svd_nt(fp32));
 }
 
 // Slab row stride: the padded rank plus 16 bytes, so that consecutive target
@@ -1541,21 +1565,26 @@ size_t m2l_svd_lds_bytes(int xs, bool fp32) {
          kSvdMetaBytes;
 }
 
-// Whether the warp-specialised kernel runs (FP32, FP64); it needs the
-// 4-wavefront M-blocking (NWV 4).
-#ifndef FMM_M2L_SVD_WS_F32
-#define FMM_M2L_SVD_WS_F32 1
-#endif
-#ifndef FMM_M2L_SVD_WS_F64
-#define FMM_M2L_SVD_WS_F64 1
-#endif
-// With it, NWV counts the consumer wavefronts (the workgroup has 4 more).
+// With the warp-specialised kernel, NWV counts the consumer wavefronts (the
+// workgroup has 4 more).
 
 template <typename T, int FOLD>
-static void launch_svd_mtw(int mtw, int kc, const JobDev* jobs, const StepTab* tab, int grid,
+static void launch_svd_mtw(SvdShape sh, int kc, const JobDev* jobs, const StepTab* tab, int grid,
                            size_t lds, hipStream_t s) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
   constexpr bool WS = sizeof(T) == 4 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
+  const int mtw = sh.mtw;
+  if (WS && sh.ncw == 8 && NW != 8) {  // wide: one M-block for l >= 8
+    constexpr int WB = 64 * 12;
+    switch (mtw) {
+      case 4: m2l_svd_ws_kernel<T, 4, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 5: m2l_svd_ws_kernel<T, 5, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 6: m2l_svd_ws_kernel<T, 6, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
+      case 7: m2l_svd_ws_kernel<T, 7, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
+      default: m2l_svd_ws_kernel<T, kSvdWideMtw, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
+    }
+    return;
+  }
   if (WS) {
     constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
     constexpr int WB = 64 * (4 + NW);
@@ -1593,9 +1622,19 @@ static void launch_svd_mtw(int mtw, int kc, const JobDev* jobs, const StepTab* t
 bool m2l_svd_splits(bool fp32) { return fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64; }
 
 template <typename T>
-static const void* svd_ws_fn(int mtw, bool staged) {
+static const void* svd_ws_fn(SvdShape sh, bool staged) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4);
   constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
+  const int mtw = sh.mtw;
+  if (sh.ncw == 8 && NW != 8) {
+    switch (mtw) {
+      case 4: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 4, NT, 0, 8>);
+      case 5: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 5, NT, 0, 8>);
+      case 6: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 6, NT, 0, 8>);
+      case 7: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 7, NT, 0, 8>);
+      default: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, kSvdWideMtw, NT, 0, 8>);
+    }
+  }
 #define FMM_WS_FN(M)                                                                     \
   return staged ? reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, M, NT, D, NW>)    \
                 : reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, M, NT, 0, NW>)
@@ -1612,13 +1651,13 @@ static const void* svd_ws_fn(int mtw, bool staged) {
 
 int m2l_svd_slots(int order, bool fp32, int xs) {
   const int l3 = order * order * order, kc = (l3 + 15) / 16;
-  const int mtw = m2l_svd_mtw(kc, fp32);
+  const SvdShape sh = m2l_svd_shape(kc, fp32);
   const int D = fp32 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
-  const bool staged = D > 0 && (kc + 3) / 4 <= D;
-  const void* f = fp32 ? svd_ws_fn<float>(mtw, staged) : svd_ws_fn<double>(mtw, staged);
+  const bool staged = D > 0 && (kc + 3) / 4 <= D && sh.ncw == svd_nwv(fp32);
+  const void* f = fp32 ? svd_ws_fn<float>(sh, staged) : svd_ws_fn<double>(sh, staged);
   int per_cu = 0, dev = 0, cus = 0;
   FMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, f, 64 * (4 + svd_nwv(fp32)), m2l_svd_lds_bytes(xs, fp32)));
+      &per_cu, f, 64 * (4 + sh.ncw), m2l_svd_lds_bytes(xs, fp32)));
   FMM_HIP_CHECK(hipGetDevice(&dev));
   FMM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   return std::max(1, per_cu) * std::max(1, cus);
@@ -1626,13 +1665,13 @@ int m2l_svd_slots(int order, bool fp32, int xs) {
 
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
                          int xs, hipStream_t s) {
-  const int l3 = order * order * order;
-  const int mtw = m2l_svd_mtw((l3 + 15) / 16, fp32), kc = (l3 + 15) / 16;
+  const int l3 = order * order * order, kc = (l3 + 15) / 16;
+  const SvdShape sh = m2l_svd_shape(kc, fp32);
   const size_t lds = m2l_svd_lds_bytes(xs, fp32);
   if (fp32)
-    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(mtw, kc, jobs, tab, grid, lds, s);
+    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(sh, kc, jobs, tab, grid, lds, s);
   else
-    launch_svd_mtw<double, 0>(mtw, kc, jobs, tab, grid, lds, s);
+    launch_svd_mtw<double, 0>(sh, kc, jobs, tab, grid, lds, s);
   FMM_HIP_CHECK(hipGetLastError());
 }
 
