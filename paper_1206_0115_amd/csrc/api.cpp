@@ -74,7 +74,6 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.mt = op->mt;
   J.kc = op->kc;
   const bool fp32 = p->precision == FMM_MIXED_FP32 || p->precision == FMM_MIXED_SVD;
-  J.nmb = p->svd ? m2l_svd_nmb(op->mt, fp32) : m2l_nmb(op->mt);
   J.kernel = p->kernel;
   J.w32_leaf = p->w32_leaf ? 1 : 0;
   // FP32 accumulation error grows with the fold interval and, through the
@@ -82,8 +81,9 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   // FP64 (8: 3.5e-7, 5% slower); above order 7 the default folds every 2
   J.fold_every = p->m2l_fold > 0 ? p->m2l_fold : (p->order <= 7 ? 16 : 2);
   J.svd = p->svd ? 1 : 0;
+  if (p->svd) J.xs = m2l_svd_xs(p->svd->rmax_pad, fp32);
+  J.nmb = p->svd ? m2l_svd_nmb(op->mt, fp32, J.xs) : m2l_nmb(op->mt);
   if (p->svd) {
-    J.xs = m2l_svd_xs(p->svd->rmax_pad, fp32);
     J.svd_rpad = p->svd->rpad;
     J.svd_rank = p->svd->rk;
     J.svd_off = p->svd->off;
@@ -369,7 +369,8 @@ static void apply_mode(fmm_plan_s* p, int mode) {
                              : nullptr;
   if (sv) {
     // the compressed kernel keeps two sets of four rank x 16*NT slabs in LDS
-    const size_t need = fmm::m2l_svd_lds_bytes(fmm::m2l_svd_xs(sv->rmax_pad, mixed), mixed);
+    const size_t need =
+        fmm::m2l_svd_lds_need(p->order, mixed, fmm::m2l_svd_xs(sv->rmax_pad, mixed));
     int have = 0;
     FMM_HIP_CHECK(hipDeviceGetAttribute(&have, hipDeviceAttributeMaxSharedMemoryPerBlock,
                                         p->device));

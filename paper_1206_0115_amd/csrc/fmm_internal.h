@@ -124,12 +124,19 @@ enum {
 };
 
 int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
-int m2l_svd_nmb(int mt, bool fp32);  // work items per tile for the compressed M2L
+// Compressed M2L for mt 16-row tiles and a slab stride of xs values (the
+// kernel's shape depends on both): work items per tile, and 16-column
+// N-tiles per item (launches of one order and precision that batch several
+// plans group them by the latter)
+int m2l_svd_nmb(int mt, bool fp32, int xs);
+int m2l_svd_nt(int order, bool fp32, int xs);
 int m2l_svd_slots(int order, bool fp32, int xs);  // compressed M2L workgroups resident at once
 bool m2l_svd_splits(bool fp32);          // whether the compressed kernel takes m2l_parts
-// LDS bytes of one compressed-M2L workgroup for a slab stride of xs values
-size_t m2l_svd_lds_bytes(int xs, bool fp32);
-int m2l_svd_xs(int rmax_pad, bool fp32);  // that slab stride for a padded rank
+// LDS bytes of one compressed-M2L workgroup of nt N-tiles, and of the shape
+// the kernel takes at this order
+size_t m2l_svd_lds_bytes(int xs, bool fp32, int nt);
+size_t m2l_svd_lds_need(int order, bool fp32, int xs);
+int m2l_svd_xs(int rmax_pad, bool fp32);  // the slab stride for a padded rank
 
 }  // namespace fmm
 

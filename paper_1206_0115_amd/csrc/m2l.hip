@@ -1020,6 +1020,14 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #ifndef FMM_M2L_SVD_WS_WAVES
 #define FMM_M2L_SVD_WS_WAVES 4
 #endif
+// ...and for workgroups of 8 consumers whose items span all 64 columns
+// (NT = 4), whose accumulators need more registers per lane
+#ifndef FMM_M2L_SVD_WS_WAVES_BIG
+#define FMM_M2L_SVD_WS_WAVES_BIG 3
+#endif
+constexpr int svd_ws_waves(int ncw, int nt) {
+  return ncw * nt >= 32 ? FMM_M2L_SVD_WS_WAVES_BIG : FMM_M2L_SVD_WS_WAVES;
+}
 // Producer stage depth D, FP32 and FP64: where every K-group has at most D
 // chunks of the l^3 contraction (ceil(KC / 4) <= D), the kernel built for D
 // loads each K-group's chunks all at once; otherwise (or D = 0) they stream
@@ -1502,7 +1510,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
 }
 
 template <typename T, int MTW, int NT, int D, int NCW>
-__global__ __launch_bounds__(64 * (4 + NCW), FMM_M2L_SVD_WS_WAVES) void m2l_svd_ws_kernel(
+__global__ __launch_bounds__(64 * (4 + NCW), svd_ws_waves(NCW, NT)) void m2l_svd_ws_kernel(
     const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   // the per-offset table first (a fixed size, so jobs of different slab
@@ -1534,110 +1542,99 @@ __global__ __launch_bounds__(64 * (4 + NCW), FMM_M2L_SVD_WS_WAVES) void m2l_svd_
 #define FMM_M2L_SVD_WIDE 1
 #endif
 constexpr int kSvdWideMtw = 8;
+// FP32, warp-specialised: where the slabs of all 64 columns of a tile fit
+// the LDS, one item takes the whole tile (NT = 4) with 8 consumers of up to
+// 6 M-tiles, so that each operator chunk is read once per tile rather than
+// once per 32-column half (M2L time on gfx950: order 7 -2.2%, order 8
+// -6.8%).  Beyond 6 M-tiles NT = 4 spills, and the shapes above take over;
+// at 16 M-tiles or fewer (l <= 6) the 32-column items are as fast (l = 6)
+// or faster (l = 5: by 9%).
+#ifndef FMM_M2L_SVD_FULL_F32
+#define FMM_M2L_SVD_FULL_F32 1
+#endif
+constexpr int kSvdFullNt = 4, kSvdFullMtw = 6;
+constexpr size_t kSvdLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
 
 struct SvdShape {
-  int ncw, mtw;  // consumer wavefronts (compressed kernel: wavefronts), M-tiles each
+  int ncw, mtw, nt;  // consumer wavefronts (compressed kernel: wavefronts), M-tiles each,
+                     // 16-column N-tiles per item
 };
 
-static SvdShape m2l_svd_shape(int mt, bool fp32) {
-  const int nw = svd_nwv(fp32);
-  for (int w = 1; w <= 6; ++w)
-    if (nw * w >= mt) return {nw, w};
-  const bool ws = fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
-  if (ws && FMM_M2L_SVD_WIDE && nw < 8)
-    for (int w = 4; w <= kSvdWideMtw; ++w)
-      if (8 * w >= mt) return {8, w};
-  return ws && FMM_M2L_SVD_WIDE && nw < 8 ? SvdShape{8, kSvdWideMtw} : SvdShape{nw, 6};
+size_t m2l_svd_lds_bytes(int xs, bool fp32, int nt) {
+  return size_t(2) * 4 * 16 * nt * xs * (fp32 ? sizeof(float) : sizeof(double)) + kSvdMetaBytes;
 }
 
+static SvdShape m2l_svd_shape(int mt, bool fp32, int xs) {
+  const int nw = svd_nwv(fp32), nt = svd_nt(fp32);
+  const bool ws = fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
+  if (ws && fp32 && FMM_M2L_SVD_FULL_F32 && nt < kSvdFullNt && mt > 16 && 8 * kSvdFullMtw >= mt &&
+      m2l_svd_lds_bytes(xs, fp32, kSvdFullNt) <= kSvdLdsMax)
+    for (int w = 1; w <= kSvdFullMtw; ++w)
+      if (8 * w >= mt) return {8, w, kSvdFullNt};
+  for (int w = 1; w <= 6; ++w)
+    if (nw * w >= mt) return {nw, w, nt};
+  if (ws && FMM_M2L_SVD_WIDE && nw < 8)
+    for (int w = 4; w <= kSvdWideMtw; ++w)
+      if (8 * w >= mt) return {8, w, nt};
+  return ws && FMM_M2L_SVD_WIDE && nw < 8 ? SvdShape{8, kSvdWideMtw, nt} : SvdShape{nw, 6, nt};
+}
 
-int m2l_svd_nmb(int mt, bool fp32) {
-  const SvdShape sh = m2l_svd_shape(mt, fp32);
-  return (mt + sh.ncw * sh.mtw - 1) / (sh.ncw * sh.mtw) * (4 / svd_nt(fp32));
+static int svd_kc(int order) { return (order * order * order + 15) / 16; }
+
+int m2l_svd_nt(int order, bool fp32, int xs) { return m2l_svd_shape(svd_kc(order), fp32, xs).nt; }
+
+int m2l_svd_nmb(int mt, bool fp32, int xs) {
+  const SvdShape sh = m2l_svd_shape(mt, fp32, xs);
+  return (mt + sh.ncw * sh.mtw - 1) / (sh.ncw * sh.mtw) * (4 / sh.nt);
 }
 
 // Slab row stride: the padded rank plus 16 bytes, so that consecutive target
 // columns start 16 bytes apart modulo the LDS banks.
 int m2l_svd_xs(int rmax_pad, bool fp32) { return rmax_pad + (fp32 ? 4 : 2); }
 
-size_t m2l_svd_lds_bytes(int xs, bool fp32) {
-  return size_t(2) * 4 * 16 * svd_nt(fp32) * xs * (fp32 ? sizeof(float) : sizeof(double)) +
-         kSvdMetaBytes;
+size_t m2l_svd_lds_need(int order, bool fp32, int xs) {
+  return m2l_svd_lds_bytes(xs, fp32, m2l_svd_shape(svd_kc(order), fp32, xs).nt);
 }
 
 // With the warp-specialised kernel, NWV counts the consumer wavefronts (the
 // workgroup has 4 more).
 
-template <typename T, int FOLD>
-static void launch_svd_mtw(SvdShape sh, int kc, const JobDev* jobs, const StepTab* tab, int grid,
-                           size_t lds, hipStream_t s) {
-  constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
-  constexpr bool WS = sizeof(T) == 4 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
-  const int mtw = sh.mtw;
-  if (WS && sh.ncw == 8 && NW != 8) {  // wide: one M-block for l >= 8
-    constexpr int WB = 64 * 12;
-    switch (mtw) {
-      case 4: m2l_svd_ws_kernel<T, 4, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 5: m2l_svd_ws_kernel<T, 5, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 6: m2l_svd_ws_kernel<T, 6, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 7: m2l_svd_ws_kernel<T, 7, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
-      default: m2l_svd_ws_kernel<T, kSvdWideMtw, NT, 0, 8><<<grid, WB, lds, s>>>(jobs, tab); break;
-    }
-    return;
-  }
-  if (WS) {
-    constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
-    constexpr int WB = 64 * (4 + NW);
-    if (D > 0 && (kc + 3) / 4 <= D) {
-      switch (mtw) {
-        case 1: m2l_svd_ws_kernel<T, 1, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-        case 2: m2l_svd_ws_kernel<T, 2, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-        case 3: m2l_svd_ws_kernel<T, 3, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-        case 4: m2l_svd_ws_kernel<T, 4, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-        case 5: m2l_svd_ws_kernel<T, 5, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-        default: m2l_svd_ws_kernel<T, 6, NT, D, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-      }
-      return;
-    }
-    switch (mtw) {
-      case 1: m2l_svd_ws_kernel<T, 1, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 2: m2l_svd_ws_kernel<T, 2, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 3: m2l_svd_ws_kernel<T, 3, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 4: m2l_svd_ws_kernel<T, 4, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-      case 5: m2l_svd_ws_kernel<T, 5, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-      default: m2l_svd_ws_kernel<T, 6, NT, 0, NW><<<grid, WB, lds, s>>>(jobs, tab); break;
-    }
-    return;
-  }
-  switch (mtw) {
-    case 1: m2l_svd_kernel<T, 1, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
-    case 2: m2l_svd_kernel<T, 2, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
-    case 3: m2l_svd_kernel<T, 3, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
-    case 4: m2l_svd_kernel<T, 4, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
-    case 5: m2l_svd_kernel<T, 5, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
-    default: m2l_svd_kernel<T, 6, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
-  }
+template <typename T, int MTW, int NT, int NCW>
+static const void* svd_ws_ptr() {
+  return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, MTW, NT, 0, NCW>);
 }
 
-bool m2l_svd_splits(bool fp32) { return fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64; }
-
+// The warp-specialised kernel of a shape; staged selects the stage depth
+// FMM_M2L_SVD_WS_STAGE_* of the NWV-consumer shape.
 template <typename T>
 static const void* svd_ws_fn(SvdShape sh, bool staged) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4);
   constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
   const int mtw = sh.mtw;
+  if constexpr (sizeof(T) == 4 && NT < kSvdFullNt) {
+    if (sh.nt == kSvdFullNt) {
+      switch (mtw) {
+        case 1: return svd_ws_ptr<T, 1, kSvdFullNt, 8>();
+        case 2: return svd_ws_ptr<T, 2, kSvdFullNt, 8>();
+        case 3: return svd_ws_ptr<T, 3, kSvdFullNt, 8>();
+        case 4: return svd_ws_ptr<T, 4, kSvdFullNt, 8>();
+        case 5: return svd_ws_ptr<T, 5, kSvdFullNt, 8>();
+        default: return svd_ws_ptr<T, kSvdFullMtw, kSvdFullNt, 8>();
+      }
+    }
+  }
   if (sh.ncw == 8 && NW != 8) {
     switch (mtw) {
-      case 4: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 4, NT, 0, 8>);
-      case 5: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 5, NT, 0, 8>);
-      case 6: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 6, NT, 0, 8>);
-      case 7: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, 7, NT, 0, 8>);
-      default: return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, kSvdWideMtw, NT, 0, 8>);
+      case 4: return svd_ws_ptr<T, 4, NT, 8>();
+      case 5: return svd_ws_ptr<T, 5, NT, 8>();
+      case 6: return svd_ws_ptr<T, 6, NT, 8>();
+      case 7: return svd_ws_ptr<T, 7, NT, 8>();
+      default: return svd_ws_ptr<T, kSvdWideMtw, NT, 8>();
     }
   }
 #define FMM_WS_FN(M)                                                                     \
   return staged ? reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, M, NT, D, NW>)    \
-                : reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, M, NT, 0, NW>)
+                : svd_ws_ptr<T, M, NT, NW>()
   switch (mtw) {
     case 1: FMM_WS_FN(1);
     case 2: FMM_WS_FN(2);
@@ -1649,15 +1646,41 @@ static const void* svd_ws_fn(SvdShape sh, bool staged) {
 #undef FMM_WS_FN
 }
 
+template <typename T, int FOLD>
+static void launch_svd_mtw(SvdShape sh, int kc, const JobDev* jobs, const StepTab* tab, int grid,
+                           size_t lds, hipStream_t s) {
+  constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
+  constexpr bool WS = sizeof(T) == 4 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
+  if (WS) {
+    constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
+    const bool staged = D > 0 && (kc + 3) / 4 <= D && sh.ncw == NW && sh.nt == NT;
+    const void* f = svd_ws_fn<T>(sh, staged);
+    void* args[] = {&jobs, &tab};
+    FMM_HIP_CHECK(hipLaunchKernel(f, dim3(grid), dim3(64 * (4 + sh.ncw)), args, lds, s));
+    return;
+  }
+  switch (sh.mtw) {
+    case 1: m2l_svd_kernel<T, 1, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 2: m2l_svd_kernel<T, 2, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 3: m2l_svd_kernel<T, 3, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 4: m2l_svd_kernel<T, 4, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    case 5: m2l_svd_kernel<T, 5, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+    default: m2l_svd_kernel<T, 6, NT, NW, FOLD><<<grid, B, lds, s>>>(jobs, tab); break;
+  }
+}
+
+bool m2l_svd_splits(bool fp32) { return fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64; }
+
 int m2l_svd_slots(int order, bool fp32, int xs) {
-  const int l3 = order * order * order, kc = (l3 + 15) / 16;
-  const SvdShape sh = m2l_svd_shape(kc, fp32);
+  const int kc = svd_kc(order);
+  const SvdShape sh = m2l_svd_shape(kc, fp32, xs);
   const int D = fp32 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
-  const bool staged = D > 0 && (kc + 3) / 4 <= D && sh.ncw == svd_nwv(fp32);
+  const bool staged =
+      D > 0 && (kc + 3) / 4 <= D && sh.ncw == svd_nwv(fp32) && sh.nt == svd_nt(fp32);
   const void* f = fp32 ? svd_ws_fn<float>(sh, staged) : svd_ws_fn<double>(sh, staged);
   int per_cu = 0, dev = 0, cus = 0;
   FMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, f, 64 * (4 + sh.ncw), m2l_svd_lds_bytes(xs, fp32)));
+      &per_cu, f, 64 * (4 + sh.ncw), m2l_svd_lds_bytes(xs, fp32, sh.nt)));
   FMM_HIP_CHECK(hipGetDevice(&dev));
   FMM_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   return std::max(1, per_cu) * std::max(1, cus);
@@ -1665,9 +1688,9 @@ int m2l_svd_slots(int order, bool fp32, int xs) {
 
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
                          int xs, hipStream_t s) {
-  const int l3 = order * order * order, kc = (l3 + 15) / 16;
-  const SvdShape sh = m2l_svd_shape(kc, fp32);
-  const size_t lds = m2l_svd_lds_bytes(xs, fp32);
+  const int kc = svd_kc(order);
+  const SvdShape sh = m2l_svd_shape(kc, fp32, xs);
+  const size_t lds = m2l_svd_lds_bytes(xs, fp32, sh.nt);
   if (fp32)
     launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(sh, kc, jobs, tab, grid, lds, s);
   else

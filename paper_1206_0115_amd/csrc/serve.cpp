@@ -294,12 +294,16 @@ bool fmm_server_s::launch_batch() {
         [&](Request* r) { return r->h - 2 - s; });
   add(kStepCast, 0, true, [&](Request* r) { return far(r) && mixed(r); },
       [](Request* r) { return int(r->plan->tab_h[kTabCast].start[1]); }, lvl0);
+  // dense, then compressed by the kernel's N-tiles per item (1, 2, 4): one
+  // launch decodes every plan's items alike
+  auto svd_nt = [&](Request* r) { return m2l_svd_nt(r->order, mixed(r), r->plan->job_h.xs); };
   for (int L : orders)
     for (int f32 = 0; f32 < 2; ++f32)
-      for (int cmp = 0; cmp < 2; ++cmp)
+      for (int cmp = 0; cmp < 4; ++cmp)
         add(cmp ? kStepM2LSvd : kStepM2L, L, f32 != 0,
             [&](Request* r) {
-              return far(r) && r->order == L && mixed(r) == (f32 != 0) && svd(r) == (cmp != 0);
+              return far(r) && r->order == L && mixed(r) == (f32 != 0) && svd(r) == (cmp != 0) &&
+                     (cmp == 0 || svd_nt(r) == 1 << (cmp - 1));
             },
             [](Request* r) {
               return int(r->plan->ntiles) * r->plan->job_h.nmb * r->plan->job_h.m2l_parts;
