@@ -84,6 +84,64 @@ void dev_free(void* p) {
   g_live.erase(it);
 }
 
+namespace {
+std::mutex g_smu;
+std::multimap<int, hipStream_t> g_streams;  // device -> idle side stream
+std::multimap<int, hipEvent_t> g_events;    // device -> idle event (no timing)
+}  // namespace
+
+hipStream_t side_stream_get(int device) {
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    auto it = g_streams.find(device);
+    if (it != g_streams.end()) {
+      hipStream_t s = it->second;
+      g_streams.erase(it);
+      return s;
+    }
+  }
+  hipStream_t s = nullptr;
+  FMM_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  return s;
+}
+
+void side_stream_put(int device, hipStream_t s) {
+  if (!s) return;
+  if (hipStreamSynchronize(s) != hipSuccess) {  // not reused after an error
+    (void)hipGetLastError();
+    (void)hipStreamDestroy(s);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_smu);
+  g_streams.insert({device, s});
+}
+
+hipEvent_t event_get(int device) {
+  {
+    std::lock_guard<std::mutex> lk(g_smu);
+    auto it = g_events.find(device);
+    if (it != g_events.end()) {
+      hipEvent_t e = it->second;
+      g_events.erase(it);
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  FMM_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  return e;
+}
+
+void event_put(int device, hipEvent_t e) {
+  if (!e) return;
+  if (hipEventSynchronize(e) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipEventDestroy(e);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_smu);
+  g_events.insert({device, e});
+}
+
 // Pinned host staging for the small transfers of plan construction: copies
 // between pinned memory and the device skip the driver's pageable staging.
 // One buffer per thread, grown on demand and kept for the process.

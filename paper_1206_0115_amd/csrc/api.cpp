@@ -198,13 +198,11 @@ void fmm_plan_s::free_block(void* ptr) {
 }
 
 fmm_plan_s::~fmm_plan_s() {
-  if (done) {
-    (void)hipEventSynchronize(done);
-    (void)hipEventDestroy(done);
-  }
-  if (ev_fork) (void)hipEventDestroy(ev_fork);
-  if (ev_join) (void)hipEventDestroy(ev_join);
-  if (side) (void)hipStreamDestroy(side);
+  // the evaluation's last work first: done, then the side stream
+  fmm::event_put(device, done);
+  fmm::side_stream_put(device, side);
+  fmm::event_put(device, ev_fork);
+  fmm::event_put(device, ev_join);
   for (auto& b : blocks) fmm::dev_free(b.first);
 }
 
@@ -293,10 +291,10 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
       // the multipole buffers depend on the precision mode: ensure_w
     }
     fmm::upload_job(p, stream);
-    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
-    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-    FMM_HIP_CHECK(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
-    FMM_HIP_CHECK(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    p->done = fmm::event_get(p->device);
+    p->ev_fork = fmm::event_get(p->device);
+    p->ev_join = fmm::event_get(p->device);
+    p->side = fmm::side_stream_get(p->device);
     return FMM_OK;
   });
   if (rc != FMM_OK) {

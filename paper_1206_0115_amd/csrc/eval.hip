@@ -101,7 +101,15 @@ __global__ __launch_bounds__(256) void p2m_kernel(const JobDev* __restrict__ job
 // ------------------------------------------------------------- M2M / L2L
 // Three 1-D contractions with the child-to-parent matrices
 // Sc[s][m][m'] = S(xb_m; (s + xb_m')/2), s in {-1,+1} by the child octant bit.
-constexpr int kTransThreads = 256;
+// Threads per workgroup (one parent cell per workgroup).  The LDS staging
+// holds three workgroups per CU at order 7, so the wider workgroup keeps
+// more wavefronts in flight: 1M cube, order 7, evaluation 5.23 -> 5.12 ms
+// at 512 (1024: the same).  Each value's arithmetic and summation order do
+// not depend on it.
+#ifndef FMM_TRANS_THREADS
+#define FMM_TRANS_THREADS 512
+#endif
+constexpr int kTransThreads = FMM_TRANS_THREADS;
 constexpr int kTransMaxR = (kMaxOrder * kMaxOrder * kMaxOrder + kTransThreads - 1) / kTransThreads;
 
 // Children are staged in LDS, up to 8 x l^3 values per buffer: all children
@@ -725,8 +733,10 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
 }
 
 // Where the forked schedule starts the near field: 0 = just before the M2L
-// launch, 1 = just after it.  Measured (1M cube, order 7, compressed mixed
-// mode, evaluate only): after 6.84 ms, serial 6.90 ms, before 6.98 ms.
+// launch, 1 = just after it, 2 = after the L2L levels, 3 = before the last
+// L2L level.  Measured (1M cube, order 7, compressed mixed mode, evaluate
+// only): after 6.84 ms, serial 6.90 ms, before 6.98 ms; later, with the
+// faster M2L: 1 5.24 ms, 2 5.23 ms, 3 5.21 ms (within the spread).
 #ifndef FMM_FORK_AFTER_M2L
 #define FMM_FORK_AFTER_M2L 1
 #endif
@@ -794,10 +804,13 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
                       p->tab_h[kTabLocSum].start[1], s);
       }
     }
-    if (forked && FMM_FORK_AFTER_M2L) fork_near();
-    for (int st = 0; st + 4 <= h; ++st)
+    if (forked && FMM_FORK_AFTER_M2L == 1) fork_near();
+    for (int st = 0; st + 4 <= h; ++st) {
+      if (forked && FMM_FORK_AFTER_M2L == 3 && st + 4 == h) fork_near();
       launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,
                   p->tab_h[kTabL2L + st].start[1], s);
+    }
+    if (forked && (FMM_FORK_AFTER_M2L == 2 || (FMM_FORK_AFTER_M2L == 3 && h < 4))) fork_near();
     {
       Timed t(FMM_TIME_L2P, s);
       launch_step(kStepL2P, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);

@@ -54,6 +54,13 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 size_t dev_cached_bytes();
 void dev_trim();
+// A plan's side stream (non-blocking, default priority) and its events,
+// recycled per device: creating and destroying them costs more host time
+// than a plan's whole build.  put_* waits for the stream's work first.
+hipStream_t side_stream_get(int device);
+void side_stream_put(int device, hipStream_t s);
+hipEvent_t event_get(int device);
+void event_put(int device, hipEvent_t e);
 // The calling thread's pinned host staging buffer, at least `bytes` long.
 // Growing it frees the previous one: callers finish every transfer through
 // it (a stream synchronisation) before asking for more.
