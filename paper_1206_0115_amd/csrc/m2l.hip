@@ -689,9 +689,11 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
 // Target columns per workgroup of the compressed kernel, 16 * NT, for FP32
 // and FP64.  Fewer columns than the tile's 64 cost operator re-reads (from
 // L2) but free registers for two wavefronts per SIMD.  Measured on gfx950
-// at order 7: FP32 best at 32 columns in 8 wavefronts (3 M-tiles each, no
-// spills); FP64 at 16 columns in 4 wavefronts (within 1% of 32 columns in
-// 8, and half the LDS, so order 9 at 1e-9 still fits).
+// at order 7 with the 4-wavefront kernel: FP32 best at 32 columns in 8
+// wavefronts (3 M-tiles each, no spills); FP64 at 16 columns in 4
+// wavefronts (within 1% of 32 columns in 8, and half the LDS, so order 9 at
+// 1e-9 still fits).  These are the base shapes; the warp-specialised kernel
+// takes wider items where they fit (FMM_M2L_SVD_FULL_*).
 #ifndef FMM_M2L_SVD_NT_F32
 #define FMM_M2L_SVD_NT_F32 2
 #endif
@@ -1020,8 +1022,9 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #ifndef FMM_M2L_SVD_WS_WAVES
 #define FMM_M2L_SVD_WS_WAVES 4
 #endif
-// ...and for workgroups of 8 consumers whose items span all 64 columns
-// (NT = 4), whose accumulators need more registers per lane
+// ...and for workgroups of 8 consumers whose items hold 64 FP32 or 32 FP64
+// columns (NT = 4, FP32; NT = 2, FP64), which need more registers per lane;
+// svd_ws_waves takes NT in FP32 column units
 #ifndef FMM_M2L_SVD_WS_WAVES_BIG
 #define FMM_M2L_SVD_WS_WAVES_BIG 3
 #endif
@@ -1510,7 +1513,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
 }
 
 template <typename T, int MTW, int NT, int D, int NCW>
-__global__ __launch_bounds__(64 * (4 + NCW), svd_ws_waves(NCW, NT)) void m2l_svd_ws_kernel(
+__global__ __launch_bounds__(64 * (4 + NCW), svd_ws_waves(NCW, NT * int(sizeof(T) / 4))) void m2l_svd_ws_kernel(
     const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   // the per-offset table first (a fixed size, so jobs of different slab
@@ -1552,7 +1555,14 @@ constexpr int kSvdWideMtw = 8;
 #ifndef FMM_M2L_SVD_FULL_F32
 #define FMM_M2L_SVD_FULL_F32 1
 #endif
-constexpr int kSvdFullNt = 4, kSvdFullMtw = 6;
+// FP64 likewise with 32-column items (NT = 2) where they fit: fp64_svd M2L
+// order 7 9.0 -> 8.3 ms, order 8 16.0 -> 13.6 ms (order 9 at 1e-9 needs
+// 168 KiB and keeps 16 columns).
+#ifndef FMM_M2L_SVD_FULL_F64
+#define FMM_M2L_SVD_FULL_F64 1
+#endif
+constexpr int kSvdFullNt = 4, kSvdFullNt64 = 2, kSvdFullMtw = 6;
+constexpr int svd_full_nt(bool fp32) { return fp32 ? kSvdFullNt : kSvdFullNt64; }
 constexpr size_t kSvdLdsMax = 160 * 1024;  // LDS per workgroup on gfx950
 
 struct SvdShape {
@@ -1567,10 +1577,12 @@ size_t m2l_svd_lds_bytes(int xs, bool fp32, int nt) {
 static SvdShape m2l_svd_shape(int mt, bool fp32, int xs) {
   const int nw = svd_nwv(fp32), nt = svd_nt(fp32);
   const bool ws = fp32 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
-  if (ws && fp32 && FMM_M2L_SVD_FULL_F32 && nt < kSvdFullNt && mt > 16 && 8 * kSvdFullMtw >= mt &&
-      m2l_svd_lds_bytes(xs, fp32, kSvdFullNt) <= kSvdLdsMax)
+  const int fnt = svd_full_nt(fp32);
+  const bool full = fp32 ? FMM_M2L_SVD_FULL_F32 : FMM_M2L_SVD_FULL_F64;
+  if (ws && full && nt < fnt && mt > 16 && 8 * kSvdFullMtw >= mt &&
+      m2l_svd_lds_bytes(xs, fp32, fnt) <= kSvdLdsMax)
     for (int w = 1; w <= kSvdFullMtw; ++w)
-      if (8 * w >= mt) return {8, w, kSvdFullNt};
+      if (8 * w >= mt) return {8, w, fnt};
   for (int w = 1; w <= 6; ++w)
     if (nw * w >= mt) return {nw, w, nt};
   if (ws && FMM_M2L_SVD_WIDE && nw < 8)
@@ -1611,15 +1623,17 @@ static const void* svd_ws_fn(SvdShape sh, bool staged) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4);
   constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
   const int mtw = sh.mtw;
-  if constexpr (sizeof(T) == 4 && NT < kSvdFullNt) {
-    if (sh.nt == kSvdFullNt) {
+  constexpr int FNT = svd_full_nt(sizeof(T) == 4);
+  constexpr bool FULL = sizeof(T) == 4 ? FMM_M2L_SVD_FULL_F32 : FMM_M2L_SVD_FULL_F64;
+  if constexpr (FULL && NT < FNT) {
+    if (sh.nt == FNT) {
       switch (mtw) {
-        case 1: return svd_ws_ptr<T, 1, kSvdFullNt, 8>();
-        case 2: return svd_ws_ptr<T, 2, kSvdFullNt, 8>();
-        case 3: return svd_ws_ptr<T, 3, kSvdFullNt, 8>();
-        case 4: return svd_ws_ptr<T, 4, kSvdFullNt, 8>();
-        case 5: return svd_ws_ptr<T, 5, kSvdFullNt, 8>();
-        default: return svd_ws_ptr<T, kSvdFullMtw, kSvdFullNt, 8>();
+        case 1: return svd_ws_ptr<T, 1, FNT, 8>();
+        case 2: return svd_ws_ptr<T, 2, FNT, 8>();
+        case 3: return svd_ws_ptr<T, 3, FNT, 8>();
+        case 4: return svd_ws_ptr<T, 4, FNT, 8>();
+        case 5: return svd_ws_ptr<T, 5, FNT, 8>();
+        default: return svd_ws_ptr<T, kSvdFullMtw, FNT, 8>();
       }
     }
   }
