@@ -36,8 +36,27 @@ __device__ inline void leaf_centre(const LeafGeom& g, uint64_t key, double* c) {
 // over the leaf's particles: W += q Sx[m1] Sy[m2] Sz[*].
 constexpr int kP2MChunk = 64;
 
+// Minimum wavefronts per SIMD the register allocation of P2M and L2P must
+// allow (0: the compiler's choice).
+#ifndef FMM_P2M_WAVES
+#define FMM_P2M_WAVES 0
+#endif
+#ifndef FMM_L2P_WAVES
+#define FMM_L2P_WAVES 0
+#endif
+#if FMM_P2M_WAVES > 0
+#define FMM_P2M_BOUNDS __launch_bounds__(256, FMM_P2M_WAVES)
+#else
+#define FMM_P2M_BOUNDS __launch_bounds__(256)
+#endif
+#if FMM_L2P_WAVES > 0
+#define FMM_L2P_BOUNDS __launch_bounds__(64, FMM_L2P_WAVES)
+#else
+#define FMM_L2P_BOUNDS __launch_bounds__(64)
+#endif
+
 template <int L>
-__global__ __launch_bounds__(256) void p2m_kernel(const JobDev* __restrict__ jobs,
+__global__ FMM_P2M_BOUNDS void p2m_kernel(const JobDev* __restrict__ jobs,
                                                   const StepTab* __restrict__ tab) {
   __shared__ double C[L * L];
   __shared__ double S[kP2MChunk][3][L];
@@ -276,11 +295,13 @@ __global__ __launch_bounds__(kTransThreads) void l2l_kernel(const JobDev* __rest
 }
 
 // ------------------------------------------------------------------- L2P
-// Item = leaf; one thread per particle; the leaf's local expansion sits in
-// LDS and every lane reads the same coefficient (broadcast).
+// Item = leaf; two lanes per particle (a leaf holds about 30 at the usual
+// occupancy, so a wavefront's second half would idle otherwise); the leaf's
+// local expansion sits in LDS and each half-wavefront reads one coefficient
+// (broadcast).
 // phi = sum_m S_m(u) Loc[m];  F = -q (1/a) grad_u sum_m S_m(u) Loc[m].
 template <int L>
-__global__ __launch_bounds__(64) void l2p_kernel(const JobDev* __restrict__ jobs,
+__global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
                                                  const StepTab* __restrict__ tab) {
   __shared__ double C[L * L];
   __shared__ double Lc[L * L * L];
@@ -297,9 +318,17 @@ __global__ __launch_bounds__(64) void l2p_kernel(const JobDev* __restrict__ jobs
     const double ia = 2.0 / J.geo.w;
     __syncthreads();
     const int s0 = J.leaf_start[a], s1 = J.leaf_start[a + 1];
-    for (int i = s0 + t; i < s1; i += 64) {
+    // Two lanes per particle, t and t + 32, each take half of the m1 sum
+    // (m1 < H and m1 >= H); the halves are added once, to the same value in
+    // both lanes, and the first lane writes.
+    constexpr int H = (L + 1) / 2;
+    const int half = t >> 5;
+    for (int i0 = s0; i0 < s1; i0 += 32) {
+      const int i = i0 + (t & 31);
+      const bool valid = i < s1;
+      const int ip = valid ? i : s0;
       double S[3][L], dS[3][L];
-      const double xyz[3] = {J.px[i], J.py[i], J.pz[i]};
+      const double xyz[3] = {J.px[ip], J.py[ip], J.pz[ip]};
       for (int d = 0; d < 3; ++d) {
         const double u = (xyz[d] - c[d]) * ia;
         double T[L], dT[L];
@@ -323,8 +352,16 @@ __global__ __launch_bounds__(64) void l2p_kernel(const JobDev* __restrict__ jobs
           dS[d][m] = dv;
         }
       }
+      // this lane's dimension-0 factors; past m1 = L - 1 they are zero
+      double s0h[H], d0h[H];
+      for (int j = 0; j < H; ++j) {
+        const int hi = H + j < L ? H + j : L - 1;
+        s0h[j] = half ? (H + j < L ? S[0][hi] : 0.0) : S[0][j];
+        d0h[j] = half ? (H + j < L ? dS[0][hi] : 0.0) : dS[0][j];
+      }
       double ph = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
-      for (int m1 = 0; m1 < L; ++m1) {
+      for (int j = 0; j < H; ++j) {
+        const int m1 = min(half * H + j, L - 1);
         double b0 = 0.0, by = 0.0, bz = 0.0;
         for (int m2 = 0; m2 < L; ++m2) {
           double a0 = 0.0, a1 = 0.0;
@@ -337,11 +374,16 @@ __global__ __launch_bounds__(64) void l2p_kernel(const JobDev* __restrict__ jobs
           by += dS[1][m2] * a0;
           bz += S[1][m2] * a1;
         }
-        ph += S[0][m1] * b0;
-        gx += dS[0][m1] * b0;
-        gy += S[0][m1] * by;
-        gz += S[0][m1] * bz;
+        ph += s0h[j] * b0;
+        gx += d0h[j] * b0;
+        gy += s0h[j] * by;
+        gz += s0h[j] * bz;
       }
+      ph += __shfl_xor(ph, 32, 64);
+      gx += __shfl_xor(gx, 32, 64);
+      gy += __shfl_xor(gy, 32, 64);
+      gz += __shfl_xor(gz, 32, 64);
+      if (!valid || half) continue;
       const double fq = -J.qs[i] * ia;
       J.phi_f[i] = ph;
       J.f_f[3 * i] = fq * gx;
