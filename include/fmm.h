@@ -68,7 +68,11 @@ enum fmm_precision {
 /* Truncation tolerance of the compressed M2L (0 < eps < 1); takes effect for
  * the SVD precision modes.  The truncated operators of an order and tolerance
  * are computed once per device (rocSOLVER SVD of the 16 canonical operators)
- * and cached.  Returns FMM_ERR_ARG for a tolerance outside (0, 1). */
+ * and cached.  Returns FMM_ERR_ARG for a tolerance outside (0, 1), and, in an
+ * SVD mode, for one whose kept ranks need more LDS per workgroup than the
+ * device has (two sets of four slabs of the padded rank by 32 target columns
+ * in FP32, 16 in FP64; e.g. order 9 at 1e-14); the plan then keeps its
+ * previous tolerance. */
 int fmm_plan_set_m2l_tolerance(fmm_plan_t plan, double eps);
 
 /* Fold interval of the compressed mixed mode (FMM_MIXED_SVD): the FP32 MFMA
