@@ -473,6 +473,15 @@ __device__ __forceinline__ bool near_next(int nj0, int nj1, int& sl, int& jb, in
 // taken in the same order as one leaf, one chunk at a time.
 typedef double src4 __attribute__((ext_vector_type(4)));  // x, y, z, q of one source
 
+// FP32 charges travel in the q slot as their own bits (low word), so the
+// pair loop reads them without a conversion.
+__device__ __forceinline__ double q_slot(float q) {
+  return __longlong_as_double(static_cast<long long>(__float_as_uint(q)));
+}
+__device__ __forceinline__ float q_of_slot(double d) {
+  return __uint_as_float(static_cast<unsigned>(__double_as_longlong(d)));
+}
+
 template <int KP, bool F32>
 __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
   const int lane = threadIdx.x;
@@ -514,7 +523,7 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
     while (have) {
       const int ccnt = cnt, csl = sl;
       __syncthreads();  // the previous chunk's reads are done
-      src[lane] = src4{rx, ry, rz, double(rq)};
+      src[lane] = src4{rx, ry, rz, F32 ? q_slot(float(rq)) : double(rq)};
       __syncthreads();
       have = near_next(nj0, nj1, sl, jb, j1);
       cnt = have ? min(64, j1 - jb) : 0;
@@ -528,14 +537,14 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
         int kk = split;
         for (; kk + S < ccnt; kk += 2 * S) {  // two sources per pass, same order
           const src4 u = src[kk], v = src[kk + S];
-          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), float(u.w), p32, x32,
+          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), q_of_slot(u.w), p32, x32,
                        y32, z32);
-          pair_f32<KP>(float(xi - v.x), float(yi - v.y), float(zi - v.z), float(v.w), p32, x32,
+          pair_f32<KP>(float(xi - v.x), float(yi - v.y), float(zi - v.z), q_of_slot(v.w), p32, x32,
                        y32, z32);
         }
         if (kk < ccnt) {
           const src4 u = src[kk];
-          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), float(u.w), p32, x32,
+          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), q_of_slot(u.w), p32, x32,
                        y32, z32);
         }
         if (!have || sl != csl) {  // the source leaf ends here
