@@ -148,8 +148,9 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height,
 int fmm_evaluate(fmm_plan_t plan, const double* charges, double* potential,
                  double* forces, hipStream_t stream);
 
-/* Release a plan: waits for its in-flight evaluation, returns its device
- * memory to the library's cache.  NULL-safe. */
+/* Release a plan: waits for its in-flight evaluation and its side stream,
+ * returns its device memory, side stream and events to the library's
+ * per-device caches.  NULL-safe. */
 void fmm_release(fmm_plan_t plan);
 
 /* Message for the calling thread's most recent failure ("" if none). */
@@ -163,7 +164,9 @@ int fmm_plan_set_precision(fmm_plan_t plan, int mode);
  * and the far field (P2M, M2M, M2L, L2L, L2P) writes other buffers, so the two
  * branches may run at the same time and meet at the final sum.
  *   FMM_SCHEDULE_SERIAL  every operator in order on the caller's stream
- *   FMM_SCHEDULE_FORKED  (default) P2P on a stream owned by the plan, forked
+ *   FMM_SCHEDULE_FORKED  (default) P2P on a stream owned by the plan (a
+ *                        non-blocking stream of default priority, reused
+ *                        from plans released earlier on the device), forked
  *                        from the caller's stream after the M2L launch (so
  *                        it runs beside L2L and L2P, which leave the GPU
  *                        partly idle) and joined back before the final sum;
