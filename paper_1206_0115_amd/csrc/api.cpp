@@ -290,7 +290,8 @@ fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int o
       p->Loc = static_cast<double*>(p->alloc(sizeof(double) * rows * ld));
       // the multipole buffers depend on the precision mode: ensure_w
     }
-    fmm::upload_job(p, stream);
+    fmm::upload_job(p, stream);  // ends with a synchronisation of the stream
+    fmm::plan_stats(p);
     p->done = fmm::event_get(p->device);
     p->ev_fork = fmm::event_get(p->device);
     p->ev_join = fmm::event_get(p->device);

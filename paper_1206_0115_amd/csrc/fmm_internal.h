@@ -183,6 +183,7 @@ struct fmm_plan_s {
   int64_t far_pairs = 0;           // M2L (target, source) cell pairs
   int64_t far_pairs_level[fmm::kMaxHeight] = {0};
   int64_t active_slots = 0;        // sum over tiles of slots with a source
+  const unsigned long long* stats_stage = nullptr;  // unread statistics (plan_stats)
   int64_t pairs_by_kid[fmm::kOffsets] = {0};  // far pairs per packed operator
 
   // evaluation buffers
@@ -222,6 +223,10 @@ struct fmm_plan_s {
 namespace fmm {
 // plan construction (plan.hip)
 void build_plan(fmm_plan_s* p, const double* positions, hipStream_t stream);
+// The plan's statistics (pair counts), copied to the calling thread's
+// pinned staging by build_plan without a wait: read them once the stream
+// has been synchronised, before that staging is used again.
+void plan_stats(fmm_plan_s* p);
 // evaluation (eval.hip)
 void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f,
               double* phi_n, double* f_n, double* phi_f, double* f_f,

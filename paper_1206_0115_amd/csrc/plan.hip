@@ -847,7 +847,14 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   unsigned long long* hc = reinterpret_cast<unsigned long long*>(stage);
   FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(unsigned long long) * (kMaxHeight + 2 + kOffsets),
                                hipMemcpyDeviceToHost, s));
-  FMM_HIP_CHECK(hipStreamSynchronize(s));
+  // read by plan_stats after the caller's next synchronisation of s (no
+  // wait here: nothing the plan builds next needs them)
+  p->stats_stage = hc;
+}
+
+void plan_stats(fmm_plan_s* p) {
+  const unsigned long long* hc = p->stats_stage;
+  if (!hc) return;
   for (int k = 0; k < kOffsets; ++k) p->pairs_by_kid[k] = int64_t(hc[kMaxHeight + 2 + k]);
   p->near_pairs = int64_t(hc[kMaxHeight]);
   p->far_pairs = 0;
@@ -856,6 +863,7 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
     p->far_pairs += int64_t(hc[l]);
   }
   p->active_slots = int64_t(hc[kMaxHeight + 1]);
+  p->stats_stage = nullptr;
 }
 
 }  // namespace fmm
