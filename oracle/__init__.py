@@ -5,9 +5,12 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check in
 package.  It shares no code with the HIP path and never calls it; the product
 package never imports it.
 
-This module only marshals numpy arrays into the C library.  Every step of the
-method lives in ``fmm_oracle.c``; see its header for the passages of the paper
-each function follows.
+This module marshals numpy arrays into the C library, where every step of
+the method lives (``fmm_oracle.c``; its header names the passages of the
+paper each function follows).  One step is written here instead:
+:func:`compressed_unit_ops`, the truncated SVD of each far-offset operator
+(Sec. 2.1.2), which calls numpy's LAPACK SVD on the C library's dense
+operators and keeps the singular values at or above eps times the largest.
 """
 from __future__ import annotations
 

@@ -386,9 +386,10 @@ __global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
       if (!valid || half) continue;
       const double fq = -J.qs[i] * ia;
       J.phi_f[i] = ph;
-      J.f_f[3 * i] = fq * gx;
-      J.f_f[3 * i + 1] = fq * gy;
-      J.f_f[3 * i + 2] = fq * gz;
+      const int64_t i3 = 3 * int64_t(i);  // forces of n > 2^31/3 particles
+      J.f_f[i3] = fq * gx;
+      J.f_f[i3 + 1] = fq * gy;
+      J.f_f[i3 + 2] = fq * gz;
     }
     __syncthreads();
   }
@@ -571,9 +572,10 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
       const int i = t0 + ti;
       const double qi = gld(J.qs + i);
       gst(J.phi_n + i, ph);
-      gst(J.f_n + 3 * i, qi * fx);
-      gst(J.f_n + 3 * i + 1, qi * fy);
-      gst(J.f_n + 3 * i + 2, qi * fz);
+      const int64_t i3 = 3 * int64_t(i);
+      gst(J.f_n + i3, qi * fx);
+      gst(J.f_n + i3 + 1, qi * fy);
+      gst(J.f_n + i3 + 2, qi * fz);
     }
   }
 }
@@ -649,24 +651,25 @@ __device__ inline void combine_chunk(const JobDev& J, const CallDev& C, int chun
   const int64_t o = J.perm[i];
   const bool far = J.has_far;
   const double a = J.phi_n[i], b = far ? J.phi_f[i] : 0.0;
-  const double ax = J.f_n[3 * i], ay = J.f_n[3 * i + 1], az = J.f_n[3 * i + 2];
-  const double bx = far ? J.f_f[3 * i] : 0.0, by = far ? J.f_f[3 * i + 1] : 0.0,
-               bz = far ? J.f_f[3 * i + 2] : 0.0;
+  const int64_t i3 = 3 * int64_t(i), o3 = 3 * o;
+  const double ax = J.f_n[i3], ay = J.f_n[i3 + 1], az = J.f_n[i3 + 2];
+  const double bx = far ? J.f_f[i3] : 0.0, by = far ? J.f_f[i3 + 1] : 0.0,
+               bz = far ? J.f_f[i3 + 2] : 0.0;
   if (C.phi) {
     C.phi[o] = a + b;
-    C.f[3 * o] = ax + bx;
-    C.f[3 * o + 1] = ay + by;
-    C.f[3 * o + 2] = az + bz;
+    C.f[o3] = ax + bx;
+    C.f[o3 + 1] = ay + by;
+    C.f[o3 + 2] = az + bz;
   }
   if (C.pn) {
     C.pn[o] = a;
-    C.fn[3 * o] = ax;
-    C.fn[3 * o + 1] = ay;
-    C.fn[3 * o + 2] = az;
+    C.fn[o3] = ax;
+    C.fn[o3 + 1] = ay;
+    C.fn[o3 + 2] = az;
     C.pf[o] = b;
-    C.ff[3 * o] = bx;
-    C.ff[3 * o + 1] = by;
-    C.ff[3 * o + 2] = bz;
+    C.ff[o3] = bx;
+    C.ff[o3 + 1] = by;
+    C.ff[o3 + 2] = bz;
   }
 }
 

@@ -72,3 +72,31 @@ def test_error_tracks_tolerance(orc):
         errs.append(e)
         assert e < 10 * eps, (eps, e)
     assert all(b < a for a, b in zip(errs, errs[1:]))
+
+
+def test_truncation_error_is_first_dropped_singular_value(orc):
+    # Eckart-Young: the best rank-r approximation in the spectral norm errs
+    # by exactly the first singular value it drops, so the oracle's
+    # truncated operator must sit at that distance from the exact one
+    l, eps = 4, 1e-4
+    ops, ranks = orc.compressed_unit_ops(l, eps)
+    for t, i in orc.far_offsets()[::29]:
+        K = orc.m2l_matrix(l, 1.0, 2.0, t)
+        s = np.linalg.svd(K, compute_uv=False)
+        r = ranks[t]
+        assert 0 < r < l ** 3 and s[r] < eps * s[0] <= s[r - 1]
+        d = np.linalg.norm(K - ops[i], ord=2)
+        assert abs(d - s[r]) <= 1e-12 * s[0], (t, d, s[r])
+
+
+def test_ranks_fall_with_tolerance_and_rise_with_order(orc):
+    prev = None
+    for eps in (1e-3, 1e-5, 1e-7):
+        _, ranks = orc.compressed_unit_ops(5, eps)
+        if prev is not None:
+            assert all(ranks[t] >= prev[t] for t in ranks)
+            assert sum(ranks.values()) > sum(prev.values())
+        prev = ranks
+    w = [np.mean(list(orc.compressed_unit_ops(l, 10.0 ** -l)[1].values()))
+         for l in (3, 4, 5, 6)]
+    assert all(b > a for a, b in zip(w, w[1:])), w
