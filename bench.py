@@ -4,13 +4,19 @@
 One step = the whole path over one particle set already resident in HBM:
 plan (root box, Morton keys, radix sort, leaves, cells, near lists, M2L
 tiles) + evaluation (P2M, M2M, M2L, L2L, L2P, P2P, combine) + release.
-Workload: N = 1,000,000 particles uniform in the unit cube, charges uniform
-in [-1, 1), octree height 6, order 7 (seed 1002).
 
-Every precision mode (dense FP64, mixed FP32, and both with the compressed
-M2L) is checked on every run against the dense FP64 path on the same inputs;
-the headline is the fastest mode whose relative L2 error is at most 1e-6.
-All modes are reported.  Prints one JSON line.
+Headline workload: the largest configuration that fits one GPU, N = 30,000,000
+particles uniform in the unit cube, charges uniform in [-1, 1), octree height
+9, order 10 (seed 1005), in the compressed mixed mode (FP32 MFMA M2L on
+Chebyshev-coefficient accumulators, FP32 near field).  Its dense FP64
+evaluation does not fit in HBM, so the 1e-6 gate against FP64 is checked on
+its density twin (468,750 particles, height 7, the same 1.79 particles per
+leaf slot and the same order and tolerance), and the error against exact sums
+is measured at 256 seeded targets of the 30M set itself (GPU direct sums).
+The 1M-particle cube (height 6, order 7) and the 10M-particle sphere
+(height 8, order 7) are reported beside it, every precision mode checked
+against the dense FP64 path on the same inputs; a short serving leg runs a
+Poisson request stream.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -31,6 +37,18 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
 HBM_GBPS = 8000.0
 GATE = 1e-6
+MODES = ["fp64", "mixed", "fp64_svd", "mixed_svd"]
+HEADLINE = "cube30m_h9_p10"
+# Workloads whose dense FP64 evaluation does not fit in HBM are checked
+# against FP64 on their density twin: the same particles per leaf slot,
+# order and M2L tolerance, two levels fewer.
+TWIN = {"cube30m_h9_p10": "cube469k_h7_p10"}
+# Compressed-M2L tolerance per workload (None: the library default,
+# 10^-order).  At order 10 the mixed mode's error against FP64 is set by
+# the SVD truncation and the FP32 phase-1 sums; 1e-7 keeps the twin within
+# half the gate with about half the ranks of 1e-10.
+HEADLINE_EPS = {"cube30m_h9_p10": 1e-7, "cube469k_h7_p10": 1e-7}
+N_EXACT = 256  # seeded targets of the exact-sum check
 
 
 def rel(a, b):
@@ -39,7 +57,7 @@ def rel(a, b):
 
 def m2l_source_hash():
     h = hashlib.sha256()
-    for f in ("m2l.hip",):
+    for f in ("m2l.hip", "eval.hip"):
         h.update(open(os.path.join(ROOT, "paper_1206_0115_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -62,9 +80,10 @@ def load_traffic(workload, precision):
 
 def cpu_baseline(kind, n, h, l, seed, budget_s):
     """The oracle (plan + FMM, all host cores) on a bounded sample of the
-    workload.  The sample keeps the particle density and the leaf size: N/8
-    particles with one level fewer (the same seeded generator).  When 8x that
-    sample's time fits the budget, the full workload is timed instead."""
+    workload that keeps its particle density, leaf occupancy and order: N/8^k
+    particles of the same seeded generator with k levels fewer, starting
+    from height 4 and growing by one level while 9 times the last time still
+    fits the budget (the full workload if it does)."""
     import oracle
     from paper_1206_0115_amd import inputs
 
@@ -75,13 +94,14 @@ def cpu_baseline(kind, n, h, l, seed, budget_s):
         tree.fmm(l, q)
         return time.perf_counter() - t0
 
-    n_s, h_s = n // 8, h - 1
+    h_s = min(h, 4)
+    n_s = max(1, n // 8 ** (h - h_s))
     dt = run(n_s, h_s)
-    what = "density- and leaf-size-matched sample"
-    if 9.0 * dt <= budget_s:
-        n_s, h_s = n, h
+    while h_s < h and 9.0 * dt <= budget_s:
+        h_s += 1
+        n_s = n // 8 ** (h - h_s)
         dt = run(n_s, h_s)
-        what = "the full workload"
+    what = "the full workload" if h_s == h else "density-, occupancy- and order-matched sample"
     model = None
     try:
         with open("/proc/cpuinfo") as fh:
@@ -93,8 +113,8 @@ def cpu_baseline(kind, n, h, l, seed, budget_s):
         pass
     return {"value": n_s / dt, "unit": "particles/s", "cores": oracle.get_threads(),
             "kind": "oracle", "cpu_model": model,
-            "sample": f"{what}: {kind} N={n_s} height={h_s} order={l} seed={seed}, "
-                      f"plan+evaluate in {dt:.1f}s"}
+            "sample": f"{what}: {kind} N={n_s} height={h_s} order={l} seed={seed} "
+                      f"(dense M2L, FP64), plan+evaluate in {dt:.1f}s"}
 
 
 def serve_height(pos, target=64.0):
@@ -112,19 +132,20 @@ def serve_height(pos, target=64.0):
     return best
 
 
-def run_serve(args):
+def serve_leg(n_requests, loads, budget_gb, prec, seed=1004):
     """Serving loop under a Poisson request stream: N log-uniform in
     [1e4, 2e6], cube or sphere 50/50, order in {3, 5, 7, 9}, height for about
-    64 particles per leaf.  Latency p50/p99 and throughput at several loads,
-    against the same requests run one at a time."""
+    64 particles per leaf.  Latency p50/p99 and throughput at the given loads
+    (rho = arrival rate x mean one-at-a-time service time), against the same
+    requests run one at a time."""
     import torch
 
     from paper_1206_0115_amd import fmm, inputs
 
     fmm.lib()
-    rng = np.random.default_rng(1004)
+    rng = np.random.default_rng(seed)
     reqs = []
-    for i in range(args.requests):
+    for i in range(n_requests):
         n = int(np.exp(rng.uniform(np.log(1e4), np.log(2e6))))
         kind = "cube" if rng.random() < 0.5 else "sphere"
         l = int(rng.choice([3, 5, 7, 9]))
@@ -133,8 +154,7 @@ def run_serve(args):
         reqs.append((torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda(), h, l, n))
     torch.cuda.synchronize()
     total_n = sum(r[4] for r in reqs)
-    srv = fmm.Server(hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_active=32)
-    prec = args.serve_precision
+    srv = fmm.Server(hbm_budget_bytes=int(budget_gb * (1 << 30)), max_active=32)
 
     # warm the operator caches (every order) and graphs
     warm = {}
@@ -155,13 +175,13 @@ def run_serve(args):
            "config": {"workload": "poisson_serving", "requests": len(reqs),
                       "N": "log-uniform [1e4, 2e6]", "orders": [3, 5, 7, 9],
                       "kinds": "cube/sphere 50/50", "leaf_target": 64,
-                      "precision": prec, "budget_gb": args.serve_budget_gb},
+                      "precision": prec, "budget_gb": budget_gb},
            "one_at_a_time": {"particles_per_s": round(total_n / float(service.sum()), 1),
                              "mean_service_ms": round(1e3 * mean_s, 3),
                              "p50_ms": round(1e3 * float(np.percentile(service, 50)), 3),
                              "p99_ms": round(1e3 * float(np.percentile(service, 99)), 3)},
            "loads": []}
-    for rho in (0.5, 0.8, 0.95, 2.0):
+    for rho in loads:
         lam = rho / mean_s
         gaps = rng.exponential(1.0 / lam, len(reqs))
         t0 = srv.now()
@@ -183,15 +203,27 @@ def run_serve(args):
     out["server"] = {k: int(getattr(s, k)) for k, _ in fmm.ServerStats._fields_}
     srv.close()
     out["value"] = max(x["particles_per_s"] for x in out["loads"])
+    return out
+
+
+def run_serve(args):
+    out = serve_leg(args.requests, (0.5, 0.8, 0.95, 2.0), args.serve_budget_gb,
+                    args.serve_precision)
     print(json.dumps(out), flush=True)
 
 
 COPY_BYTES = 1 << 30  # the plain copy that calibrates the HBM counters
 
 
+def probe_modes(workload):
+    """The precision modes the traffic probe runs on a workload: all four
+    where the dense FP64 evaluation fits, else the compressed mixed mode."""
+    return ["mixed_svd"] if workload in TWIN else MODES
+
+
 def run_traffic_probe(args):
     """One copy of COPY_BYTES (device to device) and then, for every
-    precision mode, one plan + evaluation of the workload: the program that
+    precision mode of the workload, one plan + evaluation: the program that
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs to measure HBM traffic."""
     import torch
 
@@ -206,8 +238,8 @@ def run_traffic_probe(args):
     kind, n, h, l, seed = inputs.CONFIGS[args.workload]
     pos, q = inputs.make(kind, n, seed)
     pos_d, q_d = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
-    for m in ("fp64", "mixed", "fp64_svd", "mixed_svd"):
-        p = fmm.Plan(pos_d, h, l, m)
+    for m in probe_modes(args.workload):
+        p = fmm.Plan(pos_d, h, l, m, m2l_tolerance=HEADLINE_EPS.get(args.workload))
         p.evaluate(q_d)
         torch.cuda.synchronize()
         p.release()
@@ -231,14 +263,14 @@ def ingest_traffic(args):
 
     fetch = per_dispatch(args.ingest_traffic[0], "FETCH_SIZE")
     write = per_dispatch(args.ingest_traffic[1], "WRITE_SIZE")
-    modes = ["fp64", "mixed", "fp64_svd", "mixed_svd"]
+    modes = probe_modes(args.workload)
 
     def scale_and_m2l(rows):
         # the elementwise negation of the COPY_BYTES buffer is the largest
         # elementwise dispatch for both counters
         cal = max(v for _, k, v in rows if "elementwise" in k)
-        # one M2L step per mode: the M2L kernel, then (compressed modes run
-        # in parts) the kernel that adds the partial sums back
+        # one M2L step per mode: the M2L kernel, then the row pass that adds
+        # the partial sums back and turns coefficients into node values
         m2l = []
         for _, k, v in rows:
             if "m2l_kernel" in k or "m2l_svd_kernel" in k or "m2l_svd_ws_kernel" in k:
@@ -265,15 +297,240 @@ def ingest_traffic(args):
     print(json.dumps(d[args.workload]))
 
 
+class Bench:
+    """The measurements of one workload on one stream."""
+
+    def __init__(self, name, stream):
+        import torch
+
+        from paper_1206_0115_amd import fmm, inputs
+
+        self.fmm, self.torch = fmm, torch
+        self.name = name
+        self.kind, self.n, self.h, self.l, self.seed = inputs.CONFIGS[name]
+        self.eps = HEADLINE_EPS.get(name)
+        pos, q = inputs.make(self.kind, self.n, self.seed)
+        self.pos, self.q = pos, q
+        dev = torch.device("cuda:0")
+        self.stream = stream
+        self.pos_d = torch.from_numpy(pos).to(dev)
+        self.q_d = torch.from_numpy(q).to(dev)
+        self.phi = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.frc = torch.empty(self.n, 3, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+
+    def plan(self, prec, kernel="inv_r"):
+        return self.fmm.Plan(self.pos_d, self.h, self.l, prec, stream=self.stream,
+                             kernel=kernel, m2l_tolerance=self.eps)
+
+    def new_events(self, k):
+        ev = [self.torch.cuda.Event(enable_timing=True) for _ in range(k)]
+        for x in ev:  # materialise the HIP events before handing them over
+            x.record(self.stream)
+        return ev
+
+    def check_modes(self, quick_steps):
+        """Every mode against the dense FP64 path on the same inputs, and a
+        short timing of each."""
+        torch, s = self.torch, self.stream
+        out, infos = {}, {}
+        with torch.cuda.stream(s):
+            plan = self.plan("fp64")
+            p64, f64 = plan.evaluate(self.q_d, stream=s)
+            s.synchronize()
+            p64, f64 = p64.cpu().numpy(), f64.cpu().numpy()
+            for m in MODES:
+                plan.set_precision(m)
+                pm, fm = plan.evaluate(self.q_d, stream=s)
+                s.synchronize()
+                e_phi, e_f = rel(pm.cpu().numpy(), p64), rel(fm.cpu().numpy(), f64)
+                out[m] = {"rel_l2_vs_fp64": max(e_phi, e_f), "phi": e_phi, "F": e_f,
+                          "within_gate": max(e_phi, e_f) <= GATE,
+                          "m2l_split": plan.m2l_split()}
+                infos[m] = plan.info()
+            self.svd = plan.svd_info()
+            plan.release()
+        for m in MODES:
+            ms, _, m2l_ms = self.run_steps(m, quick_steps, 1)
+            out[m].update({"ms_per_step": round(ms, 4),
+                           "particles_per_s": round(self.n / (ms / 1e3), 1),
+                           "m2l_avg_ms": round(float(np.mean(m2l_ms)), 4),
+                           "m2l_flops": float(infos[m].m2l_flops)})
+        return out
+
+    def run_steps(self, prec, steps, warmup):
+        """Plan + evaluate + release per step on the default (forked)
+        schedule; the M2L launch bracketed by HIP events in every step."""
+        torch, fmm, s = self.torch, self.fmm, self.stream
+        with torch.cuda.stream(s):
+            ev = [self.new_events(4) for _ in range(steps + warmup)]
+            s.synchronize()
+            torch.cuda.synchronize()
+            t0 = None
+            for i, (s0, s1, m0, m1) in enumerate(ev):
+                if i == warmup:
+                    s.synchronize()
+                    t0 = time.perf_counter()
+                fmm.set_m2l_timing_events(m0, m1)
+                s0.record(s)
+                p = self.plan(prec)
+                p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+                s1.record(s)
+                if i == 0:
+                    self.info = p.info()
+                    self.split = p.m2l_split()
+                    self.step_svd = p.svd_info() if prec.endswith("svd") else None
+                p.release()
+            s.synchronize()
+            t1 = time.perf_counter()
+            fmm.set_m2l_timing_events(None, None)
+        torch.cuda.synchronize()
+        step_ms = np.array([a.elapsed_time(b) for a, b, _, _ in ev[warmup:]])
+        m2l_ms = np.array([a.elapsed_time(b) for _, _, a, b in ev[warmup:]])
+        return (t1 - t0) * 1e3 / steps, step_ms, m2l_ms
+
+    def eval_only(self, prec, steps):
+        torch, s = self.torch, self.stream
+        with torch.cuda.stream(s):
+            p = self.plan(prec)
+            p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+            s.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+            s.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3 / steps
+            p.release()
+        return dt
+
+    def step_times(self, prec, reps):
+        """Average duration of each bulk operator's kernel, every operator on
+        one stream (serial schedule, so no kernel shares the GPU)."""
+        torch, fmm, s = self.torch, self.fmm, self.stream
+        names = ("m2l", "p2p", "p2m", "l2p")
+        with torch.cuda.stream(s):
+            p = self.plan(prec)
+            p.set_schedule("serial")
+            p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+            ev = [self.new_events(2 * len(names)) for _ in range(reps)]
+            s.synchronize()
+            for e in ev:
+                for k, name in enumerate(names):
+                    fmm.set_step_timing_events(name, e[2 * k], e[2 * k + 1])
+                p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+            s.synchronize()
+            for name in names:
+                fmm.set_step_timing_events(name, None, None)
+            p.release()
+        return {name: float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
+                for k, name in enumerate(names)}
+
+    def exact_error(self, count):
+        """Error of the last evaluation's output against exact sums (GPU
+        direct summation over all sources) at `count` seeded targets."""
+        torch, s = self.torch, self.stream
+        idx = np.sort(np.random.default_rng(self.seed).choice(self.n, count, replace=False))
+        with torch.cuda.stream(s):
+            pe, fe = self.fmm.direct_sampled(self.pos_d, self.q_d,
+                                             torch.from_numpy(idx).cuda(), stream=s)
+            s.synchronize()
+        pe, fe = pe.cpu().numpy(), fe.cpu().numpy()
+        phi = self.phi.cpu().numpy()[idx]
+        frc = self.frc.cpu().numpy()[idx]
+        return {"targets": count, "phi": rel(phi, pe), "F": rel(frc, fe)}
+
+    def kernels(self, prec, reps):
+        st = self.step_times(prec, reps)
+        inf, n, l3 = self.info, self.n, self.l ** 3
+        flops = float(inf.m2l_flops)
+        peak = PEAK_TFLOPS["mixed" if prec.startswith("mixed") else "fp64"]
+        p2p_flops = 20.0 * float(inf.near_pairs)
+        p2m_bytes = 32.0 * n + 8.0 * l3 * float(inf.n_leaf)
+        l2p_bytes = 64.0 * n + 8.0 * l3 * float(inf.n_leaf)
+
+        def rate(work, ms, pk, unit, bound, what):
+            a = work / (ms / 1e3) / (1e12 if unit == "TFLOP/s" else 1e9)
+            return {"bound": bound, "avg_ms": round(ms, 4), "achieved": round(a, 2),
+                    "peak": pk, "unit": unit, "frac": round(a / pk, 4),
+                    "work_per_launch": work, "work": what}
+
+        return {
+            "m2l": rate(flops, st["m2l"], peak, "TFLOP/s", "mfma", "algorithmic flops"),
+            "p2p": rate(p2p_flops, st["p2p"], peak, "TFLOP/s", "valu",
+                        "20 flops per directed near pair"),
+            "p2m": rate(p2m_bytes, st["p2m"], HBM_GBPS, "GB/s", "hbm",
+                        "32 B per particle read + l^3 x 8 B per leaf written"),
+            "l2p": rate(l2p_bytes, st["l2p"], HBM_GBPS, "GB/s", "hbm",
+                        "64 B per particle read and written + l^3 x 8 B per leaf read"),
+        }
+
+    def second_kernel(self, prec, steps):
+        """The 1/r^2 kernel on the same workload and mode: plan + evaluate +
+        release per step, and its error against its own FP64 evaluation."""
+        torch, s = self.torch, self.stream
+        with torch.cuda.stream(s):
+            ref = self.plan("fp64", kernel="inv_r2")
+            pr, fr = ref.evaluate(self.q_d, stream=s)
+            s.synchronize()
+            pr, fr = pr.cpu().numpy(), fr.cpu().numpy()
+            ref.release()
+            p = self.plan(prec, kernel="inv_r2")
+            pm, fm = p.evaluate(self.q_d, stream=s)
+            s.synchronize()
+            err = max(rel(pm.cpu().numpy(), pr), rel(fm.cpu().numpy(), fr))
+            p.release()
+            for i in range(steps + 1):
+                if i == 1:
+                    s.synchronize()
+                    t0 = time.perf_counter()
+                p = self.plan(prec, kernel="inv_r2")
+                p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+                p.release()
+            s.synchronize()
+            dt = (time.perf_counter() - t0) * 1e3 / steps
+        return {"kernel": "1/r^2", "precision": prec, "ms_per_step": round(dt, 4),
+                "particles_per_s": round(self.n / (dt / 1e3), 1), "rel_l2_vs_fp64": err}
+
+    def release(self):
+        del self.pos_d, self.q_d, self.phi, self.frc
+        self.torch.cuda.synchronize()
+        self.torch.cuda.empty_cache()
+        self.fmm.trim_cache()
+
+
+def side_config(name, stream, steps):
+    """A workload reported beside the headline: every mode against FP64 on
+    it, the fastest mode within the gate timed, its error against exact sums."""
+    b = Bench(name, stream)
+    modes = b.check_modes(max(3, steps // 4))
+    ok = [m for m in MODES if modes[m]["within_gate"]]
+    prec = min(ok, key=lambda m: modes[m]["ms_per_step"])
+    ms, step_ms, m2l_ms = b.run_steps(prec, steps, 2)
+    out = {"kind": b.kind, "N": b.n, "height": b.h, "order": b.l, "seed": b.seed,
+           "precision": prec, "m2l_svd_tolerance": b.svd.eps,
+           "ms_per_step": round(ms, 4), "particles_per_s": round(b.n / (ms / 1e3), 1),
+           "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
+           "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
+           "eval_only_ms": round(b.eval_only(prec, max(5, steps)), 4),
+           "rel_l2_vs_fp64": modes[prec]["rel_l2_vs_fp64"],
+           "rel_l2_vs_exact": b.exact_error(N_EXACT), "modes": modes,
+           "kernels": b.kernels(prec, 5)}
+    if name == "cube1m_h6_p7":
+        out["second_kernel"] = b.second_kernel(prec, max(5, steps // 2))
+    b.release()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube1m_h6_p7")
-    ap.add_argument("--precision", default="auto",
-                    choices=["auto", "fp64", "mixed", "fp64_svd", "mixed_svd"])
+    ap.add_argument("--workload", default=HEADLINE)
+    ap.add_argument("--precision", default="auto", choices=["auto"] + MODES)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="only the headline workload (no side configurations, no serving leg)")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--serve", action="store_true",
                     help="benchmark the serving loop instead (Poisson request stream)")
@@ -283,8 +540,7 @@ def main():
                     help="write profiles/m2l_traffic.json from the two counter CSVs")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serve-precision", default="mixed_svd",
-                    choices=["fp64", "mixed", "fp64_svd", "mixed_svd"])
+    ap.add_argument("--serve-precision", default="mixed_svd", choices=MODES)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -306,181 +562,64 @@ def main():
 
     import torch
 
-    from paper_1206_0115_amd import fmm, inputs
+    from paper_1206_0115_amd import fmm
 
     fmm.lib()  # fails loudly if the HIP library is not built
-    kind, n, h, l, seed = inputs.CONFIGS[args.workload]
-    pos, q = inputs.make(kind, n, seed)
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.Stream(device=dev)
-    pos_d = torch.from_numpy(pos).to(dev)
-    q_d = torch.from_numpy(q).to(dev)
-    phi = torch.empty(n, dtype=torch.float64, device=dev)
-    frc = torch.empty(n, 3, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
+    stream = torch.cuda.Stream(device=torch.device("cuda:0"))
+    name = args.workload
+    twin = TWIN.get(name)
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    # dense FP64 reference, and every mode's error against it on the same inputs
-    modes = ["fp64", "mixed", "fp64_svd", "mixed_svd"]
-    errors, infos, splits = {}, {}, {}
-    with torch.cuda.stream(stream):
-        plan = fmm.Plan(pos_d, h, l, "fp64", stream=stream)
-        p64, f64 = plan.evaluate(q_d, stream=stream)
-        stream.synchronize()
-        p64, f64 = p64.cpu().numpy(), f64.cpu().numpy()
-        for m in modes:
-            plan.set_precision(m)
-            pm, fm = plan.evaluate(q_d, stream=stream)
-            stream.synchronize()
-            errors[m] = max(rel(pm.cpu().numpy(), p64), rel(fm.cpu().numpy(), f64))
-            infos[m] = plan.info()
-            splits[m] = plan.m2l_split()
-        svd = plan.svd_info()
-        plan.release()
-    ok = [m for m in modes if errors[m] <= GATE]
-
-    def new_events(k):
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k)]
-        for x in ev:  # materialise the HIP events before handing them over
-            x.record(stream)
-        return ev
-
-    def run_steps(prec, steps, warmup):
-        """Plan + evaluate + release per step on the default (forked)
-        schedule; the M2L launch bracketed by HIP events in every step."""
-        with torch.cuda.stream(stream):
-            ev = [new_events(4) for _ in range(steps + warmup)]
-            stream.synchronize()
-            torch.cuda.synchronize()
-            t0 = None
-            for i, (s0, s1, m0, m1) in enumerate(ev):
-                if i == warmup:
-                    stream.synchronize()
-                    t0 = time.perf_counter()
-                fmm.set_m2l_timing_events(m0, m1)
-                s0.record(stream)
-                p = fmm.Plan(pos_d, h, l, prec, stream=stream)
-                p.evaluate(q_d, phi, frc, stream=stream)
-                s1.record(stream)
-                p.release()
-            stream.synchronize()
-            t1 = time.perf_counter()
-            fmm.set_m2l_timing_events(None, None)
-        torch.cuda.synchronize()
-        step_ms = np.array([a.elapsed_time(b) for a, b, _, _ in ev[warmup:]])
-        m2l_ms = np.array([a.elapsed_time(b) for _, _, a, b in ev[warmup:]])
-        return (t1 - t0) * 1e3 / steps, step_ms, m2l_ms
-
-    def step_times(prec, reps):
-        """Average duration of each bulk operator's kernel, every operator on
-        one stream (serial schedule, so no kernel shares the GPU)."""
-        names = ("m2l", "p2p", "p2m", "l2p")
-        with torch.cuda.stream(stream):
-            p = fmm.Plan(pos_d, h, l, prec, stream=stream)
-            p.set_schedule("serial")
-            p.evaluate(q_d, phi, frc, stream=stream)
-            ev = [new_events(2 * len(names)) for _ in range(reps)]
-            stream.synchronize()
-            for e in ev:
-                for k, name in enumerate(names):
-                    fmm.set_step_timing_events(name, e[2 * k], e[2 * k + 1])
-                p.evaluate(q_d, phi, frc, stream=stream)
-            stream.synchronize()
-            for name in names:
-                fmm.set_step_timing_events(name, None, None)
-            p.release()
-        return {name: float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
-                for k, name in enumerate(names)}
-
-    def eval_only(prec, steps):
-        with torch.cuda.stream(stream):
-            p = fmm.Plan(pos_d, h, l, prec, stream=stream)
-            p.evaluate(q_d, phi, frc, stream=stream)
-            stream.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                p.evaluate(q_d, phi, frc, stream=stream)
-            stream.synchronize()
-            dt = (time.perf_counter() - t0) * 1e3 / steps
-            p.release()
-        return dt
-
-    # the headline: the fastest mode within the error gate, timed over the full
-    # step count; every other mode with a shorter run
+    # the gate: every mode against dense FP64, on the workload or its twin
+    log(f"modes against FP64 on {twin or name}")
+    g = Bench(twin or name, stream)
+    gate = g.check_modes(3)
+    g.release()
+    ok = [m for m in MODES if gate[m]["within_gate"]]
     if args.precision != "auto":
-        ok = [args.precision]
-    quick = {}
-    for m in modes:
-        quick[m] = run_steps(m, max(3, args.steps // 4), 1)
-    precision = min(ok, key=lambda m: quick[m][0])
-    ms, step_ms, m2l_ms = run_steps(precision, args.steps, args.warmup)
-    eval_ms = eval_only(precision, max(5, args.steps))
+        precision = args.precision
+    elif twin:
+        # at the twin's size every mode runs; at the full size only the
+        # compressed ones are practical (dense order-10 M2L: 5e15 flops)
+        precision = min([m for m in ok if m.endswith("svd")],
+                        key=lambda m: gate[m]["ms_per_step"])
+    else:
+        precision = min(ok, key=lambda m: gate[m]["ms_per_step"])
 
-    flops = float(infos[precision].m2l_flops)
+    log(f"headline {name} {precision}: {args.warmup} + {args.steps} steps")
+    b = Bench(name, stream)
+    ms, step_ms, m2l_ms = b.run_steps(precision, args.steps, args.warmup)
+    exact = b.exact_error(N_EXACT)
+    log(f"headline {ms:.1f} ms per step; eval only")
+    eval_ms = b.eval_only(precision, 3 if b.n > 10_000_000 else max(5, args.steps))
+    log("kernels (serial schedule)")
+    kernels = b.kernels(precision, 2 if b.n > 10_000_000 else 10)
+    inf = b.info
+    flops = float(inf.m2l_flops)
     m2l_s = float(np.mean(m2l_ms)) / 1e3
     achieved = flops / m2l_s / 1e12
     peak = PEAK_TFLOPS["mixed" if precision.startswith("mixed") else "fp64"]
-    kernel = "m2l_svd_ws_kernel" if precision.endswith("svd") else "m2l_kernel"
-    roof = {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 2),
-            "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": load_traffic(args.workload, precision),
-            "flops_per_launch": flops, "far_pairs": int(infos[precision].far_pairs),
-            "m2l_split": splits[precision],
-            "avg_launch_ms": round(m2l_s * 1e3, 4)}
+    roof = {"bound": "mfma",
+            "kernel": "m2l_svd_ws_kernel" if precision.endswith("svd") else "m2l_kernel",
+            "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": load_traffic(name, precision),
+            "flops_per_launch": flops, "far_pairs": int(inf.far_pairs),
+            "m2l_split": b.split, "avg_launch_ms": round(m2l_s * 1e3, 4)}
+    sv = b.step_svd
+    kind, n, h, l, seed = b.kind, b.n, b.h, b.l, b.seed
+    b.release()
 
-    # every bulk operator against the roof that bounds it (serial schedule)
-    st = step_times(precision, 10)
-    inf = infos[precision]
-    l3 = l ** 3
-    p2p_flops = 20.0 * float(inf.near_pairs)
-    p2m_bytes = 32.0 * n + 8.0 * l3 * float(inf.n_leaf)
-    l2p_bytes = 64.0 * n + 8.0 * l3 * float(inf.n_leaf)
-    vpeak = PEAK_TFLOPS["mixed" if precision.startswith("mixed") else "fp64"]
-
-    def rate(work, ms, peak, unit, bound, what):
-        a = work / (ms / 1e3) / (1e12 if unit == "TFLOP/s" else 1e9)
-        return {"bound": bound, "avg_ms": round(ms, 4), "achieved": round(a, 2), "peak": peak,
-                "unit": unit, "frac": round(a / peak, 4), "work_per_launch": work, "work": what}
-
-    kernels = {
-        "m2l": rate(flops, st["m2l"], peak, "TFLOP/s", "mfma", "algorithmic flops"),
-        "p2p": rate(p2p_flops, st["p2p"], vpeak, "TFLOP/s", "valu",
-                    "20 flops per directed near pair"),
-        "p2m": rate(p2m_bytes, st["p2m"], HBM_GBPS, "GB/s", "hbm",
-                    "32 B per particle read + l^3 x 8 B per leaf written"),
-        "l2p": rate(l2p_bytes, st["l2p"], HBM_GBPS, "GB/s", "hbm",
-                    "64 B per particle read and written + l^3 x 8 B per leaf read"),
-    }
-
-    def second_kernel(prec, steps):
-        """The 1/r^2 kernel on the same workload and mode: plan + evaluate +
-        release per step, and its error against its own FP64 evaluation."""
-        with torch.cuda.stream(stream):
-            ref = fmm.Plan(pos_d, h, l, "fp64", stream=stream, kernel="inv_r2")
-            pr, fr = ref.evaluate(q_d, stream=stream)
-            stream.synchronize()
-            pr, fr = pr.cpu().numpy(), fr.cpu().numpy()
-            ref.release()
-            p = fmm.Plan(pos_d, h, l, prec, stream=stream, kernel="inv_r2")
-            pm, fm = p.evaluate(q_d, stream=stream)
-            stream.synchronize()
-            err = max(rel(pm.cpu().numpy(), pr), rel(fm.cpu().numpy(), fr))
-            p.release()
-            for i in range(steps + 1):
-                if i == 1:
-                    stream.synchronize()
-                    t0 = time.perf_counter()
-                p = fmm.Plan(pos_d, h, l, prec, stream=stream, kernel="inv_r2")
-                p.evaluate(q_d, phi, frc, stream=stream)
-                p.release()
-            stream.synchronize()
-            dt = (time.perf_counter() - t0) * 1e3 / steps
-        return {"kernel": "1/r^2", "precision": prec, "ms_per_step": round(dt, 4),
-                "particles_per_s": round(n / (dt / 1e3), 1), "rel_l2_vs_fp64": err}
-
-    kernel2 = second_kernel(precision, max(5, args.steps // 2))
+    side, serving = {}, None
+    if not args.no_side:
+        for cfg in ("cube1m_h6_p7", "sphere10m_h8_p7"):
+            log(f"side configuration {cfg}")
+            side[cfg] = side_config(cfg, stream, args.steps)
+        log("serving leg")
+        serving = serve_leg(60, (0.8,), 64.0, "mixed_svd")
 
     base = None
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         base = cpu_baseline(kind, n, h, l, seed, args.cpu_budget)
 
     value = n / (ms / 1e3)
@@ -497,25 +636,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if precision.startswith("mixed") else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "kind": kind, "N": n, "height": h, "order": l,
+        "config": {"workload": name, "kind": kind, "N": n, "height": h, "order": l,
                    "seed": seed, "precision": precision,
-                   "m2l_svd_tolerance": svd.eps if precision.endswith("svd") else None,
+                   "m2l_svd_tolerance": sv.eps if sv else None,
                    "step": "plan+evaluate+release, inputs resident in HBM",
                    "schedule": "forked (near field beside the far chain)"},
         "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "eval_only_ms": round(eval_ms, 4),
         "eval_only_particles_per_s": round(n / (eval_ms / 1e3), 1),
-        "rel_l2_vs_fp64": errors[precision],
-        "modes": {m: {"rel_l2_vs_fp64": errors[m], "within_gate": errors[m] <= GATE,
-                      "ms_per_step": round(quick[m][0], 4),
-                      "particles_per_s": round(n / (quick[m][0] / 1e3), 1),
-                      "m2l_avg_ms": round(float(np.mean(quick[m][2])), 4),
-                      "m2l_flops": float(infos[m].m2l_flops)} for m in modes},
-        "svd_weighted_rank": round(svd.weighted_rank, 3),
+        "rel_l2_vs_fp64": gate[precision]["rel_l2_vs_fp64"],
+        "gate_checked_on": twin or name,
+        "rel_l2_vs_exact": exact,
+        "modes": gate,
+        "svd_weighted_rank": round(sv.weighted_rank, 3) if sv else None,
         "roofline": roof,
         "kernels": kernels,
-        "second_kernel": kernel2,
+        "configs": side,
+        "serving": serving,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -55,14 +55,22 @@ enum fmm_precision {
    * M2L as FP32 MFMA contractions with FP32 accumulation folded into FP64 per
    * far offset; P2M, M2M, L2L, L2P and the output sums stay FP64 */
   FMM_MIXED_FP32 = 1,
+  /* Reserved for M2L as BF16 MFMA products with FP32 accumulation.  Not
+   * built: BF16 keeps 8 significant bits, so even a two-term (hi + lo)
+   * split of every operand carries a relative error of about 2^-17 per
+   * product, far above what the 1e-6 relative L2 gate of the mixed modes
+   * leaves (FP32 products already use most of it at order 10).
+   * fmm_plan_set_precision and fmm_server_submit return FMM_ERR_ARG. */
+  FMM_MIXED_BF16 = 2,
+  /* Extensions beyond the three modes above. */
   /* FMM_FP64 with the compressed M2L of Sec. 2.1.2 ("improved M2L"): each of
    * the 16 canonical operators factorised by one SVD, truncated at singular
    * values s_k >= eps s_1 (eps from fmm_plan_set_m2l_tolerance; default
    * 10^-order as in the paper's accuracy setting, at most down to 1e-10),
    * applied as two skinny MFMA products per far offset */
-  FMM_FP64_SVD = 2,
+  FMM_FP64_SVD = 3,
   /* FMM_MIXED_FP32 with the compressed M2L in FP32 MFMA (FP64 folding) */
-  FMM_MIXED_SVD = 3
+  FMM_MIXED_SVD = 4
 };
 
 /* Truncation tolerance of the compressed M2L (0 < eps < 1); takes effect for
@@ -264,22 +272,46 @@ int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1);
 enum fmm_timed_step { FMM_TIME_M2L = 0, FMM_TIME_P2P = 1, FMM_TIME_P2M = 2, FMM_TIME_L2P = 3 };
 int fmm_set_step_timing_events(int step, hipEvent_t ev0, hipEvent_t ev1);
 
+/*
+ * Exact sums at chosen targets: the direct summation of Eq. (1) with the
+ * kernel of Eq. (2) (or 1/r^2, enum fmm_kernel) over all n sources, the
+ * result the FMM approximates, for checking it at a sample of particles:
+ *   potential[k] = sum_{j: r > 0} q_j / r^p,
+ *   forces[k]    = q_i sum_{j: r > 0} q_j p (x_i - x_j) / r^(p+2),
+ * i = targets[k], r = |x_i - x_j|; pairs at zero distance are skipped.
+ *   positions  device [n][3] f64; charges device [n] f64
+ *   targets    device [nt] int64, indices into the particles (1 <= nt <= 2^30);
+ *              an index outside [0, n) gives NaN results for that target
+ *   potential  device [nt] f64, forces device [nt][3] f64 (outputs, in
+ *              target order, overwritten)
+ * FP64 throughout; the sources are summed in fixed chunks, so results are
+ * bit-identical from call to call.  Allocates a partial-sum buffer of
+ * 32 * ceil(nt / 64) * 64 * chunks bytes (at most 8 MiB) and waits for the
+ * stream before returning.  Errors: FMM_ERR_ARG (null pointer, sizes,
+ * kernel), FMM_ERR_OOM, FMM_ERR_HIP.
+ */
+int fmm_direct_sampled(const double* positions, const double* charges, int64_t n,
+                       const int64_t* targets, int64_t nt, int kernel, double* potential,
+                       double* forces, hipStream_t stream);
+
 /* Return cached device memory of released plans to the HIP runtime. */
 void fmm_trim_cache(void);
 
 /*
  * Serving loop: a device-resident request loop that evaluates many particle
  * sets of different size and order concurrently (continuous batching).  A
- * worker thread plans arriving requests on its own stream, admits them while
- * the sum of their plans' device footprints stays within `hbm_budget_bytes`
- * and at most `max_active` are admitted, and evaluates the admitted requests
- * in batches: each operator of the evaluation pass (Sec. 3.2's P2M, M2M, M2L,
- * L2L, L2P, P2P) runs as one persistent launch over the work items of every
- * request in the batch (requests of equal order share the M2L, P2M and L2P
- * launches), and a batch's launch sequence is captured once as a hipGraph and
- * replayed with new work tables.  Requests that arrive while batches run are
- * planned meanwhile and join the next batch as memory frees up.  A request's
- * results are bit-identical to fmm_evaluate on the same inputs.
+ * planner thread plans arriving requests on its own stream and admits them
+ * while the sum of their plans' device footprints stays within
+ * `hbm_budget_bytes` and at most `max_active` are admitted; a launcher
+ * thread evaluates the admitted requests in batches: each operator of the
+ * evaluation pass (Sec. 3.2's P2M, M2M, M2L, L2L, L2P, P2P) runs as one
+ * persistent launch over the work items of every request in the batch
+ * (requests of equal order share the M2L, P2M and L2P launches), and a
+ * batch's launch sequence is captured once as a hipGraph and replayed with
+ * new work tables.  Up to two batches run at once, each on its own stream:
+ * requests that arrive while a batch runs are planned meanwhile and start as
+ * soon as they are admitted, beside it on the device.  A request's results
+ * are bit-identical to fmm_evaluate on the same inputs.
  */
 typedef struct fmm_server_s* fmm_server_t;
 
@@ -308,13 +340,24 @@ fmm_server_t fmm_server_create(size_t hbm_budget_bytes, int max_active);
  * Queue one evaluation.  positions [n][3], charges [n], potential [n] and
  * forces [n][3] are device pointers that the caller keeps valid and untouched
  * until the request is done.  height, order as for fmm_plan; precision an
- * fmm_precision.  Returns a ticket >= 0, or a negative fmm_status for invalid
- * arguments (checked before anything is queued).  A request whose plan alone
- * exceeds the budget finishes with status FMM_ERR_OOM.
+ * fmm_precision (FMM_MIXED_BF16 is refused).  `stream` is the caller's
+ * stream: the server reads the inputs and writes the outputs only after the
+ * work queued on it at this call (an event recorded here).  Returns a ticket
+ * >= 0, or a negative fmm_status for invalid arguments (checked before
+ * anything is queued) or a failed event record (FMM_ERR_HIP).  A request
+ * whose plan alone exceeds the budget finishes with status FMM_ERR_OOM; a
+ * plan that fails finishes with the plan's own status (FMM_ERR_OOM,
+ * FMM_ERR_HIP, ...), its message kept with the request.
  */
 int64_t fmm_server_submit(fmm_server_t srv, const double* positions, const double* charges,
                           int64_t n, int height, int order, int precision,
-                          double* potential, double* forces);
+                          double* potential, double* forces, hipStream_t stream);
+
+/* Message of a finished request's failure ("" if it succeeded or is not
+ * done), copied NUL-terminated into buf[len] (truncated if longer); returns
+ * the message length, or FMM_ERR_ARG for an unknown ticket or a NULL buffer
+ * with len > 0. */
+int fmm_server_request_error(fmm_server_t srv, int64_t ticket, char* buf, size_t len);
 
 /* Non-blocking: 1 if the request is done (its status in st->status), 0 if not,
  * FMM_ERR_ARG for an unknown ticket.  `st` may be NULL. */

@@ -15,6 +15,7 @@
 namespace fmm {
 namespace {
 thread_local std::string g_last_error;
+thread_local int g_last_code = FMM_OK;
 
 StepTab one_job(int items, int level = 0) {
   StepTab t;
@@ -29,6 +30,8 @@ StepTab one_job(int items, int level = 0) {
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+void set_error_code(int code) { g_last_code = code; }
+int last_error_code() { return g_last_code; }
 
 // Offset ranges per compressed-M2L tile.  Every tile's item runs all of its
 // far offsets, so with few items the last round of resident workgroups is
@@ -94,6 +97,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   }
   J.ntiles = int(p->ntiles);
   J.has_far = h >= 3;
+  J.modal = fp32 && h >= 3 ? 1 : 0;
   // compressed M2L split (targets are the cells of levels 2 .. h-1)
   int parts = 1;
   const int64_t lrows = h >= 3 ? int64_t(p->ncell_total) - int64_t(p->lev[2].off) : 0;
@@ -149,6 +153,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.kp32 = op->kpack32;
   J.slot_kid = op->slot_kid;
   J.cheb = op->cheb;
+  J.tcheb = op->tcheb;
   J.child = op->child;
   J.phi_n = p->phi_n;
   J.f_n = p->f_n;
@@ -162,7 +167,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
     p->tab_h[kTabCast] = one_job(int((p->w32_leaf ? p->lev[h - 1].off : p->ncell_total + 1) -
                                      p->lev[2].off));
     p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb * parts);
-    p->tab_h[kTabLocSum] = one_job(parts > 1 ? int(lrows) : 0);
+    p->tab_h[kTabLocSum] = one_job(parts > 1 || J.modal ? int(lrows) : 0);
     for (int st = 0; st + 4 <= h; ++st) {
       p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
       // L2L items are the parents (level 2 + st) of the cells it updates
@@ -210,6 +215,7 @@ namespace {
 
 int fail(int code, const std::string& msg) {
   fmm::set_error(msg);
+  fmm::set_error_code(code);
   return code;
 }
 
@@ -250,6 +256,7 @@ const char* fmm_last_error(void) { return fmm::g_last_error.c_str(); }
 fmm_plan_t fmm_plan_stream(const double* positions, int64_t n, int height, int order,
                            hipStream_t stream) {
   fmm::set_error("");
+  fmm::set_error_code(FMM_OK);
   if (!positions) {
     fail(FMM_ERR_ARG, "positions is NULL");
     return nullptr;
@@ -392,6 +399,9 @@ static void apply_mode(fmm_plan_s* p, int mode) {
 
 int fmm_plan_set_precision(fmm_plan_t p, int mode) {
   if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (mode == FMM_MIXED_BF16)
+    return fail(FMM_ERR_ARG, "FMM_MIXED_BF16 is not built (BF16 products cannot meet the "
+                             "1e-6 gate of the mixed modes); use FMM_MIXED_FP32 or FMM_MIXED_SVD");
   if (mode < FMM_FP64 || mode > FMM_MIXED_SVD)
     return fail(FMM_ERR_ARG, "unknown precision mode " + std::to_string(mode));
   return guarded([&]() -> int {

@@ -610,12 +610,19 @@ __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ 
   }
 }
 
-// ------------------------------------------------- compressed M2L parts
-// Item = row of levels >= 2 of a job whose compressed M2L ran in parts:
+// ------------------------------------------ M2L parts and coefficient rows
+// Item = row of levels >= 2 of a job whose M2L ran in parts or in FP32:
 // Loc += the partial local expansions of parts 1 .. K-1, added in part order
-// (one FP64 sum per element, the same order every run).
+// (one FP64 sum per element, the same order every run); then, where the FP32
+// M2L left Chebyshev coefficients c (J.modal), the node values
+//     Loc[m1][m2][m3] = sum_n T_n1(xb_m1) T_n2(xb_m2) T_n3(xb_m3) c[n1][n2][n3]
+// of their interpolant (Eq. 5), in FP64 as three 1-D passes (6 l^4 flops).
+constexpr int kMaxLd = kMaxOrder * kMaxOrder * kMaxOrder;
 __global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__ jobs,
                                                       const StepTab* __restrict__ tab) {
+  __shared__ double va[kMaxLd], vb[kMaxLd];
+  __shared__ double A[kMaxOrder * kMaxOrder];
+  const int t = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
@@ -623,11 +630,49 @@ __global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__
     const int64_t n = J.locx_rows * J.ld;
     double* loc = J.Loc + (J.locx_first + r) * J.ld;
     const double* x = J.LocX + r * J.ld;
-    for (int e = threadIdx.x; e < J.ld; e += 256) {
+    const int parts = wuni(J.m2l_parts);
+    if (!wuni(J.modal)) {
+      for (int e = t; e < J.ld; e += 256) {
+        double v = gld(loc + e);
+        for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
+        gst(loc + e, v);
+      }
+      continue;
+    }
+    const int L = wuni(J.order), L2 = L * L, l3 = L2 * L;
+    for (int e = t; e < L2; e += 256) A[e] = J.tcheb[e];
+    for (int e = t; e < l3; e += 256) {
       double v = gld(loc + e);
-      for (int p = 1; p < J.m2l_parts; ++p) v += gld(x + (p - 1) * n + e);
+      for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
+      va[e] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < l3; e += 256) {  // along z: (n1, n2, n3) -> (n1, n2, m3)
+      const int m3 = e % L;
+      const double* src = va + (e - m3);
+      double v = 0.0;
+      for (int j = 0; j < L; ++j) v += A[m3 * L + j] * src[j];
+      vb[e] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < l3; e += 256) {  // along y: (n1, n2, m3) -> (n1, m2, m3)
+      const int m3 = e % L, m2 = (e / L) % L, n1 = e / L2;
+      const double* src = vb + n1 * L2 + m3;
+      double v = 0.0;
+      for (int j = 0; j < L; ++j) v += A[m2 * L + j] * src[j * L];
+      va[e] = v;
+    }
+    __syncthreads();
+    for (int e = t; e < J.ld; e += 256) {  // along x: (n1, m2, m3) -> (m1, m2, m3)
+      double v = 0.0;
+      if (e < l3) {
+        const int m1 = e / L2;
+        const double* src = va + (e - m1 * L2);
+        for (int j = 0; j < L; ++j) v += A[m1 * L + j] * src[j * L2];
+      }
       gst(loc + e, v);
     }
+    __syncthreads();
   }
 }
 

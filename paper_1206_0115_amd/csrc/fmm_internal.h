@@ -35,6 +35,10 @@ constexpr int kOffsets = 316;  // distinct far offsets
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
+// status code of the calling thread's last failure (FMM_OK if none since
+// the last fmm_plan call on the thread)
+void set_error_code(int code);
+int last_error_code();
 struct FmmError {
   int code;
   std::string msg;
@@ -71,9 +75,10 @@ void* pinned_staging(size_t bytes);
 struct OpSet {
   int order = 0, l3 = 0, ld = 0, mt = 0, kc = 0;
   double* cheb = nullptr;     // [l][l]: C[m][n] = (n==0 ? 1 : 2 T_n(xb_m)) / l
+  double* tcheb = nullptr;    // [l][l]: T_n(xb_m), Chebyshev coefficients -> node values
   double* child = nullptr;    // [2][l][l]: S(xb_m; (s + xb_m')/2), s = -1, +1
   double* kpack64 = nullptr;  // [316][mt][kc][64][4] unit M2L operators, MFMA order
-  float* kpack32 = nullptr;   // same in FP32
+  float* kpack32 = nullptr;   // FP32, rows in the Chebyshev-coefficient basis (see m2l.hip)
   int* slot_kid = nullptr;    // [8][189] packed-operator index of each slot
   signed char* slot_t = nullptr;  // [8][189][3] offset (tx, ty, tz) of each slot
 };
@@ -101,6 +106,20 @@ struct SvdOps {
 };
 const SvdOps* get_svd_ops(int order, double eps, int kernel, hipStream_t stream);
 int kid_canon(int kid);  // canonical class (0..15) of packed operator kid
+
+// ------------------------------------------- exact sums at sampled targets
+// (direct.hip) The sources are cut into direct_chunks(n, nt) chunks, each
+// summed by its own workgroups into a partial-sum buffer of
+// direct_partial_doubles(nt, chunks) <= kDirectPartialMax doubles, which
+// launch_direct then adds in chunk order.
+constexpr int64_t kDirectPartialMax = int64_t(1) << 20;
+int direct_chunks(int64_t n, int64_t nt);
+size_t direct_partial_doubles(int64_t nt, int chunks);
+void launch_direct(const double* pos, const double* q, int64_t n, const int64_t* targets,
+                   int64_t nt, int p, double* phi, double* f, double* part, int chunks,
+                   hipStream_t s);
+int direct_check_args(const double* pos, const double* q, int64_t n, const int64_t* targets,
+                      int64_t nt, int kernel, const double* phi, const double* f);
 
 // ------------------------------------------------------------- the plan
 struct M2LTile {

@@ -41,6 +41,9 @@ struct JobDev {
   int kernel;  // p of the kernel |x - y|^-p (1 or 2)
   int w32_leaf;  // leaf multipoles live in W32 only (W holds levels < h-1)
   int fold_every;  // compressed FP32 M2L: far offsets between FP64 folds
+  // FP32 M2L (mixed modes): the local expansions of levels >= 2 leave M2L
+  // as Chebyshev coefficients and become node values in the loc-sum pass
+  int modal;
   // compressed M2L split: each tile's far offsets in m2l_parts consecutive
   // ranges, one work item each; part 0 writes Loc, part p > 0 the rows
   // (p - 1) * locx_rows + (target row - locx_first) of LocX
@@ -76,6 +79,7 @@ struct JobDev {
   const float* p2_32;
   const int* slot_kid;
   const double* cheb;
+  const double* tcheb;  // [l][l] T_n(xb_m)
   const double* child;
   double* phi_n;  // near/far partial results in sorted order
   double* f_n;

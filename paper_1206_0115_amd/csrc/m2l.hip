@@ -12,6 +12,21 @@
 //     Kh_t[m][n] = Kh_tc[g(m)][g(n)],  g(m)_{pi(d)} = s_d > 0 ? m_d : l-1-m_d,
 // because the mirrored Chebyshev nodes satisfy xb_{l-1-k} = -xb_k.
 //
+// FP32 operators (mixed modes) have their rows in the Chebyshev-coefficient
+// basis instead of node values: Kh'_t = T3 Kh_t with T3 = T1 (x) T1 (x) T1,
+// T1[n][m] = C[m][n] = (n == 0 ? 1 : 2 T_n(xb_m)) / l, which maps the values
+// of a degree < l polynomial at the nodes to its Chebyshev coefficients
+// (Eq. 5).  A local expansion then accumulates in FP32 as coefficients,
+// whose magnitudes fall with the degree like those of the smooth far field
+// they describe, so each rounding error is relative to its own coefficient;
+// summed as node values, the rounding errors are alike at every node and the
+// force, the gradient of the interpolant (L2P), multiplies their
+// high-degree part by up to l^2.  The loc-sum pass turns the coefficients
+// back into node values in FP64 (T3^-1: T_n(xb_m) along each dimension).
+// Mirroring a dimension maps T_n to (-1)^n T_n, so the signed permutations
+// act on coefficient rows as permutations with the sign (-1)^(sum of the
+// mirrored dimensions' degrees).
+//
 // The contraction is organised target-stationary: a work tile holds 64
 // target cells of one level and one child parity, which share the same 189
 // offsets; for each offset the tile computes Y(l^3 x 64) += Kh_t (l^3 x l^3)
@@ -150,12 +165,54 @@ __global__ void canon_kernel(const double* __restrict__ xi, const int* __restric
   }
 }
 
+// Rows to Chebyshev coefficients:
+//   out[c][u][col] = sum_a T3[u][a] in[c][a][col],  T3[u][a] = prod_d C[a_d][u_d]
+// for nmat row-major l^3 x ncol matrices (a and u are node and degree triples).
+__global__ void modal_rows_kernel(const double* __restrict__ in, const double* __restrict__ cheb,
+                                  int l, int ncol, int nmat, double* __restrict__ out) {
+  const int l3 = l * l * l;
+  const int64_t total = int64_t(nmat) * l3 * ncol;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int col = int(e % ncol);
+    const int64_t r = e / ncol;
+    const int u = int(r % l3), c = int(r / l3);
+    const int u1 = u / (l * l), u2 = (u / l) % l, u3 = u % l;
+    const double* src = in + int64_t(c) * l3 * ncol + col;
+    double v = 0.0;
+    for (int a1 = 0; a1 < l; ++a1) {
+      const double c1 = cheb[a1 * l + u1];
+      for (int a2 = 0; a2 < l; ++a2) {
+        const double c12 = c1 * cheb[a2 * l + u2];
+        const double* s3 = src + int64_t((a1 * l + a2) * l) * ncol;
+        for (int a3 = 0; a3 < l; ++a3) v += c12 * cheb[a3 * l + u3] * s3[int64_t(a3) * ncol];
+      }
+    }
+    out[e] = v;
+  }
+}
+
+// Row index and sign of a coefficient row u of offset kid in its canonical
+// class's coefficient rows: the dimension permutation without the mirroring,
+// which flips the sign of odd degrees.
+__device__ inline int modal_row(const int* in, int l, int u, double& sgn) {
+  const int uu[3] = {u / (l * l), (u / l) % l, u % l};
+  int gu[3];
+  sgn = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    gu[in[1 + d]] = uu[d];
+    if (in[4 + d] < 0 && (uu[d] & 1)) sgn = -sgn;
+  }
+  return (gu[0] * l + gu[1]) * l + gu[2];
+}
+
 // Pack the 316 operators in MFMA fragment order:
 //   kp[((kid*mt + i)*kc + c)*256 + lane*4 + s] = Kh_t[16 i + lane%16][16 c + 4 (lane/16) + s]
-// (zero outside l^3), gathering from the canonical operator through g.
-__global__ void pack_kernel(const double* __restrict__ Kc, const int* __restrict__ info,
-                            int l, int mt, int kc, double* __restrict__ kp64,
-                            float* __restrict__ kp32) {
+// (zero outside l^3), gathering from the canonical operator through g; the
+// FP32 pack from the coefficient rows KcM = T3 Kc through modal_row.
+__global__ void pack_kernel(const double* __restrict__ Kc, const double* __restrict__ KcM,
+                            const int* __restrict__ info, int l, int mt, int kc,
+                            double* __restrict__ kp64, float* __restrict__ kp32) {
   const int l3 = l * l * l;
   const int64_t total = int64_t(kOffsets) * mt * kc * 256;
   for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
@@ -168,7 +225,7 @@ __global__ void pack_kernel(const double* __restrict__ Kc, const int* __restrict
     const int kid = int(r / mt);
     const int row = 16 * i + (lane & 15);
     const int col = 16 * c + 4 * (lane >> 4) + s;
-    double v = 0.0;
+    double v = 0.0, vm = 0.0;
     if (row < l3 && col < l3) {
       const int* in = info + 7 * kid;  // canon, pi[3], sg[3]
       int mm[3] = {row / (l * l), (row / l) % l, row % l};
@@ -181,9 +238,12 @@ __global__ void pack_kernel(const double* __restrict__ Kc, const int* __restrict
       const int gmi = (gm[0] * l + gm[1]) * l + gm[2];
       const int gni = (gn[0] * l + gn[1]) * l + gn[2];
       v = Kc[(int64_t(in[0]) * l3 + gmi) * l3 + gni];
+      double sgn;
+      const int gu = modal_row(in, l, row, sgn);
+      vm = sgn * KcM[(int64_t(in[0]) * l3 + gu) * l3 + gni];
     }
     kp64[e] = v;
-    kp32[e] = float(v);
+    kp32[e] = float(vm);
   }
 }
 
@@ -209,10 +269,13 @@ const OpSet* get_opset(int l, int kernel, hipStream_t s) {
 
   double xi[kMaxOrder], Tm[kMaxOrder];
   cheb_nodes(l, xi);
-  std::vector<double> cheb(l * l), child(2 * l * l);
+  std::vector<double> cheb(l * l), tcheb(l * l), child(2 * l * l);
   for (int m = 0; m < l; ++m) {
     cheb_T(l, xi[m], Tm);
-    for (int n = 0; n < l; ++n) cheb[m * l + n] = (n == 0 ? 1.0 : 2.0 * Tm[n]) / l;
+    for (int n = 0; n < l; ++n) {
+      cheb[m * l + n] = (n == 0 ? 1.0 : 2.0 * Tm[n]) / l;
+      tcheb[m * l + n] = Tm[n];
+    }
   }
   // child-to-parent interpolation S(xb_m; (sigma + xb_m')/2), sigma = -1, +1
   for (int sg = 0; sg < 2; ++sg)
@@ -247,6 +310,7 @@ const OpSet* get_opset(int l, int kernel, hipStream_t s) {
   };
   try {
     op->cheb = static_cast<double*>(up(cheb.data(), sizeof(double) * cheb.size(), true));
+    op->tcheb = static_cast<double*>(up(tcheb.data(), sizeof(double) * tcheb.size(), true));
     op->child = static_cast<double*>(up(child.data(), sizeof(double) * child.size(), true));
     op->slot_kid = static_cast<int*>(up(T.slot_kid.data(), sizeof(int) * T.slot_kid.size(), true));
     op->slot_t = static_cast<signed char*>(up(T.slot_t.data(), T.slot_t.size(), true));
@@ -255,12 +319,17 @@ const OpSet* get_opset(int l, int kernel, hipStream_t s) {
     int* info_d = static_cast<int*>(up(info.data(), sizeof(int) * info.size(), false));
     double* kc_d = static_cast<double*>(dev_alloc(sizeof(double) * 16 * size_t(op->l3) * op->l3));
     tmp.push_back(kc_d);
+    double* kcm_d = static_cast<double*>(dev_alloc(sizeof(double) * 16 * size_t(op->l3) * op->l3));
+    tmp.push_back(kcm_d);
     const size_t npack = size_t(kOffsets) * op->mt * op->kc * 256;
     op->kpack64 = static_cast<double*>(dev_alloc(sizeof(double) * npack));
     op->kpack32 = static_cast<float*>(dev_alloc(sizeof(float) * npack));
     canon_kernel<<<1024, 256, 0, s>>>(xi_d, tc_d, l, 16, kernel, kc_d);
     FMM_HIP_CHECK(hipGetLastError());
-    pack_kernel<<<4096, 256, 0, s>>>(kc_d, info_d, l, op->mt, op->kc, op->kpack64, op->kpack32);
+    modal_rows_kernel<<<4096, 256, 0, s>>>(kc_d, op->cheb, l, op->l3, 16, kcm_d);
+    FMM_HIP_CHECK(hipGetLastError());
+    pack_kernel<<<4096, 256, 0, s>>>(kc_d, kcm_d, info_d, l, op->mt, op->kc, op->kpack64,
+                                     op->kpack32);
     FMM_HIP_CHECK(hipGetLastError());
     FMM_HIP_CHECK(hipStreamSynchronize(s));
   } catch (...) {
@@ -506,6 +575,7 @@ __host__ __device__ inline int rank_slot(int p) {
 }
 
 __global__ void svd_pack_kernel(const double* __restrict__ U, const double* __restrict__ Vt,
+                                const double* __restrict__ VtM,
                                 const double* __restrict__ S, const int* __restrict__ info,
                                 const int* __restrict__ rank, const int* __restrict__ rpad,
                                 const int64_t* __restrict__ off, int l, int mt, int kc,
@@ -519,6 +589,7 @@ __global__ void svd_pack_kernel(const double* __restrict__ U, const double* __re
   const int64_t nblk = int64_t(rp) * kc * 16;  // elements per factor block
   const double* Uc = U + int64_t(c) * l3 * l3;
   const double* Vc = Vt + int64_t(c) * l3 * l3;
+  const double* VcM = VtM + int64_t(c) * l3 * l3;  // the same in coefficient rows
   const double* Sc = S + int64_t(c) * l3;
   auto gmap = [&](int m) {
     int mm[3] = {m / (l * l), (m / l) % l, m % l}, gm[3];
@@ -537,13 +608,19 @@ __global__ void svd_pack_kernel(const double* __restrict__ U, const double* __re
       p1_64[off[kid] + e] = v;
       p1_32[off[kid] + e] = float(v);
     }
-    {  // phase-2 factor: rows m (ld), columns k (rp, in rank_slot order)
+    {  // phase-2 factor: rows m (ld), columns k (rp, in rank_slot order); the
+       // FP32 factor's rows are Chebyshev coefficients
       const int cc = int(q % nr), i = int(q / nr);
       const int m = 16 * i + (lane & 15), k = rank_slot(16 * cc + 4 * (lane >> 4) + s);
-      double v = 0.0;
-      if (m < l3 && k < r) v = Vc[int64_t(gmap(m)) * l3 + k];
+      double v = 0.0, vm = 0.0;
+      if (m < l3 && k < r) {
+        v = Vc[int64_t(gmap(m)) * l3 + k];
+        double sgn;
+        const int gu = modal_row(in, l, m, sgn);
+        vm = sgn * VcM[int64_t(gu) * l3 + k];
+      }
       p2_64[off[kid] + e] = v;
-      p2_32[off[kid] + e] = float(v);
+      p2_32[off[kid] + e] = float(vm);
     }
   }
 }
@@ -667,7 +744,11 @@ const SvdOps* get_svd_ops(int l, double eps, int kernel, hipStream_t s) {
     sv->p2_64 = static_cast<double*>(dev_alloc(sizeof(double) * tot));
     sv->p1_32 = static_cast<float*>(dev_alloc(sizeof(float) * tot));
     sv->p2_32 = static_cast<float*>(dev_alloc(sizeof(float) * tot));
-    svd_pack_kernel<<<dim3(64, kOffsets), 256, 0, s>>>(U, Vt, S, info_d, rank_d, sv->rpad,
+    // Uc[a][k] = Vt[a * l3 + k]: its rows as Chebyshev coefficients, for FP32
+    double* VtM = static_cast<double*>(talloc(sizeof(double) * 16 * nn));
+    modal_rows_kernel<<<4096, 256, 0, s>>>(Vt, op->cheb, l, l3, 16, VtM);
+    FMM_HIP_CHECK(hipGetLastError());
+    svd_pack_kernel<<<dim3(64, kOffsets), 256, 0, s>>>(U, Vt, VtM, S, info_d, rank_d, sv->rpad,
                                                         sv->off, l, op->mt, op->kc, sv->p1_64,
                                                         sv->p1_32, sv->p2_64, sv->p2_32);
     FMM_HIP_CHECK(hipGetLastError());

@@ -1,15 +1,17 @@
 // Serving loop: continuous batching of FMM evaluations on one GPU.
 //
-// A worker thread owns two streams.  On the plan stream it builds the plans
-// of arriving requests (root box, sort, lists: the synchronous part) and
-// admits them while the admitted plans' device bytes stay within the budget.
-// On the execution stream it evaluates batches: all admitted requests that
-// are not yet running form one batch whose operators run as persistent
-// launches over one shared work table (jobs.h), the whole launch sequence
-// captured once per shape as a hipGraph and replayed with new tables.  The
-// table travels inside the graph as a copy from a pinned host buffer; two
-// buffers let the next batch be prepared while one runs.  Planning on the
-// plan stream overlaps the running batch on the device.
+// Two threads.  The planner builds the plans of arriving requests on its
+// own stream (root box, sort, lists: the synchronous part, after the
+// caller's inputs are ready) and admits them while the admitted plans'
+// device bytes stay within the budget.  The launcher evaluates batches: all
+// admitted requests that are not yet running form one batch whose operators
+// run as persistent launches over one shared work table (jobs.h), the whole
+// launch sequence captured once per shape as a hipGraph and replayed with
+// new tables.  The table travels inside the graph as a copy from a pinned
+// host buffer.  Each of the two table buffers has its own execution stream,
+// so a batch formed while another runs is launched at once and runs beside
+// it on the device; batches retire in whatever order they finish.  Planning
+// overlaps the running batches, and never holds up a launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +36,22 @@ constexpr int kMaxSteps = 160;
 constexpr int kBuffers = 2;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// code and message of the exception being handled
+void current_failure(int& code, std::string& msg) {
+  code = FMM_ERR_HIP;
+  msg = "serving loop failure";
+  try {
+    throw;
+  } catch (const FmmError& e) {
+    code = e.code;
+    msg = e.msg;
+  } catch (const std::bad_alloc&) {
+    code = FMM_ERR_OOM;
+    msg = "host allocation failed";
+  } catch (...) {
+  }
+}
 
 // Blocks per persistent launch, by kernel (sized to keep every CU busy; a
 // block loops over the items of the batch with this stride).
@@ -62,6 +80,8 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int64_t batch = -1;
   int64_t bytes = 0;        // admitted footprint (known after the first plan)
+  hipEvent_t inputs = nullptr;  // recorded on the caller's stream at submit
+  std::string err;          // message of a failed request
 };
 
 struct Launch {
@@ -74,6 +94,7 @@ struct Launch {
 struct TableBuf {
   void* pinned = nullptr;
   void* dev = nullptr;
+  hipStream_t stream = nullptr;  // the batches of this buffer run here
   hipEvent_t last = nullptr;  // completion of the batch that last read it
   bool busy = false;
 };
@@ -97,12 +118,14 @@ struct fmm_server_s {
   int device = 0;
   size_t budget = 0;
   int max_active = 0;
-  hipStream_t plan_stream = nullptr, exec_stream = nullptr;
+  hipStream_t plan_stream = nullptr;
   fmm::TableBuf buf[fmm::kBuffers];
   std::map<std::pair<int, std::string>, hipGraphExec_t> graphs;
 
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  // cv_work wakes the planner (a submit, freed memory or slots), cv_launch
+  // the launcher (a request admitted), cv_done the callers of wait
+  std::condition_variable cv_work, cv_launch, cv_done;
   std::deque<fmm::Request*> pending;          // submitted, not yet admitted
   std::vector<fmm::Request*> ready;           // admitted, not yet launched
   std::deque<fmm::Batch> inflight;
@@ -111,50 +134,66 @@ struct fmm_server_s {
   size_t used = 0;
   int active = 0;
   bool stop = false;
+  bool planner_done = false;
   struct fmm_server_stats st{};
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-  std::thread worker;
+  std::thread planner, launcher;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
-  void run();
-  void retire();
+  void plan_loop();
+  void launch_loop();
+  bool retire();
   bool admit();
   bool launch_batch();
-  void finish(fmm::Request* r, int status);
+  void launch_on(int bi, const std::vector<fmm::Request*>& reqs);
+  void finish(fmm::Request* r, int status, const std::string& err = std::string());
 };
 
 using namespace fmm;
 
-void fmm_server_s::finish(Request* r, int status) {
+void fmm_server_s::finish(Request* r, int status, const std::string& err) {
   // called with mu held
   r->status = status;
+  r->err = err;
   r->done = true;
   r->t_done = now();
+  if (r->inputs) {
+    (void)hipEventDestroy(r->inputs);
+    r->inputs = nullptr;
+  }
   if (status == FMM_OK) ++st.completed;
   else ++st.rejected;
   cv_done.notify_all();
 }
 
-void fmm_server_s::retire() {
+// Retire every finished batch, in whatever order the streams finish them.
+bool fmm_server_s::retire() {
+  bool any = false;
   while (true) {
     Batch b;
+    bool found = false;
     {
       std::lock_guard<std::mutex> lk(mu);
-      if (inflight.empty()) return;
-      hipError_t e = hipEventQuery(inflight.front().ev);
-      if (e == hipErrorNotReady) return;
-      b = inflight.front();
-      inflight.pop_front();
-      const int status = e == hipSuccess ? FMM_OK : FMM_ERR_HIP;
-      if (e != hipSuccess) (void)hipGetLastError();
-      for (Request* r : b.reqs) {
-        used -= size_t(r->bytes);
-        --active;
-        finish(r, status);
+      for (auto it = inflight.begin(); it != inflight.end(); ++it) {
+        hipError_t e = hipEventQuery(it->ev);
+        if (e == hipErrorNotReady) continue;
+        b = *it;
+        inflight.erase(it);
+        found = true;
+        const int status = e == hipSuccess ? FMM_OK : FMM_ERR_HIP;
+        if (e != hipSuccess) (void)hipGetLastError();
+        for (Request* r : b.reqs) {
+          used -= size_t(r->bytes);
+          --active;
+          finish(r, status, status == FMM_OK ? "" : hipGetErrorString(e));
+        }
+        break;
       }
     }
+    if (!found) return any;
+    any = true;
     buf[b.buf].busy = false;
     (void)hipEventDestroy(b.ev);
     for (Request* r : b.reqs) {
@@ -178,19 +217,24 @@ bool fmm_server_s::admit() {
       if (r->bytes > 0 && used + size_t(r->bytes) > budget) return any;
       pending.pop_front();
     }
+    // the caller's inputs are ready on the device before the plan reads them
+    FMM_HIP_CHECK(hipStreamWaitEvent(plan_stream, r->inputs, 0));
     fmm_plan_s* p = fmm_plan_stream(r->pos, r->n, r->h, r->order, plan_stream);
-    int rc = p ? fmm_plan_set_precision(p, r->prec) : FMM_ERR_ARG;
+    int rc = p ? fmm_plan_set_precision(p, r->prec) : last_error_code();
+    if (rc == FMM_OK && !p) rc = FMM_ERR_HIP;
+    const std::string err = rc == FMM_OK ? std::string() : std::string(fmm_last_error());
     std::lock_guard<std::mutex> lk(mu);
     if (!p || rc != FMM_OK) {
       if (p) fmm_release(p);
-      finish(r, rc != FMM_OK ? rc : FMM_ERR_ARG);
+      finish(r, rc, err);
       any = true;
       continue;
     }
     r->bytes = int64_t(p->bytes);
     if (size_t(r->bytes) > budget) {
       fmm_release(p);
-      finish(r, FMM_ERR_OOM);
+      finish(r, FMM_ERR_OOM, "the request's plan (" + std::to_string(r->bytes) +
+                                 " bytes) exceeds the server's memory budget");
       any = true;
       continue;
     }
@@ -207,6 +251,7 @@ bool fmm_server_s::admit() {
     st.max_active_seen = std::max<int64_t>(st.max_active_seen, active);
     st.peak_admitted_bytes = std::max<int64_t>(st.peak_admitted_bytes, int64_t(used));
     ready.push_back(r);
+    cv_launch.notify_all();
     any = true;
   }
 }
@@ -227,8 +272,33 @@ bool fmm_server_s::launch_batch() {
     reqs.assign(ready.begin(), ready.begin() + take);
     ready.erase(ready.begin(), ready.begin() + take);
   }
+  try {
+    launch_on(bi, reqs);
+  } catch (...) {
+    // the batch never ran: its requests end with the failure
+    int code;
+    std::string msg;
+    current_failure(code, msg);
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : reqs) {
+      used -= size_t(r->bytes);
+      --active;
+      fmm_release(r->plan);
+      r->plan = nullptr;
+      finish(r, code, msg);
+    }
+    cv_work.notify_all();
+  }
+  return true;
+}
+
+void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
   TableBuf& B = buf[bi];
+  hipStream_t exec_stream = B.stream;
   if (B.last) FMM_HIP_CHECK(hipEventSynchronize(B.last));  // its copy has been consumed
+  // the batch reads the callers' charges and writes their outputs: after
+  // everything each caller's stream had queued at submit
+  for (Request* r : reqs) FMM_HIP_CHECK(hipStreamWaitEvent(exec_stream, r->inputs, 0));
   char* host = static_cast<char*>(B.pinned);
   JobDev* jobs = reinterpret_cast<JobDev*>(host + kJobsOff);
   CallDev* calls = reinterpret_cast<CallDev*>(host + kCallsOff);
@@ -309,8 +379,12 @@ bool fmm_server_s::launch_batch() {
               return int(r->plan->ntiles) * r->plan->job_h.nmb * r->plan->job_h.m2l_parts;
             },
             lvl0);
-  // the compressed M2L of plans that split it: partial sums back into Loc
-  add(kStepLocSum, 0, false, [&](Request* r) { return far(r) && r->plan->job_h.m2l_parts > 1; },
+  // partial sums of plans that split their compressed M2L back into Loc, and
+  // the FP32 M2L's Chebyshev-coefficient rows back to node values
+  add(kStepLocSum, 0, false,
+      [&](Request* r) {
+        return far(r) && (r->plan->job_h.m2l_parts > 1 || r->plan->job_h.modal);
+      },
       [](Request* r) { return int(r->plan->job_h.locx_rows); }, lvl0);
   for (int s = 0; s < steps; ++s)
     add(kStepL2L, maxo, false, [&](Request* r) { return r->h - 4 >= s; },
@@ -362,31 +436,49 @@ bool fmm_server_s::launch_batch() {
     for (Request* r : reqs) r->batch = b.index;
     inflight.push_back(b);
   }
-  return true;
 }
 
-void fmm_server_s::run() {
+// The planner: plans and admits arriving requests.
+void fmm_server_s::plan_loop() {
   (void)hipSetDevice(device);
   while (true) {
     bool progress = false;
     try {
-      retire();
-      progress |= admit();
+      progress = admit();
+    } catch (...) {
+      // a runtime failure ends every request not yet admitted
+      int code;
+      std::string msg;
+      current_failure(code, msg);
+      std::lock_guard<std::mutex> lk(mu);
+      set_error(msg);
+      for (Request* r : pending) finish(r, code, msg);
+      pending.clear();
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    if (stop && pending.empty()) {
+      planner_done = true;
+      cv_launch.notify_all();
+      break;
+    }
+    if (progress) continue;
+    cv_work.wait_for(lk, std::chrono::milliseconds(5));
+  }
+}
+
+// The launcher: retires finished batches and launches admitted requests.
+void fmm_server_s::launch_loop() {
+  (void)hipSetDevice(device);
+  while (true) {
+    bool progress = false;
+    try {
+      progress |= retire();
       progress |= launch_batch();
     } catch (...) {
-      // a runtime failure ends every request that is not running
-      int code = FMM_ERR_HIP;
-      std::string msg = "serving loop failure";
-      try {
-        throw;
-      } catch (const FmmError& e) {
-        code = e.code;
-        msg = e.msg;
-      } catch (const std::bad_alloc&) {
-        code = FMM_ERR_OOM;
-        msg = "host allocation failed";
-      } catch (...) {
-      }
+      // a runtime failure ends every admitted request that is not running
+      int code;
+      std::string msg;
+      current_failure(code, msg);
       std::lock_guard<std::mutex> lk(mu);
       set_error(msg);
       for (Request* r : ready) {
@@ -396,23 +488,22 @@ void fmm_server_s::run() {
           fmm_release(r->plan);
           r->plan = nullptr;
         }
-        finish(r, code);
+        finish(r, code, msg);
       }
       ready.clear();
-      for (Request* r : pending) finish(r, code);
-      pending.clear();
+      cv_work.notify_all();
     }
     std::unique_lock<std::mutex> lk(mu);
-    if (stop && pending.empty() && ready.empty() && inflight.empty()) break;
+    if (stop && planner_done && ready.empty() && inflight.empty()) break;
     if (progress) continue;
     if (!inflight.empty()) {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
     } else {
-      cv_work.wait_for(lk, std::chrono::milliseconds(5));
+      cv_launch.wait_for(lk, std::chrono::milliseconds(5));
     }
   }
-  // release the graphs and the plans of anything left
+  // release the graphs
   for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
   graphs.clear();
 }
@@ -435,8 +526,8 @@ fmm_server_t fmm_server_create(size_t hbm_budget_bytes, int max_active) {
     s->budget = hbm_budget_bytes;
     s->max_active = max_active;
     FMM_HIP_CHECK(hipStreamCreateWithFlags(&s->plan_stream, hipStreamNonBlocking));
-    FMM_HIP_CHECK(hipStreamCreateWithFlags(&s->exec_stream, hipStreamNonBlocking));
     for (int i = 0; i < kBuffers; ++i) {
+      FMM_HIP_CHECK(hipStreamCreateWithFlags(&s->buf[i].stream, hipStreamNonBlocking));
       FMM_HIP_CHECK(hipHostMalloc(&s->buf[i].pinned, kTableBytes, hipHostMallocDefault));
       std::memset(s->buf[i].pinned, 0, kTableBytes);
       FMM_HIP_CHECK(hipMalloc(&s->buf[i].dev, kTableBytes));
@@ -446,19 +537,20 @@ fmm_server_t fmm_server_create(size_t hbm_budget_bytes, int max_active) {
     for (int i = 0; i < kBuffers; ++i) {
       if (s->buf[i].pinned) (void)hipHostFree(s->buf[i].pinned);
       if (s->buf[i].dev) (void)hipFree(s->buf[i].dev);
+      if (s->buf[i].stream) (void)hipStreamDestroy(s->buf[i].stream);
     }
     if (s->plan_stream) (void)hipStreamDestroy(s->plan_stream);
-    if (s->exec_stream) (void)hipStreamDestroy(s->exec_stream);
     delete s;
     return nullptr;
   }
-  s->worker = std::thread([s] { s->run(); });
+  s->planner = std::thread([s] { s->plan_loop(); });
+  s->launcher = std::thread([s] { s->launch_loop(); });
   return s;
 }
 
 int64_t fmm_server_submit(fmm_server_t s, const double* positions, const double* charges,
                           int64_t n, int height, int order, int precision, double* potential,
-                          double* forces) {
+                          double* forces, hipStream_t stream) {
   if (!s) {
     set_error("server is NULL");
     return FMM_ERR_ARG;
@@ -468,11 +560,22 @@ int64_t fmm_server_submit(fmm_server_t s, const double* positions, const double*
     return FMM_ERR_ARG;
   }
   if (n < 1 || n > int64_t(2147483646) || height < 1 || height > kMaxHeight || order < 1 ||
-      order > kMaxOrder || precision < FMM_FP64 || precision > FMM_MIXED_SVD) {
+      order > kMaxOrder || precision < FMM_FP64 || precision > FMM_MIXED_SVD ||
+      precision == FMM_MIXED_BF16) {
     set_error("invalid n, height, order or precision");
     return FMM_ERR_ARG;
   }
+  hipEvent_t inputs = nullptr;
+  hipError_t e = hipEventCreateWithFlags(&inputs, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(inputs, stream);
+  if (e != hipSuccess) {
+    if (inputs) (void)hipEventDestroy(inputs);
+    (void)hipGetLastError();
+    set_error(std::string("recording the caller's stream failed: ") + hipGetErrorString(e));
+    return FMM_ERR_HIP;
+  }
   Request* r = new Request();
+  r->inputs = inputs;
   r->pos = positions;
   r->q = charges;
   r->n = n;
@@ -514,6 +617,26 @@ int fmm_server_poll(fmm_server_t s, int64_t ticket, fmm_request_stats* out) {
   return it->second->done ? 1 : 0;
 }
 
+int fmm_server_request_error(fmm_server_t s, int64_t ticket, char* buf, size_t len) {
+  if (!s || (!buf && len > 0)) {
+    set_error("server or buffer is NULL");
+    return FMM_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->all.find(ticket);
+  if (it == s->all.end()) {
+    set_error("unknown ticket");
+    return FMM_ERR_ARG;
+  }
+  const std::string& m = it->second->err;
+  if (len > 0) {
+    const size_t k = std::min(len - 1, m.size());
+    std::memcpy(buf, m.data(), k);
+    buf[k] = '\0';
+  }
+  return int(m.size());
+}
+
 int fmm_server_wait(fmm_server_t s, int64_t ticket, fmm_request_stats* out) {
   if (!s) return FMM_ERR_ARG;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -543,8 +666,10 @@ void fmm_server_destroy(fmm_server_t s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
     s->cv_work.notify_all();
+    s->cv_launch.notify_all();
   }
-  if (s->worker.joinable()) s->worker.join();
+  if (s->planner.joinable()) s->planner.join();
+  if (s->launcher.joinable()) s->launcher.join();
   for (auto& kv : s->all) {
     if (kv.second->plan) fmm_release(kv.second->plan);
     delete kv.second;
@@ -553,9 +678,9 @@ void fmm_server_destroy(fmm_server_t s) {
     if (s->buf[i].last) (void)hipEventDestroy(s->buf[i].last);
     (void)hipHostFree(s->buf[i].pinned);
     (void)hipFree(s->buf[i].dev);
+    (void)hipStreamDestroy(s->buf[i].stream);
   }
   (void)hipStreamDestroy(s->plan_stream);
-  (void)hipStreamDestroy(s->exec_stream);
   delete s;
 }
 

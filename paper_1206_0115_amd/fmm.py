@@ -16,8 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmm.so")
 
 FMM_OK, FMM_ERR_ARG, FMM_ERR_OOM, FMM_ERR_HIP, FMM_ERR_STATE = 0, -1, -2, -3, -4
-FMM_FP64, FMM_MIXED_FP32, FMM_FP64_SVD, FMM_MIXED_SVD = 0, 1, 2, 3
+FMM_FP64, FMM_MIXED_FP32, FMM_MIXED_BF16, FMM_FP64_SVD, FMM_MIXED_SVD = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED_FP32,
+              "mixed_bf16": FMM_MIXED_BF16,  # reserved; the library rejects it
               "fp64_svd": FMM_FP64_SVD, "mixed_svd": FMM_MIXED_SVD}
 FMM_SCHEDULE_SERIAL, FMM_SCHEDULE_FORKED = 0, 1
 SCHEDULES = {"serial": FMM_SCHEDULE_SERIAL, "forked": FMM_SCHEDULE_FORKED}
@@ -111,9 +112,11 @@ def lib():
     L.fmm_set_m2l_timing_events.argtypes = [vp, vp]
     L.fmm_set_step_timing_events.argtypes = [i32, vp, vp]
     L.fmm_trim_cache.restype = None
+    L.fmm_direct_sampled.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp, vp]
     L.fmm_server_create.argtypes = [sz, i32]
     L.fmm_server_create.restype = vp
-    L.fmm_server_submit.argtypes = [vp, vp, vp, i64, i32, i32, i32, vp, vp]
+    L.fmm_server_submit.argtypes = [vp, vp, vp, i64, i32, i32, i32, vp, vp, vp]
+    L.fmm_server_request_error.argtypes = [vp, i64, ctypes.c_char_p, sz]
     L.fmm_server_submit.restype = i64
     L.fmm_server_poll.argtypes = [vp, i64, ctypes.POINTER(RequestStats)]
     L.fmm_server_wait.argtypes = [vp, i64, ctypes.POINTER(RequestStats)]
@@ -159,7 +162,7 @@ class Plan:
     """An FMM plan over fixed particle positions (``fmm_plan``)."""
 
     def __init__(self, positions, height: int, order: int, precision="fp64", stream=None,
-                 kernel="inv_r"):
+                 kernel="inv_r", m2l_tolerance=None):
         self.n = int(positions.shape[0])
         ptr = _dev_f64(positions, (self.n, 3), "positions")
         if stream is None:
@@ -174,6 +177,8 @@ class Plan:
         self.kernel = FMM_KERNEL_INV_R
         if kernel not in ("inv_r", FMM_KERNEL_INV_R):
             self.set_kernel(kernel)
+        if m2l_tolerance is not None:  # before the mode, so only these operators load
+            self.set_m2l_tolerance(m2l_tolerance)
         self.set_precision(precision)
 
     @property
@@ -317,6 +322,25 @@ def set_m2l_timing_events(ev0, ev1):
                                            ctypes.c_void_p(ev1.cuda_event)))
 
 
+def direct_sampled(positions, charges, targets, kernel="inv_r", stream=None):
+    """Exact potentials and forces at the particles ``targets`` (int64
+    device tensor of indices) over all sources (``fmm_direct_sampled``)."""
+    import torch
+    n = int(positions.shape[0])
+    pos = _dev_f64(positions, (n, 3), "positions")
+    q = _dev_f64(charges, (n,), "charges")
+    if targets.dtype != torch.int64 or not targets.is_cuda or targets.dim() != 1:
+        raise ValueError("targets must be a 1-D int64 device tensor")
+    tg = targets.contiguous()
+    nt = int(tg.shape[0])
+    phi = torch.empty(nt, dtype=torch.float64, device=positions.device)
+    f = torch.empty(nt, 3, dtype=torch.float64, device=positions.device)
+    _check(lib().fmm_direct_sampled(pos, q, n, ctypes.c_void_p(tg.data_ptr()), nt,
+                                    KERNELS[kernel], ctypes.c_void_p(phi.data_ptr()),
+                                    ctypes.c_void_p(f.data_ptr()), _stream_handle(stream)))
+    return phi, f
+
+
 def trim_cache():
     lib().fmm_trim_cache()
 
@@ -341,6 +365,14 @@ class Request:
         lib().fmm_server_wait(self.server._h, self.ticket, ctypes.byref(st))
         return st
 
+    def error(self) -> str:
+        """Message of the request's failure ("" if none)."""
+        buf = ctypes.create_string_buffer(1024)
+        rc = lib().fmm_server_request_error(self.server._h, self.ticket, buf, len(buf))
+        if rc < 0:
+            raise FMMError(rc, last_error())
+        return buf.value.decode()
+
 
 class Server:
     """The serving loop (``fmm_server_*``): continuous batching of evaluations
@@ -353,7 +385,9 @@ class Server:
         self._h = ctypes.c_void_p(h)
 
     def submit(self, positions, charges, height, order, precision="fp64",
-               potential=None, forces=None) -> Request:
+               potential=None, forces=None, stream=None) -> Request:
+        """Queue one evaluation; the server starts on it after the work
+        queued so far on `stream` (default: the current stream)."""
         import torch
         n = int(positions.shape[0])
         pp = _dev_f64(positions, (n, 3), "positions")
@@ -365,7 +399,8 @@ class Server:
         mode = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         t = lib().fmm_server_submit(self._h, pp, qp, n, int(height), int(order), mode,
                                     _dev_f64(potential, (n,), "potential"),
-                                    _dev_f64(forces, (n, 3), "forces"))
+                                    _dev_f64(forces, (n, 3), "forces"),
+                                    _stream_handle(stream))
         if t < 0:
             raise FMMError(int(t), last_error())
         return Request(self, int(t), (positions, charges), potential, forces)

@@ -74,3 +74,29 @@ def test_info_struct_layout_matches_header():
         for part in decl.split(","):
             names.append(re.sub(r"\[.*\]", "", part).strip())
     assert names == [f[0] for f in fmm.FmmInfo._fields_]
+
+
+def test_direct_sampled_rejects_bad_arguments_without_device():
+    lib = fmm.lib()
+    fake = ctypes.c_void_p(0x1000)
+    args = lambda **kw: [kw.get(k, d) for k, d in (
+        ("pos", fake), ("q", fake), ("n", 10), ("t", fake), ("nt", 4),
+        ("kernel", fmm.FMM_KERNEL_INV_R), ("phi", fake), ("f", fake), ("s", None))]
+    assert lib.fmm_direct_sampled(*args(pos=None)) == fmm.FMM_ERR_ARG
+    assert "NULL" in fmm.last_error()
+    assert lib.fmm_direct_sampled(*args(t=None)) == fmm.FMM_ERR_ARG
+    assert lib.fmm_direct_sampled(*args(n=0)) == fmm.FMM_ERR_ARG
+    assert lib.fmm_direct_sampled(*args(nt=0)) == fmm.FMM_ERR_ARG
+    assert lib.fmm_direct_sampled(*args(kernel=3)) == fmm.FMM_ERR_ARG
+    assert "kernel" in fmm.last_error()
+
+
+def test_precision_enum_matches_header():
+    src = open(os.path.join(ROOT, "include", "fmm.h")).read()
+    body = src[src.index("enum fmm_precision {"):]
+    body = re.sub(r"/\*.*?\*/", "", body[:body.index("};")], flags=re.S)
+    vals = dict((k, int(v)) for k, v in re.findall(r"(FMM_\w+)\s*=\s*(\d+)", body))
+    assert vals == {"FMM_FP64": fmm.FMM_FP64, "FMM_MIXED_FP32": fmm.FMM_MIXED_FP32,
+                    "FMM_MIXED_BF16": fmm.FMM_MIXED_BF16, "FMM_FP64_SVD": fmm.FMM_FP64_SVD,
+                    "FMM_MIXED_SVD": fmm.FMM_MIXED_SVD}
+    assert vals["FMM_MIXED_BF16"] == 2  # the boundary's third mode keeps its value

@@ -186,3 +186,36 @@ def test_full_size_sampled_parity(name, samples, mixed_bound):
     e = max(rel(host(phm), host(phi)), rel(host(fm), host(f)))
     say(f"  mixed vs fp64 rel L2 {e:.3e}")
     assert e <= mixed_bound
+
+
+def test_second_stream_while_in_flight_is_refused():
+    """A plan evaluated on one stream refuses an evaluation on another stream
+    (FMM_ERR_STATE) until the first has finished; then it is accepted."""
+    pos, q = inputs.uniform_cube(200_000, 31)
+    plan = fmm.Plan(dev(pos), 5, 7)
+    qd = dev(q)
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    out = plan.evaluate(qd, stream=a)
+    a.synchronize()
+    ref = [host(t) for t in out]
+    x = torch.rand(4096, 4096, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(a):
+        for _ in range(4):  # keep stream a busy (about 10 ms) ahead of the evaluation
+            x = torch.matmul(x, x) * 1e-3
+    plan.evaluate(qd, stream=a)
+    with pytest.raises(fmm.FMMError) as e:
+        plan.evaluate(qd, stream=b)
+    assert e.value.code == fmm.FMM_ERR_STATE
+    a.synchronize()
+    phi, f = plan.evaluate(qd, stream=b)
+    b.synchronize()
+    assert np.array_equal(host(phi), ref[0]) and np.array_equal(host(f), ref[1])
+
+
+def test_bf16_mode_is_refused():
+    pos, _ = inputs.uniform_cube(1000, 32)
+    plan = fmm.Plan(dev(pos), 3, 4, "mixed")
+    with pytest.raises(fmm.FMMError) as e:
+        plan.set_precision("mixed_bf16")
+    assert e.value.code == fmm.FMM_ERR_ARG and "BF16" in str(e.value)
+    assert plan.info().precision == fmm.FMM_MIXED_FP32
