@@ -521,6 +521,34 @@ def side_config(name, stream, steps):
     return out
 
 
+def summarize_counters(paths):
+    """Per-kernel means of every counter in rocprofv3 --pmc CSVs (one or
+    more passes), as a markdown table: dispatches, mean value per dispatch.
+    Kernel names are shortened to their function name and template
+    arguments."""
+    import csv
+    import re
+    acc = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = r.get("Kernel_Name", "")
+            m = re.match(r"(?:void )?(?:fmm::)?([A-Za-z0-9_]+(?:<[^>(]*>)?)", name)
+            k = m.group(1) if m else name[:60]
+            c = r.get("Counter_Name")
+            acc.setdefault((k, c), []).append(float(r["Counter_Value"]))
+    counters = sorted({c for _, c in acc})
+    kernels = sorted({k for k, _ in acc})
+    lines = ["| kernel | " + " | ".join(f"{c} (mean, dispatches)" for c in counters) + " |",
+             "|---|" + "---|" * len(counters)]
+    for k in kernels:
+        cells = []
+        for c in counters:
+            v = acc.get((k, c))
+            cells.append(f"{np.mean(v):.6g} ({len(v)})" if v else "")
+        lines.append(f"| {k} | " + " | ".join(cells) + " |")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -538,6 +566,8 @@ def main():
                     help="the program to run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/m2l_traffic.json from the two counter CSVs")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
+                    help="print per-kernel counter means from rocprofv3 --pmc CSVs")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-precision", default="mixed_svd", choices=MODES)
@@ -550,6 +580,9 @@ def main():
                   f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
     if args.ingest_traffic:
         ingest_traffic(args)
         return

@@ -51,9 +51,12 @@ enum fmm_status {
 enum fmm_precision {
   /* every operator in FP64 (FP64 MFMA for M2L) */
   FMM_FP64 = 0,
-  /* P2P in FP32 with leaf-local coordinates and per-source-leaf FP64 folding;
-   * M2L as FP32 MFMA contractions with FP32 accumulation folded into FP64 per
-   * far offset; P2M, M2M, L2L, L2P and the output sums stay FP64 */
+  /* P2P in FP32 (pair differences rounded once from FP64) with
+   * per-source-leaf FP64 folding; M2L as FP32 MFMA contractions whose
+   * operators produce Chebyshev coefficients of the local expansions,
+   * accumulated in FP32 and folded into FP64 per far offset, then turned
+   * into node values in FP64; P2M, M2M, L2L, L2P and the output sums stay
+   * FP64 */
   FMM_MIXED_FP32 = 1,
   /* Reserved for M2L as BF16 MFMA products with FP32 accumulation.  Not
    * built: BF16 keeps 8 significant bits, so even a two-term (hi + lo)
@@ -69,12 +72,15 @@ enum fmm_precision {
    * 10^-order as in the paper's accuracy setting, at most down to 1e-10),
    * applied as two skinny MFMA products per far offset */
   FMM_FP64_SVD = 3,
-  /* FMM_MIXED_FP32 with the compressed M2L in FP32 MFMA (FP64 folding) */
+  /* FMM_MIXED_FP32 with the compressed M2L in FP32 MFMA: the second factor
+   * of each operator produces Chebyshev coefficients, folded into FP64 every
+   * few far offsets (fmm_plan_set_m2l_fold_interval) */
   FMM_MIXED_SVD = 4
 };
 
 /* Truncation tolerance of the compressed M2L (0 < eps < 1); takes effect for
- * the SVD precision modes.  The truncated operators of an order and tolerance
+ * the SVD precision modes (in a dense mode it is only recorded, and checked
+ * when an SVD mode is selected).  The truncated operators of an order and tolerance
  * are computed once per device (rocSOLVER SVD of the 16 canonical operators)
  * and cached.  Returns FMM_ERR_ARG for a tolerance outside (0, 1), and, in an
  * SVD mode, for one whose kept ranks need more LDS per workgroup than the
@@ -84,12 +90,14 @@ enum fmm_precision {
 int fmm_plan_set_m2l_tolerance(fmm_plan_t plan, double eps);
 
 /* Fold interval of the compressed mixed mode (FMM_MIXED_SVD): the FP32 MFMA
- * partial sums of a target tile are added into its FP64 local expansions
- * after every `offsets` far offsets (1..189; 0 restores the default, 16 up to
- * order 7 and 2 above).  Shorter intervals are more accurate and slower:
- * at order 7 on the uniform cube, 1 / 4 / 8 / 16 give a relative L2 error
- * against FP64 of 2.3e-7 / 2.9e-7 / 3.5e-7 / 4.4e-7.  Results stay
- * deterministic for any interval.  Returns FMM_ERR_ARG outside 0..189. */
+ * partial sums of a target tile (Chebyshev coefficients of its local
+ * expansions) are added into its FP64 local expansions after every
+ * `offsets` far offsets (1..189; 0 restores the default, 16).  Shorter
+ * intervals are more accurate and slower: relative L2 error against FP64 on
+ * the 1M-particle order-7 cube 1.5e-7 / 1.8e-7 / 2.6e-7 for 1 / 16 / 189
+ * (never), on the 469k-particle order-10 cube (tolerance 1e-7) 1.8e-7 /
+ * 2.0e-7 / 3.2e-7.  Results stay deterministic for any interval.  Returns
+ * FMM_ERR_ARG outside 0..189. */
 int fmm_plan_set_m2l_fold_interval(fmm_plan_t plan, int offsets);
 
 /* Work split of the compressed M2L (both SVD modes): each 64-target tile's

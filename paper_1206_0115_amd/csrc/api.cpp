@@ -79,10 +79,12 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   const bool fp32 = p->precision == FMM_MIXED_FP32 || p->precision == FMM_MIXED_SVD;
   J.kernel = p->kernel;
   J.w32_leaf = p->w32_leaf ? 1 : 0;
-  // FP32 accumulation error grows with the fold interval and, through the
-  // interpolation, with the order: 16 offsets keep order 7 at 4.4e-7 against
-  // FP64 (8: 3.5e-7, 5% slower); above order 7 the default folds every 2
-  J.fold_every = p->m2l_fold > 0 ? p->m2l_fold : (p->order <= 7 ? 16 : 2);
+  // FP32 partial sums of Chebyshev coefficients are folded into FP64 every
+  // 16 far offsets: against FP64, 1.8e-7 at order 7 (1M cube) and 2.0e-7 at
+  // order 10 (the 469k twin of the 30M cube, eps 1e-7); folding every
+  // offset gains little accuracy (1.5e-7, 1.8e-7) for a far slower M2L, and
+  // never folding loses some (2.6e-7, 3.2e-7) for about 5%
+  J.fold_every = p->m2l_fold > 0 ? p->m2l_fold : 16;
   J.svd = p->svd ? 1 : 0;
   if (p->svd) J.xs = m2l_svd_xs(p->svd->rmax_pad, fp32);
   J.nmb = p->svd ? m2l_svd_nmb(op->mt, fp32, J.xs) : m2l_nmb(op->mt);
@@ -490,6 +492,10 @@ int fmm_plan_set_m2l_tolerance(fmm_plan_t p, double eps) {
     std::lock_guard<std::mutex> lk(p->mu);
     const double prev = p->m2l_eps;
     p->m2l_eps = eps;
+    // the dense modes only record it: the operators (and, for a plan not
+    // evaluated yet, the multipole buffers) are set up when a compressed
+    // mode is selected
+    if (p->precision != FMM_FP64_SVD && p->precision != FMM_MIXED_SVD) return FMM_OK;
     try {
       apply_mode(p, p->precision);
     } catch (...) {

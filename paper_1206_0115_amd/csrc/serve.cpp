@@ -34,6 +34,10 @@ namespace {
 
 constexpr int kMaxSteps = 160;
 constexpr int kBuffers = 2;
+// Batching window: admitted requests wait for the planner to finish the
+// requests that arrived with them, but no longer than this, so that a burst
+// shares launches and a lone request starts almost at once.
+constexpr double kBatchWindowS = 0.002;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -133,6 +137,7 @@ struct fmm_server_s {
   int64_t next_id = 0;
   size_t used = 0;
   int active = 0;
+  int planning = 0;  // requests taken from `pending` whose plans are being built
   bool stop = false;
   bool planner_done = false;
   struct fmm_server_stats st{};
@@ -216,6 +221,7 @@ bool fmm_server_s::admit() {
       // footprint known from an earlier attempt and still too large for now
       if (r->bytes > 0 && used + size_t(r->bytes) > budget) return any;
       pending.pop_front();
+      ++planning;
     }
     // the caller's inputs are ready on the device before the plan reads them
     FMM_HIP_CHECK(hipStreamWaitEvent(plan_stream, r->inputs, 0));
@@ -224,6 +230,8 @@ bool fmm_server_s::admit() {
     if (rc == FMM_OK && !p) rc = FMM_ERR_HIP;
     const std::string err = rc == FMM_OK ? std::string() : std::string(fmm_last_error());
     std::lock_guard<std::mutex> lk(mu);
+    --planning;
+    cv_launch.notify_all();
     if (!p || rc != FMM_OK) {
       if (p) fmm_release(p);
       finish(r, rc, err);
@@ -268,6 +276,11 @@ bool fmm_server_s::launch_batch() {
   {
     std::lock_guard<std::mutex> lk(mu);
     if (ready.empty() || bi < 0) return false;
+    // wait for the rest of a burst, within the batching window
+    const bool burst_planned = pending.empty() && planning == 0;
+    if (!burst_planned && ready.size() < size_t(kMaxJobs) &&
+        now() - ready.front()->t_admit < kBatchWindowS)
+      return false;
     const size_t take = std::min<size_t>(ready.size(), kMaxJobs);
     reqs.assign(ready.begin(), ready.begin() + take);
     ready.erase(ready.begin(), ready.begin() + take);
@@ -500,7 +513,9 @@ void fmm_server_s::launch_loop() {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
     } else {
-      cv_launch.wait_for(lk, std::chrono::milliseconds(5));
+      // admitted requests inside their batching window: look again soon
+      cv_launch.wait_for(lk, ready.empty() ? std::chrono::microseconds(5000)
+                                           : std::chrono::microseconds(200));
     }
   }
   // release the graphs

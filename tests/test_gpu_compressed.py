@@ -60,11 +60,11 @@ def test_compressed_parity_with_oracle(kind, n, h, l, seed, eps):
     assert max(rel(host(phi), host(p64)), rel(host(f), host(f64))) < 10 * eps
 
 
-# (name, bound of the compressed mixed mode against FP64): the 1e-6 gate
-# at order 7; at order 10 with ~2 particles per leaf it measures 9.6e-7,
-# stated with a margin
-@pytest.mark.parametrize("name,mixed_bound", [("cube1m_h6_p7", 1e-6),
-                                              ("cube469k_h7_p10", 2e-6)])
+# (name, bound of the compressed mixed mode against FP64): half the 1e-6
+# gate, at order 7 and at order 10, the order of the 30M-particle workload
+# (measured 1.8e-7 and 2.0e-7)
+@pytest.mark.parametrize("name,mixed_bound", [("cube1m_h6_p7", 5e-7),
+                                              ("cube469k_h7_p10", 5e-7)])
 def test_mixed_compressed_full_size_gate(name, mixed_bound):
     kind, n, h, l, seed = inputs.CONFIGS[name]
     print(f"compressed gates {name}", flush=True)

@@ -153,15 +153,15 @@ def test_deterministic_and_reusable():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-# (name, sampled targets, bound on the dense mixed mode against FP64).  At
-# order 10 with ~2 particles per leaf the far field dominates and the
-# order-10 interpolation amplifies the FP32 rounding of M2L: the dense
-# mixed mode measures 4.0e-6 there (the compressed mixed mode 9.6e-7, see
-# the compressed tests), so that bound is stated, not the 1e-6 gate.
+# (name, sampled targets, bound on the dense mixed mode against FP64): the
+# 1e-6 gate everywhere.  The FP32 M2L accumulates Chebyshev coefficients,
+# so its rounding no longer reaches the forces through the gradient of the
+# order-10 interpolant (4.0e-6 when it accumulated node values; 3.4e-7 now
+# on the order-10 twin).
 FULL = [
     ("cube1m_h6_p7", 96, 1e-6),
     ("sphere10m_h8_p7", 96, 1e-6),
-    ("cube469k_h7_p10", 48, 1e-5),  # density twin of the 30M, order-10 cube
+    ("cube469k_h7_p10", 48, 1e-6),  # density twin of the 30M, order-10 cube
 ]
 
 
