@@ -302,6 +302,23 @@ int fmm_direct_sampled(const double* positions, const double* charges, int64_t n
                        const int64_t* targets, int64_t nt, int kernel, double* potential,
                        double* forces, hipStream_t stream);
 
+/*
+ * fmm_direct_sampled for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments and the same bits as fmm_direct_sampled, but
+ * no allocation: the partial sums live in a static device array of 8 MiB
+ * per device, held from the first call on the device until the process
+ * ends.  Stream-ordered: returns once the work is queued.  Every call on a
+ * device shares that array, so calls that overlap on one device (on two
+ * streams, or from two threads without ordering) race and give wrong
+ * results.  Returns FMM_ERR_ARG, before any device work, when nt exceeds
+ * 262,144 (the partial sums would not fit), and as fmm_direct_sampled for
+ * other invalid arguments.
+ */
+int fmm_direct_sampled_noalloc(const double* positions, const double* charges, int64_t n,
+                               const int64_t* targets, int64_t nt, int kernel,
+                               double* potential, double* forces, hipStream_t stream);
+
 /* Return cached device memory of released plans to the HIP runtime. */
 void fmm_trim_cache(void);
 

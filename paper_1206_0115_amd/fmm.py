@@ -113,6 +113,7 @@ def lib():
     L.fmm_set_step_timing_events.argtypes = [i32, vp, vp]
     L.fmm_trim_cache.restype = None
     L.fmm_direct_sampled.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp, vp]
+    L.fmm_direct_sampled_noalloc.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp, vp]
     L.fmm_server_create.argtypes = [sz, i32]
     L.fmm_server_create.restype = vp
     L.fmm_server_submit.argtypes = [vp, vp, vp, i64, i32, i32, i32, vp, vp, vp]
