@@ -403,6 +403,28 @@ class Bench:
             p.release()
         return dt
 
+    def schedule_times(self, prec, steps):
+        """Evaluate-only ms per step for each schedule, eager and replayed
+        from the plan's captured graph."""
+        torch, s = self.torch, self.stream
+        out = {}
+        with torch.cuda.stream(s):
+            p = self.plan(prec)
+            for sched in ("serial", "forked", "pipelined"):
+                for graph in (False, True):
+                    p.set_schedule(sched)
+                    p.set_graph(graph)
+                    p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+                    s.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+                    s.synchronize()
+                    out[sched + ("+graph" if graph else "")] = round(
+                        (time.perf_counter() - t0) * 1e3 / steps, 4)
+            p.release()
+        return out
+
     def step_times(self, prec, reps):
         """Average duration of each bulk operator's kernel, every operator on
         one stream (serial schedule, so no kernel shares the GPU)."""
@@ -514,7 +536,8 @@ def side_config(name, stream, steps):
            "eval_only_ms": round(b.eval_only(prec, max(5, steps)), 4),
            "rel_l2_vs_fp64": modes[prec]["rel_l2_vs_fp64"],
            "rel_l2_vs_exact": b.exact_error(N_EXACT), "modes": modes,
-           "kernels": b.kernels(prec, 5)}
+           "kernels": b.kernels(prec, 5),
+           "eval_only_ms_by_schedule": b.schedule_times(prec, max(5, steps))}
     if name == "cube1m_h6_p7":
         out["second_kernel"] = b.second_kernel(prec, max(5, steps // 2))
     b.release()
@@ -549,6 +572,51 @@ def summarize_counters(paths):
     print("\n".join(lines))
 
 
+def summarize_trace(path, top):
+    """Per-(kernel, grid) dispatch count and mean / total duration from a
+    rocprofv3 --kernel-trace CSV, as a markdown table of the `top` kernels by
+    total time.  The grid separates launches of one kernel over different
+    workloads (a headline workload and its twin)."""
+    import csv
+    import re
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name", "")
+        m = re.match(r"(?:void )?(?:fmm::)?([A-Za-z0-9_]+(?:<[^>(]*>)?)", name)
+        k = m.group(1) if m else name[:60]
+        grid = "x".join(r.get(f"Grid_Size_{d}", "?") for d in "XYZ")
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+        acc.setdefault((k, grid), []).append(dt)
+    rows = sorted(acc.items(), key=lambda kv: -sum(kv[1]))[:top]
+    print("| kernel | grid (threads) | dispatches | mean ms | total ms |")
+    print("|---|---|---|---|---|")
+    for (k, grid), v in rows:
+        print(f"| {k} | {grid} | {len(v)} | {np.mean(v):.4f} | {np.sum(v):.2f} |")
+    # time during which kernels of two or more hardware queues ran at once
+    spans = {}
+    for r in csv.DictReader(open(path)):
+        qid = r.get("Queue_Id") or r.get("Stream_Id") or "?"
+        spans.setdefault(qid, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    ev = []
+    for qid, v in spans.items():
+        for a, b in v:
+            ev += [(a, 1, qid), (b, -1, qid)]
+    ev.sort(key=lambda e: (e[0], e[1]))
+    active, busy, both, last = {}, 0, 0, None
+    for t, d, qid in ev:
+        if last is not None:
+            n = sum(1 for c in active.values() if c > 0)
+            if n >= 1:
+                busy += t - last
+            if n >= 2:
+                both += t - last
+        active[qid] = active.get(qid, 0) + d
+        last = t
+    print(f"\nqueues with kernels: {len(spans)}; time with a kernel running "
+          f"{busy * 1e-6:.2f} ms, with kernels of two or more queues at once "
+          f"{both * 1e-6:.2f} ms")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -568,6 +636,8 @@ def main():
                     help="write profiles/m2l_traffic.json from the two counter CSVs")
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
                     help="print per-kernel counter means from rocprofv3 --pmc CSVs")
+    ap.add_argument("--summarize-trace", metavar="CSV",
+                    help="print per-kernel durations from a rocprofv3 --kernel-trace CSV")
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-precision", default="mixed_svd", choices=MODES)
@@ -580,6 +650,9 @@ def main():
                   f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, 25)
+        return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
         return

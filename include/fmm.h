@@ -187,11 +187,33 @@ int fmm_plan_set_precision(fmm_plan_t plan, int mode);
  *                        it runs beside L2L and L2P, which leave the GPU
  *                        partly idle) and joined back before the final sum;
  *                        the far chain stays on the caller's stream
- * Both schedules launch the same kernels on the same data: results are
- * bit-identical.  Stream capture of the caller's stream captures the fork
- * and the join.  Returns FMM_ERR_ARG for a null plan or unknown schedule. */
-enum fmm_schedule { FMM_SCHEDULE_SERIAL = 0, FMM_SCHEDULE_FORKED = 1 };
+ *   FMM_SCHEDULE_PIPELINED  as FMM_SCHEDULE_FORKED, and the M2L of the leaf
+ *                        level (which needs only the leaf multipoles) also
+ *                        runs on the plan's stream, right after P2M and
+ *                        beside the M2M chain (Sec. 3.3: the M2L of one level
+ *                        overlaps the M2M of the next coarser one); the
+ *                        coarser levels' M2L follows the M2M chain on the
+ *                        caller's stream, which waits for the leaf level's
+ *                        before the local expansions are summed.  The M2L
+ *                        timing hook brackets the leaf level's launch.
+ * All schedules launch the same kernels on the same data: results are
+ * bit-identical.  Stream capture of the caller's stream captures the forks
+ * and joins.  Returns FMM_ERR_ARG for a null plan or unknown schedule. */
+enum fmm_schedule { FMM_SCHEDULE_SERIAL = 0, FMM_SCHEDULE_FORKED = 1, FMM_SCHEDULE_PIPELINED = 2 };
 int fmm_plan_set_schedule(fmm_plan_t plan, int schedule);
+
+/* Whole-evaluation graph (the task flow of Sec. 3.2 as one hipGraph): with
+ * on = 1, fmm_evaluate captures its launch sequence (both streams of the
+ * forked and pipelined schedules) the first time on a private stream, as a
+ * hipGraph, and afterwards replays it on the caller's stream with the
+ * call's charge and output pointers set into its first and last kernels; it
+ * is captured again after the precision mode, tolerance, kernel, fold
+ * interval, split or schedule changed.  The same kernels run on the same
+ * data: results are bit-identical to the eager launches.  Evaluations with
+ * a step timing hook set, and fmm_evaluate_parts, run eagerly.  on = 0 (the
+ * default) frees the graph.  Returns FMM_ERR_ARG for a null plan or another
+ * value of on. */
+int fmm_plan_set_graph(fmm_plan_t plan, int on);
 
 /* Kernel of later evaluations.  The black-box scheme (Sec. 2.1) needs only
  * point evaluations of the kernel P(x, y): the interpolation operators (P2M,

@@ -169,6 +169,13 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
     p->tab_h[kTabCast] = one_job(int((p->w32_leaf ? p->lev[h - 1].off : p->ncell_total + 1) -
                                      p->lev[2].off));
     p->tab_h[kTabM2L] = one_job(int(p->ntiles) * J.nmb * parts);
+    // tiles are stored finest level first: the leaf level's, then the rest
+    int64_t leaf_tiles = 0;
+    while (leaf_tiles < p->ntiles && p->tiles_host[leaf_tiles].level == h - 1) ++leaf_tiles;
+    const int leaf_items = int(leaf_tiles) * J.nmb * parts;
+    p->tab_h[kTabM2LLeaf] = one_job(leaf_items);
+    p->tab_h[kTabM2LCoarse] = one_job(int(p->ntiles) * J.nmb * parts - leaf_items);
+    p->tab_h[kTabM2LCoarse].first[0] = leaf_items;
     p->tab_h[kTabLocSum] = one_job(parts > 1 || J.modal ? int(lrows) : 0);
     for (int st = 0; st + 4 <= h; ++st) {
       p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
@@ -176,6 +183,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
       p->tab_h[kTabL2L + st] = one_job(int(p->lev[2 + st].ncell), 3 + st);
     }
   }
+  ++p->job_version;  // a captured evaluation graph no longer matches
   if (!p->job_d) p->job_d = static_cast<JobDev*>(p->alloc(sizeof(JobDev)));
   if (!p->tab_d) p->tab_d = static_cast<StepTab*>(p->alloc(sizeof(StepTab) * kTabCount));
   FMM_HIP_CHECK(hipMemcpyAsync(p->job_d, &p->job_h, sizeof(JobDev), hipMemcpyHostToDevice, s));
@@ -207,6 +215,8 @@ void fmm_plan_s::free_block(void* ptr) {
 fmm_plan_s::~fmm_plan_s() {
   // the evaluation's last work first: done, then the side stream
   fmm::event_put(device, done);
+  fmm::release_graph(this);
+  if (capture) fmm::side_stream_put(device, capture);
   fmm::side_stream_put(device, side);
   fmm::event_put(device, ev_fork);
   fmm::event_put(device, ev_join);
@@ -413,9 +423,22 @@ int fmm_plan_set_precision(fmm_plan_t p, int mode) {
   });
 }
 
+int fmm_plan_set_graph(fmm_plan_t p, int on) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (on != 0 && on != 1) return fail(FMM_ERR_ARG, "graph switch must be 0 or 1");
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
+    p->graph_on = on != 0;
+    if (!p->graph_on) fmm::release_graph(p);
+    return FMM_OK;
+  });
+}
+
 int fmm_plan_set_schedule(fmm_plan_t p, int schedule) {
   if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
-  if (schedule != FMM_SCHEDULE_SERIAL && schedule != FMM_SCHEDULE_FORKED)
+  if (schedule != FMM_SCHEDULE_SERIAL && schedule != FMM_SCHEDULE_FORKED &&
+      schedule != FMM_SCHEDULE_PIPELINED)
     return fail(FMM_ERR_ARG, "unknown schedule " + std::to_string(schedule));
   return guarded([&]() -> int {
     std::lock_guard<std::mutex> lk(p->mu);
@@ -536,7 +559,10 @@ static int eval_common(fmm_plan_t p, const double* q, double* phi, double* f, do
     if (dev != p->device) return fail(FMM_ERR_ARG, "plan belongs to another device");
     // the first evaluation of a plan whose mode was never set allocates here
     if (ensure_w(p, s)) fmm::upload_job(p, s);
-    fmm::evaluate(p, q, phi, f, pn, fn, pf, ff, s);
+    if (p->graph_on && phi && !fmm::timing_hooks_set())
+      fmm::evaluate_graph(p, q, phi, f, s);
+    else
+      fmm::evaluate(p, q, phi, f, pn, fn, pf, ff, s);
     FMM_HIP_CHECK(hipEventRecord(p->done, s));
     p->in_flight = true;
     p->last_stream = s;

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "device_util.h"
 #include "fmm_internal.h"
@@ -870,7 +871,9 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   const unsigned chunks = unsigned((p->n + kChunk - 1) / kChunk);
   gather1_kernel<<<chunks, kChunk, 0, s>>>(J, q);
   FMM_HIP_CHECK(hipGetLastError());
-  const bool forked = p->schedule == FMM_SCHEDULE_FORKED;
+  // the pipelined schedule forks the near field like the forked one
+  const bool pipelined = p->schedule == FMM_SCHEDULE_PIPELINED;
+  const bool forked = p->schedule == FMM_SCHEDULE_FORKED || pipelined;
   auto fork_near = [&]() {
     FMM_HIP_CHECK(hipEventRecord(p->ev_fork, s));
     FMM_HIP_CHECK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
@@ -881,10 +884,33 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
     FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
   };
   if (forked && h < 3) fork_near();
+  const StepKind m2l_kind = p->svd ? kStepM2LSvd : kStepM2L;
+  auto m2l_launch = [&](int tab, hipStream_t st) {
+    if (p->tab_h[tab].start[1] > 0)
+      launch_step(m2l_kind, L, mixed, J, p->tab_d + tab, nullptr, p->tab_h[tab].start[1], st,
+                  p->job_h.xs);
+  };
+  auto loc_sum = [&]() {
+    if (p->tab_h[kTabLocSum].start[1] > 0)
+      launch_step(kStepLocSum, L, false, J, p->tab_d + kTabLocSum, nullptr,
+                  p->tab_h[kTabLocSum].start[1], s);
+  };
   if (h >= 3) {
     {
       Timed t(FMM_TIME_P2M, s);
       launch_step(kStepP2M, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+    }
+    // pipelined: the leaf level's M2L needs only the leaf multipoles, so it
+    // starts on the side stream beside the M2M chain (Sec. 3.3: M2L of one
+    // level overlaps M2M of the next coarser one)
+    if (pipelined && p->ntiles > 0) {
+      FMM_HIP_CHECK(hipEventRecord(p->ev_fork, s));
+      FMM_HIP_CHECK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+      {
+        Timed t(FMM_TIME_M2L, p->side);
+        m2l_launch(kTabM2LLeaf, p->side);
+      }
+      FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
     }
     for (int st = 0; st + 4 <= h; ++st)
       launch_step(kStepM2M, L, false, J, p->tab_d + kTabM2M + st, nullptr,
@@ -893,14 +919,17 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
       launch_step(kStepCast, L, true, J, p->tab_d + kTabCast, nullptr,
                   p->tab_h[kTabCast].start[1], s);
     if (forked && !FMM_FORK_AFTER_M2L) fork_near();
-    {
+    if (pipelined) {
+      if (p->ntiles > 0) {
+        m2l_launch(kTabM2LCoarse, s);
+        FMM_HIP_CHECK(hipStreamWaitEvent(s, p->ev_join, 0));
+        loc_sum();
+      }
+    } else {
       Timed t(FMM_TIME_M2L, s);
       if (p->ntiles > 0) {
-        launch_step(p->svd ? kStepM2LSvd : kStepM2L, L, mixed, J, p->tab_d + kTabM2L, nullptr,
-                    p->tab_h[kTabM2L].start[1], s, p->job_h.xs);
-        if (p->tab_h[kTabLocSum].start[1] > 0)
-          launch_step(kStepLocSum, L, false, J, p->tab_d + kTabLocSum, nullptr,
-                      p->tab_h[kTabLocSum].start[1], s);
+        m2l_launch(kTabM2L, s);
+        loc_sum();
       }
     }
     if (forked && FMM_FORK_AFTER_M2L == 1) fork_near();
@@ -924,6 +953,84 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   CallDev c{q, phi, f, phi_n, f_n, phi_f, f_f};
   combine1_kernel<<<chunks, kChunk, 0, s>>>(J, c);
   FMM_HIP_CHECK(hipGetLastError());
+}
+
+
+bool timing_hooks_set() {
+  for (int i = 0; i < 4; ++i)
+    if (g_time_ev[i][0] || g_time_ev[i][1]) return true;
+  return false;
+}
+
+void release_graph(fmm_plan_s* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  p->graph_gather = p->graph_combine = nullptr;
+  p->graph_version = -1;
+  p->graph_schedule = -1;
+}
+
+// Capture: evaluate() on the plan's private stream (the near-field fork and
+// join become branches of the graph), then find the two kernel nodes that
+// take the call's pointers.  No memset or allocation happens in evaluate().
+static void capture_graph(fmm_plan_s* p, const double* q, double* phi, double* f) {
+  release_graph(p);
+  if (!p->capture) p->capture = side_stream_get(p->device);
+  // the side stream joins the capture: nothing of an eager evaluation may be
+  // pending on it
+  FMM_HIP_CHECK(hipStreamSynchronize(p->side));
+  FMM_HIP_CHECK(hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal));
+  try {
+    evaluate(p, q, phi, f, nullptr, nullptr, nullptr, nullptr, p->capture);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(p->capture, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  FMM_HIP_CHECK(hipStreamEndCapture(p->capture, &p->graph));
+  size_t nn = 0;
+  FMM_HIP_CHECK(hipGraphGetNodes(p->graph, nullptr, &nn));
+  std::vector<hipGraphNode_t> nodes(nn);
+  FMM_HIP_CHECK(hipGraphGetNodes(p->graph, nodes.data(), &nn));
+  for (hipGraphNode_t nd : nodes) {
+    hipGraphNodeType t;
+    FMM_HIP_CHECK(hipGraphNodeGetType(nd, &t));
+    if (t != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp;
+    FMM_HIP_CHECK(hipGraphKernelNodeGetParams(nd, &kp));
+    if (kp.func == reinterpret_cast<void*>(&gather1_kernel)) p->graph_gather = nd;
+    if (kp.func == reinterpret_cast<void*>(&combine1_kernel)) p->graph_combine = nd;
+  }
+  if (!p->graph_gather || !p->graph_combine) {
+    release_graph(p);
+    throw FmmError{FMM_ERR_HIP, "internal: captured evaluation lacks its gather or combine"};
+  }
+  FMM_HIP_CHECK(hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0));
+  p->graph_version = p->job_version;
+  p->graph_schedule = p->schedule;
+}
+
+void evaluate_graph(fmm_plan_s* p, const double* q, double* phi, double* f, hipStream_t s) {
+  if (!p->graph_exec || p->graph_version != p->job_version || p->graph_schedule != p->schedule)
+    capture_graph(p, q, phi, f);
+  // the call's pointers into the two nodes that take them
+  const JobDev* J = p->job_d;
+  hipKernelNodeParams kp;
+  FMM_HIP_CHECK(hipGraphKernelNodeGetParams(p->graph_gather, &kp));
+  void* ga[] = {&J, &q};
+  kp.kernelParams = ga;
+  kp.extra = nullptr;
+  FMM_HIP_CHECK(hipGraphExecKernelNodeSetParams(p->graph_exec, p->graph_gather, &kp));
+  CallDev c{q, phi, f, nullptr, nullptr, nullptr, nullptr};
+  FMM_HIP_CHECK(hipGraphKernelNodeGetParams(p->graph_combine, &kp));
+  void* ca[] = {&J, &c};
+  kp.kernelParams = ca;
+  kp.extra = nullptr;
+  FMM_HIP_CHECK(hipGraphExecKernelNodeSetParams(p->graph_exec, p->graph_combine, &kp));
+  FMM_HIP_CHECK(hipGraphLaunch(p->graph_exec, s));
 }
 
 }  // namespace fmm

@@ -146,7 +146,9 @@ enum {
   kTabM2M = 3,   // + step s: parents at level h-2-s
   kTabL2L = 3 + kMaxHeight,  // + step s: children at level 3+s
   kTabLocSum = 3 + 2 * kMaxHeight,  // M2L parts: one item per row of levels >= 2
-  kTabCount = 4 + 2 * kMaxHeight
+  kTabM2LLeaf = 4 + 2 * kMaxHeight,    // kTabM2L's items of the leaf-level tiles
+  kTabM2LCoarse = 5 + 2 * kMaxHeight,  // kTabM2L's items of the coarser levels
+  kTabCount = 6 + 2 * kMaxHeight
 };
 
 int m2l_nmb(int mt);      // M-blocks per M2L tile for mt 16-row tiles (dense)
@@ -230,6 +232,17 @@ struct fmm_plan_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool in_flight = false;
   hipStream_t last_stream = nullptr;  // stream of the last evaluation
+  // whole-evaluation graph (fmm_plan_set_graph): the captured launch
+  // sequence, its gather and combine nodes (which take each call's
+  // pointers), and what it was captured for
+  bool graph_on = false;
+  int64_t job_version = 0;         // bumped by every upload_job
+  int64_t graph_version = -1;      // job_version and schedule of the capture
+  int graph_schedule = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraphNode_t graph_gather = nullptr, graph_combine = nullptr;
+  hipStream_t capture = nullptr;   // the private stream graphs are captured on
   std::vector<std::pair<void*, size_t>> blocks;  // every device block this plan owns
   size_t bytes = 0;
   std::mutex mu;
@@ -250,6 +263,13 @@ void plan_stats(fmm_plan_s* p);
 void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f,
               double* phi_n, double* f_n, double* phi_f, double* f_f,
               hipStream_t stream);
+// The same launches replayed from the plan's captured graph (captured on
+// first use, and again after the job or the schedule changed).
+void evaluate_graph(fmm_plan_s* p, const double* q, double* phi, double* f,
+                    hipStream_t stream);
+// whether any step timing hook is set on the calling thread
+bool timing_hooks_set();
+void release_graph(fmm_plan_s* p);
 // fill the plan's JobDev and step tables and copy them to the device (api.cpp)
 void upload_job(fmm_plan_s* p, hipStream_t stream);
 // Step timing hooks (enum fmm_timed_step): the step's launch in later

@@ -103,6 +103,7 @@ struct StepTab {
   int job[kMaxJobs];    // index into the job array
   int level[kMaxJobs];  // per-job level argument (M2M: parent level; L2L: child level)
   int start[kMaxJobs + 1];
+  int first[kMaxJobs];  // M2L: the job's first item (a launch may take a range of its tiles)
 };
 
 __device__ inline int step_total(const StepTab& t) { return t.start[t.njobs]; }

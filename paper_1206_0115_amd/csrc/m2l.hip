@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256, FMM_M2L_WAVES_PER_SIMD) void m2l_kernel(
     }
     const int k = step_find(*tab, b);
     const JobDev& J = jobs[tab->job[k]];
-    const int local = b - tab->start[k];
+    const int local = b - tab->start[k] + tab->first[k];
     const int tile = local / J.nmb, mb = local % J.nmb;
     const int MT = J.mt, KC = J.kc, ld = J.ld;
     const int mt0 = (mb * 4 + wave) * MTW;
@@ -871,7 +871,7 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
     }
     const int k = step_find(*tab, b);
     const JobDev& J = jobs[tab->job[k]];
-    const int local = b - tab->start[k];
+    const int local = b - tab->start[k] + tab->first[k];
     const int tile = local / J.nmb, rem = local % J.nmb;
     const int mb = rem / NG, col0 = NC * (rem % NG);
     const M2LTile tl = J.tiles[tile];
@@ -1216,7 +1216,7 @@ __device__ inline bool svd_item(const JobDev* __restrict__ jobs, const StepTab* 
   }
   const int k = step_find(*tab, b);
   const JobDev& J = jobs[tab->job[k]];
-  const int local = b - tab->start[k];
+  const int local = b - tab->start[k] + tab->first[k];
   I.J = &J;
   const int per_tile = J.nmb * J.m2l_parts;
   I.tile = local / per_tile;

@@ -20,8 +20,9 @@ FMM_FP64, FMM_MIXED_FP32, FMM_MIXED_BF16, FMM_FP64_SVD, FMM_MIXED_SVD = 0, 1, 2,
 PRECISIONS = {"fp64": FMM_FP64, "mixed": FMM_MIXED_FP32, "mixed_fp32": FMM_MIXED_FP32,
               "mixed_bf16": FMM_MIXED_BF16,  # reserved; the library rejects it
               "fp64_svd": FMM_FP64_SVD, "mixed_svd": FMM_MIXED_SVD}
-FMM_SCHEDULE_SERIAL, FMM_SCHEDULE_FORKED = 0, 1
-SCHEDULES = {"serial": FMM_SCHEDULE_SERIAL, "forked": FMM_SCHEDULE_FORKED}
+FMM_SCHEDULE_SERIAL, FMM_SCHEDULE_FORKED, FMM_SCHEDULE_PIPELINED = 0, 1, 2
+SCHEDULES = {"serial": FMM_SCHEDULE_SERIAL, "forked": FMM_SCHEDULE_FORKED,
+             "pipelined": FMM_SCHEDULE_PIPELINED}
 FMM_KERNEL_INV_R, FMM_KERNEL_INV_R2 = 1, 2
 KERNELS = {"inv_r": FMM_KERNEL_INV_R, "inv_r2": FMM_KERNEL_INV_R2}
 
@@ -101,6 +102,7 @@ def lib():
     L.fmm_last_error.restype = ctypes.c_char_p
     L.fmm_plan_set_precision.argtypes = [vp, i32]
     L.fmm_plan_set_schedule.argtypes = [vp, i32]
+    L.fmm_plan_set_graph.argtypes = [vp, i32]
     L.fmm_plan_set_kernel.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
     L.fmm_plan_set_m2l_fold_interval.argtypes = [vp, i32]
@@ -197,6 +199,10 @@ class Plan:
         chain; the default)."""
         code = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         _check(lib().fmm_plan_set_schedule(self._h, code))
+
+    def set_graph(self, on: bool):
+        """Replay evaluations from a captured hipGraph (``fmm_plan_set_graph``)."""
+        _check(lib().fmm_plan_set_graph(self._h, 1 if on else 0))
 
     def set_kernel(self, kernel):
         """"inv_r" (1/r, the default) or "inv_r2" (1/r^2)."""
