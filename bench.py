@@ -545,10 +545,10 @@ def side_config(name, stream, steps):
 
 
 def summarize_counters(paths):
-    """Per-kernel means of every counter in rocprofv3 --pmc CSVs (one or
-    more passes), as a markdown table: dispatches, mean value per dispatch.
-    Kernel names are shortened to their function name and template
-    arguments."""
+    """Every counter of every kernel in rocprofv3 --pmc CSVs (one or more
+    passes), as a markdown table: the value of each dispatch in dispatch
+    order (or the mean over more than 8).  Kernel names are shortened to
+    their function name and template arguments."""
     import csv
     import re
     acc = {}
@@ -561,13 +561,19 @@ def summarize_counters(paths):
             acc.setdefault((k, c), []).append(float(r["Counter_Value"]))
     counters = sorted({c for _, c in acc})
     kernels = sorted({k for k, _ in acc})
-    lines = ["| kernel | " + " | ".join(f"{c} (mean, dispatches)" for c in counters) + " |",
+    lines = ["| kernel | " + " | ".join(counters) + " |",
              "|---|" + "---|" * len(counters)]
     for k in kernels:
         cells = []
         for c in counters:
             v = acc.get((k, c))
-            cells.append(f"{np.mean(v):.6g} ({len(v)})" if v else "")
+            # up to 8 dispatches: each value in dispatch order; else the mean
+            if not v:
+                cells.append("")
+            elif len(v) <= 8:
+                cells.append(" / ".join(f"{x:.4g}" for x in v))
+            else:
+                cells.append(f"mean {np.mean(v):.4g} of {len(v)}")
         lines.append(f"| {k} | " + " | ".join(cells) + " |")
     print("\n".join(lines))
 

@@ -92,11 +92,12 @@ int fmm_plan_set_m2l_tolerance(fmm_plan_t plan, double eps);
 /* Fold interval of the compressed mixed mode (FMM_MIXED_SVD): the FP32 MFMA
  * partial sums of a target tile (Chebyshev coefficients of its local
  * expansions) are added into its FP64 local expansions after every
- * `offsets` far offsets (1..189; 0 restores the default, 16).  Shorter
- * intervals are more accurate and slower: relative L2 error against FP64 on
- * the 1M-particle order-7 cube 1.5e-7 / 1.8e-7 / 2.6e-7 for 1 / 16 / 189
- * (never), on the 469k-particle order-10 cube (tolerance 1e-7) 1.8e-7 /
- * 2.0e-7 / 3.2e-7.  Results stay deterministic for any interval.  Returns
+ * `offsets` far offsets (1..189; 0 restores the default, 189: once, after
+ * the tile's last offset).  Shorter intervals are more accurate and slower:
+ * relative L2 error against FP64 on the 1M-particle order-7 cube 1.5e-7 /
+ * 1.8e-7 / 2.6e-7 for 1 / 16 / 189, on the 469k-particle order-10 cube
+ * (tolerance 1e-7) 1.8e-7 / 2.0e-7 / 3.2e-7; 189 runs the M2L 6-9% faster
+ * than 16.  Results stay deterministic for any interval.  Returns
  * FMM_ERR_ARG outside 0..189. */
 int fmm_plan_set_m2l_fold_interval(fmm_plan_t plan, int offsets);
 

@@ -410,17 +410,20 @@ __device__ inline int p2p_groups(int nt) {
 // One near-field pair for the kernel |x - y|^-KP: adds the potential term
 // q r^-KP to ph and the force factor KP q r^-(KP+2) times d to (fx, fy, fz);
 // the target charge multiplies the force at the end.  Zero distance adds 0.
-template <int KP>
+// CHECK: whether the pair may be at zero distance.  Particles at one position
+// share a leaf, so only the target leaf's own particles need the test; the
+// padding of a source tile (q = 0, 1e30 away) contributes exact zeros.
+template <int KP, bool CHECK = true>
 __device__ __forceinline__ void pair_f64(double dx, double dy, double dz, double q, double& ph,
                                          double& fx, double& fy, double& fz) {
   const double r2 = dx * dx + dy * dy + dz * dz;
   double t, s;
   if (KP == 2) {
-    const double ir2 = r2 > 0.0 ? 1.0 / r2 : 0.0;
+    const double ir2 = !CHECK || r2 > 0.0 ? 1.0 / r2 : 0.0;
     t = q * ir2;
     s = 2.0 * t * ir2;
   } else {
-    const double ir = r2 > 0.0 ? rsqrt(r2) : 0.0;
+    const double ir = !CHECK || r2 > 0.0 ? rsqrt(r2) : 0.0;
     t = q * ir;
     s = t * ir * ir;
   }
@@ -431,17 +434,17 @@ __device__ __forceinline__ void pair_f64(double dx, double dy, double dz, double
 }
 
 // The same in FP32 (v_rsq_f32 for 1/r, v_rcp_f32 for 1/r^2).
-template <int KP>
+template <int KP, bool CHECK = true>
 __device__ __forceinline__ void pair_f32(float dx, float dy, float dz, float q, float& ph,
                                          float& fx, float& fy, float& fz) {
   const float r2 = dx * dx + dy * dy + dz * dz;
   float t, s;
   if (KP == 2) {
-    const float ir2 = r2 > 0.f ? __builtin_amdgcn_rcpf(r2) : 0.f;
+    const float ir2 = !CHECK || r2 > 0.f ? __builtin_amdgcn_rcpf(r2) : 0.f;
     t = q * ir2;
     s = 2.f * t * ir2;
   } else {
-    const float ir = r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
+    const float ir = !CHECK || r2 > 0.f ? __builtin_amdgcn_rsqf(r2) : 0.f;
     t = q * ir;
     s = t * ir * ir;
   }
@@ -484,6 +487,43 @@ __device__ __forceinline__ float q_of_slot(double d) {
   return __uint_as_float(static_cast<unsigned>(__double_as_longlong(d)));
 }
 
+// A source tile's passes for one lane group: sources k = split + S i,
+// i < npass (a wavefront-uniform count, so the loop needs no lane masks),
+// two per iteration, in increasing i.  Slots past the tile's sources hold
+// the padding source, which adds zeros.
+constexpr int kSelfSlot = 13;   // the near-list slot of the target leaf itself
+constexpr int kSrcSlots = 128;  // 64 staged sources, then padding for the last passes
+constexpr double kFarAway = 1e30;
+
+template <int KP, bool CHECK>
+__device__ __forceinline__ void p2p_passes_f32(const src4* src, int split, int S, int npass,
+                                               double xi, double yi, double zi, float& p32,
+                                               float& x32, float& y32, float& z32) {
+  int i = 0;
+  for (; i + 1 < npass; i += 2) {
+    const src4 u = src[split + S * i], v = src[split + S * (i + 1)];
+    pair_f32<KP, CHECK>(float(xi - u.x), float(yi - u.y), float(zi - u.z), q_of_slot(u.w), p32,
+                        x32, y32, z32);
+    pair_f32<KP, CHECK>(float(xi - v.x), float(yi - v.y), float(zi - v.z), q_of_slot(v.w), p32,
+                        x32, y32, z32);
+  }
+  if (i < npass) {
+    const src4 u = src[split + S * i];
+    pair_f32<KP, CHECK>(float(xi - u.x), float(yi - u.y), float(zi - u.z), q_of_slot(u.w), p32,
+                        x32, y32, z32);
+  }
+}
+
+template <int KP, bool CHECK>
+__device__ __forceinline__ void p2p_passes_f64(const src4* src, int split, int S, int npass,
+                                               double xi, double yi, double zi, double& ph,
+                                               double& fx, double& fy, double& fz) {
+  for (int i = 0; i < npass; ++i) {
+    const src4 u = src[split + S * i];
+    pair_f64<KP, CHECK>(xi - u.x, yi - u.y, zi - u.z, u.w, ph, fx, fy, fz);
+  }
+}
+
 template <int KP, bool F32>
 __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
   const int lane = threadIdx.x;
@@ -514,7 +554,7 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
     int sl = -1, jb = 0, j1 = 0;
     bool have = near_next(nj0, nj1, sl, jb, j1);
     int cnt = have ? min(64, j1 - jb) : 0;
-    double rx = 0.0, ry = 0.0, rz = 0.0;
+    double rx = kFarAway, ry = kFarAway, rz = kFarAway;
     QT rq = 0;
     if (lane < cnt) {
       rx = gld(px + jb + lane);
@@ -529,26 +569,20 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
       __syncthreads();
       have = near_next(nj0, nj1, sl, jb, j1);
       cnt = have ? min(64, j1 - jb) : 0;
+      rx = ry = rz = kFarAway;
+      rq = 0;
       if (lane < cnt) {
         rx = gld(px + jb + lane);
         ry = gld(py + jb + lane);
         rz = gld(pz + jb + lane);
         rq = gld(qsrc + int64_t(jb + lane) * qstride + qoff);
       }
+      const int npass = (ccnt + S - 1) / S;
       if (F32) {
-        int kk = split;
-        for (; kk + S < ccnt; kk += 2 * S) {  // two sources per pass, same order
-          const src4 u = src[kk], v = src[kk + S];
-          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), q_of_slot(u.w), p32, x32,
-                       y32, z32);
-          pair_f32<KP>(float(xi - v.x), float(yi - v.y), float(zi - v.z), q_of_slot(v.w), p32, x32,
-                       y32, z32);
-        }
-        if (kk < ccnt) {
-          const src4 u = src[kk];
-          pair_f32<KP>(float(xi - u.x), float(yi - u.y), float(zi - u.z), q_of_slot(u.w), p32, x32,
-                       y32, z32);
-        }
+        if (csl == kSelfSlot)
+          p2p_passes_f32<KP, true>(src, split, S, npass, xi, yi, zi, p32, x32, y32, z32);
+        else
+          p2p_passes_f32<KP, false>(src, split, S, npass, xi, yi, zi, p32, x32, y32, z32);
         if (!have || sl != csl) {  // the source leaf ends here
           ph += double(p32);
           fx += double(x32);
@@ -556,11 +590,10 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
           fz += double(z32);
           p32 = x32 = y32 = z32 = 0.f;
         }
+      } else if (csl == kSelfSlot) {
+        p2p_passes_f64<KP, true>(src, split, S, npass, xi, yi, zi, ph, fx, fy, fz);
       } else {
-        for (int kk = split; kk < ccnt; kk += S) {
-          const src4 u = src[kk];
-          pair_f64<KP>(xi - u.x, yi - u.y, zi - u.z, u.w, ph, fx, fy, fz);
-        }
+        p2p_passes_f64<KP, false>(src, split, S, npass, xi, yi, zi, ph, fx, fy, fz);
       }
     }
     for (int o = P; o < 64; o <<= 1) {
@@ -583,7 +616,10 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
 
 __global__ __launch_bounds__(64) void p2p_f64_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
-  __shared__ src4 src[64];
+  __shared__ src4 src[kSrcSlots];
+  // slots past the 64 staged sources: the padding source, set once (the
+  // first staging's barrier orders it before any read)
+  src[64 + threadIdx.x] = src4{kFarAway, kFarAway, kFarAway, 0.0};
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
@@ -598,7 +634,10 @@ __global__ __launch_bounds__(64) void p2p_f64_kernel(const JobDev* __restrict__ 
 
 __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
-  __shared__ src4 src[64];
+  __shared__ src4 src[kSrcSlots];
+  // slots past the 64 staged sources: the padding source, set once (the
+  // first staging's barrier orders it before any read)
+  src[64 + threadIdx.x] = src4{kFarAway, kFarAway, kFarAway, 0.0};
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];

@@ -1103,14 +1103,15 @@ __global__ __launch_bounds__(64 * NWV, sizeof(T) == 4 ? FMM_M2L_SVD_WAVES_F32
 #ifndef FMM_M2L_SVD_WS_WAVES
 #define FMM_M2L_SVD_WS_WAVES 4
 #endif
-// ...and for workgroups of 8 consumers whose items hold 64 FP32 or 32 FP64
-// columns (NT = 4, FP32; NT = 2, FP64), which need more registers per lane;
-// svd_ws_waves takes NT in FP32 column units
+// ...and for workgroups of 8 consumers (12 wavefronts): one of them fills a
+// CU at 3 wavefronts per SIMD, and a second would need 6 per SIMD (85
+// VGPRs), so they take the 168 VGPRs of 3 per SIMD at no loss of occupancy
+// (the 32-column shapes of orders 8 to 10 spilled at 128).
 #ifndef FMM_M2L_SVD_WS_WAVES_BIG
 #define FMM_M2L_SVD_WS_WAVES_BIG 3
 #endif
 constexpr int svd_ws_waves(int ncw, int nt) {
-  return ncw * nt >= 32 ? FMM_M2L_SVD_WS_WAVES_BIG : FMM_M2L_SVD_WS_WAVES;
+  return ncw >= 8 ? FMM_M2L_SVD_WS_WAVES_BIG : FMM_M2L_SVD_WS_WAVES;
 }
 // Producer stage depth D, FP32 and FP64: where every K-group has at most D
 // chunks of the l^3 contraction (ceil(KC / 4) <= D), the kernel built for D

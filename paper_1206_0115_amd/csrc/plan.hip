@@ -15,14 +15,6 @@
 #include "device_util.h"
 #include "fmm_internal.h"
 
-// M2L tile order within a level: 0 interleaves the child parities (the k-th
-// tiles of the eight parities side by side, sharing source multipoles), 1
-// takes each parity's tiles in turn (the workgroups on one XCD then use the
-// same 189 operators, in the same offset order).
-#ifndef FMM_TILE_PARITY_MAJOR
-#define FMM_TILE_PARITY_MAJOR 0
-#endif
-
 namespace fmm {
 
 // ------------------------------------------------------------------ scan
@@ -804,17 +796,11 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
         if (par > 0) start[par] = start[par - 1] + hpc[8 * l + par - 1];
         kmax = std::max(kmax, hpc[8 * l + par]);
       }
-#if FMM_TILE_PARITY_MAJOR
-      for (int par = 0; par < 8; ++par)
-        for (int k = 0; k < hpc[8 * l + par]; k += kTileN)
-          tiles.push_back({l, par, int(start[par] + k), std::min(kTileN, hpc[8 * l + par] - k)});
-#else
       for (int k = 0; k < kmax; k += kTileN)
         for (int par = 0; par < 8; ++par) {
           const int c = hpc[8 * l + par];
           if (k < c) tiles.push_back({l, par, int(start[par] + k), std::min(kTileN, c - k)});
         }
-#endif
     }
     p->ntiles = int64_t(tiles.size());
     p->tiles_host = tiles;

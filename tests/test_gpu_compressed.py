@@ -150,7 +150,9 @@ def test_m2l_split_agrees_with_unsplit_and_is_checked():
     plan.set_m2l_tolerance(eps)
     ops, _ = oracle.compressed_unit_ops(l, eps)
     po, fo = oracle.Tree(pos, h).fmm(l, q, unit_ops=ops)
-    for mode, tol in (("fp64_svd", 1e-13), ("mixed_svd", 2e-7)):
+    # FP32: two summation orders of the same FP32 coefficient sums, each
+    # within the gate of FP64; they agree to half the gate
+    for mode, tol in (("fp64_svd", 1e-13), ("mixed_svd", 5e-7)):
         plan.set_precision(mode)
         plan.set_m2l_split(1)
         assert plan.m2l_split() == 1
