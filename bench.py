@@ -429,7 +429,7 @@ class Bench:
         """Average duration of each bulk operator's kernel, every operator on
         one stream (serial schedule, so no kernel shares the GPU)."""
         torch, fmm, s = self.torch, self.fmm, self.stream
-        names = ("m2l", "p2p", "p2m", "l2p")
+        names = ("m2l", "p2p", "p2m", "l2p", "m2m", "l2l", "loc_sum")
         with torch.cuda.stream(s):
             p = self.plan(prec)
             p.set_schedule("serial")
@@ -444,8 +444,13 @@ class Bench:
             for name in names:
                 fmm.set_step_timing_events(name, None, None)
             p.release()
-        return {name: float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
-                for k, name in enumerate(names)}
+        out = {}
+        for k, name in enumerate(names):
+            try:  # a step the mode does not run leaves its events unrecorded
+                out[name] = float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
+            except RuntimeError:
+                pass
+        return out
 
     def exact_error(self, count):
         """Error of the last evaluation's output against exact sums (GPU
@@ -469,22 +474,37 @@ class Bench:
         p2p_flops = 20.0 * float(inf.near_pairs)
         p2m_bytes = 32.0 * n + 8.0 * l3 * float(inf.n_leaf)
         l2p_bytes = 64.0 * n + 8.0 * l3 * float(inf.n_leaf)
+        h = self.h
+        # three 1-D passes of l^4 FMAs per cell: M2M and L2L per child cell
+        # below level 2, the coefficient rows per cell of levels >= 2
+        trans = 6.0 * self.l ** 4
+        children = float(sum(inf.ncell[lv] for lv in range(3, h)))
+        rows = float(sum(inf.ncell[lv] for lv in range(2, h)))
 
         def rate(work, ms, pk, unit, bound, what):
+            if ms is None:
+                return None
             a = work / (ms / 1e3) / (1e12 if unit == "TFLOP/s" else 1e9)
             return {"bound": bound, "avg_ms": round(ms, 4), "achieved": round(a, 2),
                     "peak": pk, "unit": unit, "frac": round(a / pk, 4),
                     "work_per_launch": work, "work": what}
 
-        return {
-            "m2l": rate(flops, st["m2l"], peak, "TFLOP/s", "mfma", "algorithmic flops"),
-            "p2p": rate(p2p_flops, st["p2p"], peak, "TFLOP/s", "valu",
+        out = {
+            "m2l": rate(flops, st.get("m2l"), peak, "TFLOP/s", "mfma", "algorithmic flops"),
+            "p2p": rate(p2p_flops, st.get("p2p"), peak, "TFLOP/s", "valu",
                         "20 flops per directed near pair"),
-            "p2m": rate(p2m_bytes, st["p2m"], HBM_GBPS, "GB/s", "hbm",
+            "p2m": rate(p2m_bytes, st.get("p2m"), HBM_GBPS, "GB/s", "hbm",
                         "32 B per particle read + l^3 x 8 B per leaf written"),
-            "l2p": rate(l2p_bytes, st["l2p"], HBM_GBPS, "GB/s", "hbm",
+            "l2p": rate(l2p_bytes, st.get("l2p"), HBM_GBPS, "GB/s", "hbm",
                         "64 B per particle read and written + l^3 x 8 B per leaf read"),
+            "m2m": rate(trans * children, st.get("m2m"), PEAK_TFLOPS["fp64"], "TFLOP/s", "alu",
+                        "6 l^4 FP64 flops per child cell, all levels"),
+            "l2l": rate(trans * children, st.get("l2l"), PEAK_TFLOPS["fp64"], "TFLOP/s", "alu",
+                        "6 l^4 FP64 flops per child cell, all levels"),
+            "loc_sum": rate(trans * rows, st.get("loc_sum"), PEAK_TFLOPS["fp64"], "TFLOP/s", "alu",
+                            "6 l^4 FP64 flops per cell of levels >= 2"),
         }
+        return {k: v for k, v in out.items() if v is not None}
 
     def second_kernel(self, prec, steps):
         """The 1/r^2 kernel on the same workload and mode: plan + evaluate +

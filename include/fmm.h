@@ -296,11 +296,23 @@ int fmm_evaluate_parts(fmm_plan_t plan, const double* charges,
  */
 int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1);
 
-/* The same for any of the four bulk operators: ev0 is recorded just before
- * the step's kernel and ev1 just after it, on the stream the kernel runs on
- * (for P2P in the forked schedule, the plan's side stream).  Pass NULLs to
- * stop.  Returns FMM_ERR_ARG for an unknown step or a single NULL event. */
-enum fmm_timed_step { FMM_TIME_M2L = 0, FMM_TIME_P2P = 1, FMM_TIME_P2M = 2, FMM_TIME_L2P = 3 };
+/* The same for any of the bulk operators: ev0 is recorded just before the
+ * step's kernel and ev1 just after it, on the stream the kernel runs on (for
+ * P2P in the forked schedule, the plan's side stream; for M2L in the
+ * pipelined one, the leaf level's launch on the side stream).  M2M and L2L
+ * bracket all their level launches; FMM_TIME_LOC_SUM the pass that adds the
+ * split M2L's partial sums and turns the FP32 M2L's Chebyshev coefficients
+ * into node values (absent where neither applies).  Pass NULLs to stop.
+ * Returns FMM_ERR_ARG for an unknown step or a single NULL event. */
+enum fmm_timed_step {
+  FMM_TIME_M2L = 0,
+  FMM_TIME_P2P = 1,
+  FMM_TIME_P2M = 2,
+  FMM_TIME_L2P = 3,
+  FMM_TIME_M2M = 4,
+  FMM_TIME_L2L = 5,
+  FMM_TIME_LOC_SUM = 6
+};
 int fmm_set_step_timing_events(int step, hipEvent_t ev0, hipEvent_t ev1);
 
 /*

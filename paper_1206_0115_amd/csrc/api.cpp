@@ -101,6 +101,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.ntiles = int(p->ntiles);
   J.has_far = h >= 3;
   J.modal = fp32 && h >= 3 ? 1 : 0;
+  J.l2p_sparse = p->nleaf > 0 && p->n <= int64_t(kL2PSparseMax) * int64_t(p->nleaf) ? 1 : 0;
   // compressed M2L split (targets are the cells of levels 2 .. h-1)
   int parts = 1;
   const int64_t lrows = h >= 3 ? int64_t(p->ncell_total) - int64_t(p->lev[2].off) : 0;
@@ -714,7 +715,7 @@ int fmm_plan_export(fmm_plan_t p, int what, int level, void* dst, size_t bytes) 
 }
 
 int fmm_set_step_timing_events(int step, hipEvent_t ev0, hipEvent_t ev1) {
-  if (step < FMM_TIME_M2L || step > FMM_TIME_L2P)
+  if (step < FMM_TIME_M2L || step > FMM_TIME_LOC_SUM)
     return fail(FMM_ERR_ARG, "unknown timed step " + std::to_string(step));
   if ((ev0 == nullptr) != (ev1 == nullptr)) return fail(FMM_ERR_ARG, "pass both events or none");
   fmm::g_time_ev[step][0] = ev0;

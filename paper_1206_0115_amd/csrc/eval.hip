@@ -88,6 +88,9 @@ __global__ FMM_P2M_BOUNDS void p2m_kernel(const JobDev* __restrict__ jobs,
         if (L > 1) T[1] = u;
         for (int n = 2; n < L; ++n) T[n] = 2.0 * u * T[n - 1] - T[n - 2];
         const double f = d == 0 ? gld(J.qs + i) : 1.0;
+        // one row of C at a time (unrolled, the compiler holds all l^2 of
+        // them: 256 VGPRs at order 10, one wavefront per SIMD)
+#pragma unroll 1
         for (int m = 0; m < L; ++m) {
           double v = 0.0;
           for (int n = 0; n < L; ++n) v += C[m * L + n] * T[n];
@@ -120,178 +123,163 @@ __global__ FMM_P2M_BOUNDS void p2m_kernel(const JobDev* __restrict__ jobs,
 
 // ------------------------------------------------------------- M2M / L2L
 // Three 1-D contractions with the child-to-parent matrices
-// Sc[s][m][m'] = S(xb_m; (s + xb_m')/2), s in {-1,+1} by the child octant bit.
-// Threads per workgroup (one parent cell per workgroup).  The LDS staging
-// holds three workgroups per CU at order 7, so the wider workgroup keeps
-// more wavefronts in flight: 1M cube, order 7, evaluation 5.23 -> 5.12 ms
-// at 512 (1024: the same).  Each value's arithmetic and summation order do
-// not depend on it.
-#ifndef FMM_TRANS_THREADS
-#define FMM_TRANS_THREADS 512
-#endif
-constexpr int kTransThreads = FMM_TRANS_THREADS;
-constexpr int kTransMaxR = (kMaxOrder * kMaxOrder * kMaxOrder + kTransThreads - 1) / kTransThreads;
+// Sc[s][m][m'] = S(xb_m; (s + xb_m')/2), s in {-1,+1} by the child octant bit
+// (Eq. 5 applied per dimension).  One wavefront per child: the child's l^3
+// values sit in LDS, each lane keeps whole lines of l values in registers,
+// and the matrix rows are read as wavefront-wide broadcasts, so that a
+// contraction reads every value once rather than once per output (the form
+// with one LDS operand per FMA was bound by LDS bandwidth at orders 7 to 10).
+// Every output is summed over q in increasing order from zero, and the
+// children of a cell in key order, as in the paper's one-child-at-a-time
+// form.
+constexpr int kTransThreads = 512;  // one wavefront per child of a cell
 
-// Children are staged in LDS, up to 8 x l^3 values per buffer: all children
-// of a cell at once when they fit (l <= 8), else one at a time.  Every
-// contraction below is written out in the same order as the one-child-at-a-
-// time form, and children are summed in key order, so the grouping changes
-// no bit of the result.
-constexpr int kStage = 4096;
-
-__host__ __device__ inline int child_group(int L3) { return 8 * L3 <= kStage ? 8 : 1; }
-
-// Dynamic LDS of the two kernels (doubles): M2M two staging buffers of G
-// children; L2L the parent's expansion plus the two buffers.
-size_t m2m_lds_bytes(int L) {
-  const int L3 = L * L * L;
-  return sizeof(double) * size_t(2) * child_group(L3) * L3;
-}
-size_t l2l_lds_bytes(int L) {
-  const int L3 = L * L * L;
-  return sizeof(double) * (size_t(1) + 2 * child_group(L3)) * L3;
-}
-// A launch may cover plans of several orders up to `max_order` (0: any).
-template <typename F>
-static size_t lds_up_to(int max_order, F bytes) {
-  const int top = max_order > 0 ? std::min(max_order, kMaxOrder) : kMaxOrder;
-  size_t b = 0;
-  for (int L = 1; L <= top; ++L) b = std::max(b, bytes(L));
-  return b;
+// Orders the LDS accesses of every lane of this wavefront before the call
+// ahead of those after it.  The hardware performs a wavefront's LDS accesses
+// in order; the fences keep the compiler from reusing a value loaded before
+// them or moving an access across them, which it may otherwise do whenever
+// it can show that no access of the lane itself conflicts (the rotated
+// contraction below reads what other lanes wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Item = parent cell at level tab->level[k].
-__global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __restrict__ jobs,
-                                                            const StepTab* __restrict__ tab) {
-  __shared__ double Sc[2 * kMaxOrder * kMaxOrder];
-  __shared__ int oct[8];
-  extern __shared__ double dyn_lds[];
-  const int t = threadIdx.x;
-  FOR_ITEMS(tab) {
-    const int k = step_find(*tab, it_);
-    const JobDev& J = jobs[tab->job[k]];
-    const int lv = tab->level[k];
-    const int p = it_ - tab->start[k];
-    const int L = J.order, L2 = L * L, L3 = L2 * L, ld = J.ld;
-    double* const A = dyn_lds;
-    double* const B = dyn_lds + child_group(L3) * L3;
-    for (int e = t; e < 2 * L2; e += kTransThreads) Sc[e] = J.child[e];
-    double acc[kTransMaxR];
-    for (int r = 0; r < kTransMaxR; ++r) acc[r] = 0.0;
-    const int c0 = J.child_start[lv][p], c1 = J.child_start[lv][p + 1];
-    const uint64_t* ckeys = J.keys[lv + 1];
-    const bool leaf_children = J.w32_leaf && lv + 1 == J.height - 1;
-    const int G = child_group(L3);
-    for (int g0 = c0; g0 < c1; g0 += G) {
-      const int nc = min(G, c1 - g0);
-      __syncthreads();
-      if (t < nc) oct[t] = int(ckeys[g0 + t] & 7u);
-      for (int e = t; e < nc * L3; e += kTransThreads) {
-        const int cc = e / L3, r = e - cc * L3;
-        const int64_t crow = (J.lev_off[lv + 1] + g0 + cc) * int64_t(ld);
-        // leaf children of the mixed modes are stored in FP32; the
-        // contraction is FP64
-        A[e] = leaf_children ? double(J.W32[crow + r]) : J.W[crow + r];
-      }
-      __syncthreads();
-      for (int e = t; e < nc * L3; e += kTransThreads) {  // along z
-        const int cc = e / L3, r = e - cc * L3;
-        const double* Sz = Sc + (((oct[cc] >> 2) & 1) ? L2 : 0);
-        const int ab = r / L, m3 = r % L;
-        const double* a = A + cc * L3 + ab * L;
-        double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sz[m3 * L + q] * a[q];
-        B[e] = v;
-      }
-      __syncthreads();
-      for (int e = t; e < nc * L3; e += kTransThreads) {  // along y
-        const int cc = e / L3, r = e - cc * L3;
-        const double* Sy = Sc + (((oct[cc] >> 1) & 1) ? L2 : 0);
-        const int a1 = r / L2, m2 = (r / L) % L, m3 = r % L;
-        const double* bb = B + cc * L3;
-        double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sy[m2 * L + q] * bb[(a1 * L + q) * L + m3];
-        A[e] = v;
-      }
-      __syncthreads();
-      for (int e = t; e < nc * L3; e += kTransThreads) {  // along x, per child
-        const int cc = e / L3, r = e - cc * L3;
-        const double* Sx = Sc + ((oct[cc] & 1) ? L2 : 0);
-        const int m1 = r / L2, rest = r % L2;
-        const double* aa = A + cc * L3;
-        double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sx[m1 * L + q] * aa[q * L2 + rest];
-        B[e] = v;
-      }
-      __syncthreads();
-      for (int r = 0, e = t; e < L3; ++r, e += kTransThreads)  // children summed in key order
-        for (int cc = 0; cc < nc; ++cc) acc[r] += B[cc * L3 + e];
+// out[m][a][b] = sum_q M[m][q] in[a][b][q] for one L^3 cube: a contraction
+// along the last index whose result has its indices rotated, so that the
+// next one again runs along the last index (three restore the order).  M is
+// row-major in LDS.  One wavefront: lane takes lines a L + b = lane + 64 r;
+// every lane reads all its lines before any lane writes (so `out` may be
+// `in`), and each output goes with its index m L^2 + a L + b to `emit`.
+template <int L, typename Emit>
+__device__ __forceinline__ void rot_contract(const double* in, const double* M, int lane,
+                                             Emit emit) {
+  constexpr int L2 = L * L, R = (L2 + 63) / 64;
+  double v[R][L];
+  wave_lds_sync();  // the previous contraction's writes, from every lane
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int line = lane + 64 * r;
+#pragma unroll
+    for (int q = 0; q < L; ++q) v[r][q] = line < L2 ? in[line * L + q] : 0.0;
+  }
+  wave_lds_sync();  // every line read before the first write
+#pragma unroll
+  for (int m = 0; m < L; ++m) {
+    double row[L];
+#pragma unroll
+    for (int q = 0; q < L; ++q) row[q] = M[m * L + q];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int line = lane + 64 * r;
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < L; ++q) acc += row[q] * v[r][q];
+      if (line < L2) emit(m * L2 + line, acc);
     }
-    double* out = J.W + (J.lev_off[lv] + p) * ld;
-    for (int r = 0, e = t; e < L3; ++r, e += kTransThreads) out[e] = acc[r];
-    for (int e = L3 + t; e < ld; e += kTransThreads) out[e] = 0.0;
-    __syncthreads();
   }
 }
 
-// Item = parent cell at level tab->level[k] - 1; every child at level
-// tab->level[k] gets Loc_child += transposed interpolation of the parent's
-// local expansion.
-__global__ __launch_bounds__(kTransThreads) void l2l_kernel(const JobDev* __restrict__ jobs,
+// Dynamic LDS (doubles): M2M one cube per child; L2L the parent's cube and
+// one per child.  The matrices (both octant signs, and for L2L transposed)
+// take 2 l^2 more.
+size_t m2m_lds_bytes(int L) { return sizeof(double) * size_t(8 * L * L * L + 2 * L * L); }
+size_t l2l_lds_bytes(int L) { return sizeof(double) * size_t(9 * L * L * L + 2 * L * L); }
+
+// Parent cell p at level lv: W_p = sum over children c (key order) of
+// (Sx (x) Sy (x) Sz)_c W_c.
+template <int L>
+__device__ void m2m_item(const JobDev& J, int lv, int p, double* lds) {
+  constexpr int L2 = L * L, L3 = L2 * L;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double* const Sc = lds;  // Sc[s][m][q]
+  double* const X = lds + 2 * L2;
+  const int ld = J.ld;
+  const int c0 = J.child_start[lv][p], nc = J.child_start[lv][p + 1] - c0;
+  for (int e = t; e < 2 * L2; e += kTransThreads) Sc[e] = J.child[e];
+  double* const Xw = X + w * L3;
+  int oct = 0;
+  if (w < nc) {
+    oct = wuni(int(gld(J.keys[lv + 1] + c0 + w) & 7u));
+    const int64_t crow = (J.lev_off[lv + 1] + c0 + w) * int64_t(ld);
+    // leaf children of the mixed modes are stored in FP32; the contraction
+    // is FP64
+    if (J.w32_leaf && lv + 1 == J.height - 1)
+      for (int e = lane; e < L3; e += 64) Xw[e] = double(gld(J.W32 + crow + e));
+    else
+      for (int e = lane; e < L3; e += 64) Xw[e] = gld(J.W + crow + e);
+  }
+  __syncthreads();
+  if (w < nc) {
+    auto to_x = [&](int i, double v) { Xw[i] = v; };
+    rot_contract<L>(Xw, Sc + ((oct >> 2) & 1) * L2, lane, to_x);  // along z
+    rot_contract<L>(Xw, Sc + ((oct >> 1) & 1) * L2, lane, to_x);  // along y
+    rot_contract<L>(Xw, Sc + (oct & 1) * L2, lane, to_x);         // along x
+  }
+  __syncthreads();
+  double* out = J.W + (J.lev_off[lv] + p) * int64_t(ld);
+  for (int e = t; e < L3; e += kTransThreads) {
+    double acc = 0.0;
+    for (int cc = 0; cc < nc; ++cc) acc += X[cc * L3 + e];
+    out[e] = acc;
+  }
+  for (int e = L3 + t; e < ld; e += kTransThreads) out[e] = 0.0;
+  __syncthreads();
+}
+
+// Item = parent cell at level tab->level[k]; every plan of the launch has
+// order L.
+template <int L>
+__global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __restrict__ jobs,
                                                             const StepTab* __restrict__ tab) {
-  __shared__ double Sc[2 * kMaxOrder * kMaxOrder];
-  __shared__ int oct[8];
   extern __shared__ double dyn_lds[];
-  const int t = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
-    const JobDev& J = jobs[tab->job[k]];
-    const int lv = tab->level[k];  // children's level
-    const int p = it_ - tab->start[k];
-    const int L = J.order, L2 = L * L, L3 = L2 * L, ld = J.ld;
-    double* const P = dyn_lds;
-    double* const A = dyn_lds + L3;
-    double* const B = A + child_group(L3) * L3;
-    for (int e = t; e < 2 * L2; e += kTransThreads) Sc[e] = J.child[e];
-    const double* lp = J.Loc + (J.lev_off[lv - 1] + p) * ld;
-    for (int e = t; e < L3; e += kTransThreads) P[e] = lp[e];
-    const int c0 = J.child_start[lv - 1][p], c1 = J.child_start[lv - 1][p + 1];
-    const int G = child_group(L3);
-    for (int g0 = c0; g0 < c1; g0 += G) {
-      const int nc = min(G, c1 - g0);
-      __syncthreads();
-      if (t < nc) oct[t] = int(J.keys[lv][g0 + t] & 7u);
-      __syncthreads();
-      for (int e = t; e < nc * L3; e += kTransThreads) {  // along z, transposed
-        const int cc = e / L3, r = e - cc * L3;
-        const double* Sz = Sc + (((oct[cc] >> 2) & 1) ? L2 : 0);
-        const int ab = r / L, m3 = r % L;
-        double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sz[q * L + m3] * P[ab * L + q];
-        B[e] = v;
-      }
-      __syncthreads();
-      for (int e = t; e < nc * L3; e += kTransThreads) {  // along y
-        const int cc = e / L3, r = e - cc * L3;
-        const double* Sy = Sc + (((oct[cc] >> 1) & 1) ? L2 : 0);
-        const int a1 = r / L2, m2 = (r / L) % L, m3 = r % L;
-        const double* bb = B + cc * L3;
-        double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sy[q * L + m2] * bb[(a1 * L + q) * L + m3];
-        A[e] = v;
-      }
-      __syncthreads();
-      for (int e = t; e < nc * L3; e += kTransThreads) {  // along x, accumulate
-        const int cc = e / L3, r = e - cc * L3;
-        const double* Sx = Sc + ((oct[cc] & 1) ? L2 : 0);
-        const int m1 = r / L2, rest = r % L2;
-        const double* aa = A + cc * L3;
-        double v = 0.0;
-        for (int q = 0; q < L; ++q) v += Sx[q * L + m1] * aa[q * L2 + rest];
-        J.Loc[(J.lev_off[lv] + g0 + cc) * int64_t(ld) + r] += v;
-      }
-    }
-    __syncthreads();
+    m2m_item<L>(jobs[tab->job[k]], tab->level[k], it_ - tab->start[k], dyn_lds);
+  }
+}
+
+// Parent cell p at level lv - 1: every child c (level lv) gets
+// Loc_c += (Sx (x) Sy (x) Sz)_c^T Loc_p.
+template <int L>
+__device__ void l2l_item(const JobDev& J, int lv, int p, double* lds) {
+  constexpr int L2 = L * L, L3 = L2 * L;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double* const St = lds;  // St[s][m][q] = Sc[s][q][m]
+  double* const P = lds + 2 * L2;
+  double* const X = P + L3;
+  const int ld = J.ld;
+  for (int e = t; e < 2 * L2; e += kTransThreads) {
+    const int s = e / L2, m = (e / L) % L, q = e % L;
+    St[e] = J.child[s * L2 + q * L + m];
+  }
+  const double* lp = J.Loc + (J.lev_off[lv - 1] + p) * int64_t(ld);
+  for (int e = t; e < L3; e += kTransThreads) P[e] = lp[e];
+  const int c0 = J.child_start[lv - 1][p], nc = J.child_start[lv - 1][p + 1] - c0;
+  __syncthreads();
+  if (w < nc) {
+    const int oct = wuni(int(gld(J.keys[lv] + c0 + w) & 7u));
+    double* const Xw = X + w * L3;
+    double* const out = J.Loc + (J.lev_off[lv] + c0 + w) * int64_t(ld);
+    auto to_x = [&](int i, double v) { Xw[i] = v; };
+    rot_contract<L>(P, St + ((oct >> 2) & 1) * L2, lane, to_x);  // along z, transposed
+    rot_contract<L>(Xw, St + ((oct >> 1) & 1) * L2, lane, to_x);  // along y
+    rot_contract<L>(Xw, St + (oct & 1) * L2, lane,
+                    [&](int i, double v) { out[i] += v; });  // along x, accumulated
+  }
+  __syncthreads();
+}
+
+// Item = parent cell at level tab->level[k] - 1 (tab->level[k] is the
+// children's level); every plan of the launch has order L.
+template <int L>
+__global__ __launch_bounds__(kTransThreads) void l2l_kernel(const JobDev* __restrict__ jobs,
+                                                            const StepTab* __restrict__ tab) {
+  extern __shared__ double dyn_lds[];
+  FOR_ITEMS(tab) {
+    const int k = step_find(*tab, it_);
+    l2l_item<L>(jobs[tab->job[k]], tab->level[k], it_ - tab->start[k], dyn_lds);
   }
 }
 
@@ -393,6 +381,106 @@ __global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
       J.f_f[i3 + 2] = fq * gz;
     }
     __syncthreads();
+  }
+}
+
+// Item = leaf, one wavefront, for plans whose leaves hold few particles
+// (kL2PSparseMax): up to kL2PSparseNP particles at a time, lanes over the
+// l^3 terms of their sums.  Per particle the 1-D factors S_d(m) and their
+// derivatives (computed as in l2p_kernel) go to LDS; lane k sums the terms
+// e = k, k + 64, ... of phi and the three gradient components; the 64
+// partial sums of each are then added in lane order.
+constexpr int kL2PSparseNP = 8;
+
+template <int L>
+__global__ __launch_bounds__(64, 4) void l2p_sparse_kernel(const JobDev* __restrict__ jobs,
+                                                        const StepTab* __restrict__ tab) {
+  constexpr int L2 = L * L, L3 = L2 * L, NP = kL2PSparseNP;
+  __shared__ double C[L2];
+  __shared__ double Sd[NP][6][L];  // S_0, S_1, S_2, dS_0, dS_1, dS_2
+  __shared__ double red[4 * NP][65];
+  const int lane = threadIdx.x;
+  FOR_ITEMS(tab) {
+    const int k = step_find(*tab, it_);
+    const JobDev& J = jobs[tab->job[k]];
+    const int a = it_ - tab->start[k];
+    for (int e = lane; e < L2; e += 64) C[e] = J.cheb[e];
+    double c[3];
+    leaf_centre(J.geo, J.leaf_keys[a], c);
+    const double ia = 2.0 / J.geo.w;
+    const double* lsrc = J.Loc + (J.lev_off[J.height - 1] + a) * J.ld;
+    const int s0 = wuni(gld(J.leaf_start + a)), s1 = wuni(gld(J.leaf_start + a + 1));
+    __syncthreads();
+    for (int i0 = s0; i0 < s1; i0 += NP) {
+      const int np = min(NP, s1 - i0);
+      for (int v = lane; v < np * 3 * L; v += 64) {
+        const int j = v / (3 * L), d = (v / L) % 3, m = v % L;
+        const int i = i0 + j;
+        const double x = gld(d == 0 ? J.px + i : (d == 1 ? J.py + i : J.pz + i));
+        const double u = (x - c[d]) * ia;
+        double T[L], dT[L];
+        T[0] = 1.0;
+        dT[0] = 0.0;
+        if (L > 1) {
+          T[1] = u;
+          dT[1] = 1.0;
+        }
+        for (int n = 2; n < L; ++n) {
+          T[n] = 2.0 * u * T[n - 1] - T[n - 2];
+          dT[n] = 2.0 * T[n - 1] + 2.0 * u * dT[n - 1] - dT[n - 2];
+        }
+        double sv = 0.0, dv = 0.0;
+        for (int n = 0; n < L; ++n) {
+          sv += C[m * L + n] * T[n];
+          dv += C[m * L + n] * dT[n];
+        }
+        Sd[j][d][m] = sv;
+        Sd[j][3 + d][m] = dv;
+      }
+      __syncthreads();
+      double acc[NP][4];
+#pragma unroll
+      for (int j = 0; j < NP; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
+#pragma unroll 2
+      for (int e = lane; e < L3; e += 64) {
+        const double lc = gld(lsrc + e);
+        const int m1 = e / L2, m2 = (e / L) % L, m3 = e % L;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+          if (j >= np) break;
+          const double t23 = lc * Sd[j][1][m2] * Sd[j][2][m3];
+          const double t1 = lc * Sd[j][0][m1];
+          acc[j][0] += Sd[j][0][m1] * t23;
+          acc[j][1] += Sd[j][3][m1] * t23;
+          acc[j][2] += t1 * Sd[j][4][m2] * Sd[j][2][m3];
+          acc[j][3] += t1 * Sd[j][1][m2] * Sd[j][5][m3];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        if (j >= np) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[4 * j + q][lane] = acc[j][q];
+      }
+      __syncthreads();
+      if (lane < 4 * np) {
+        double v = 0.0;
+#pragma unroll 8
+        for (int l = 0; l < 64; ++l) v += red[lane][l];
+        red[lane][64] = v;
+      }
+      __syncthreads();
+      if (lane < np) {
+        const int i = i0 + lane;
+        const double fq = -J.qs[i] * ia;
+        J.phi_f[i] = red[4 * lane][64];
+        const int64_t i3 = 3 * int64_t(i);
+        J.f_f[i3] = fq * red[4 * lane + 1][64];
+        J.f_f[i3 + 1] = fq * red[4 * lane + 2][64];
+        J.f_f[i3 + 2] = fq * red[4 * lane + 3][64];
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -657,62 +745,61 @@ __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ 
 // M2L left Chebyshev coefficients c (J.modal), the node values
 //     Loc[m1][m2][m3] = sum_n T_n1(xb_m1) T_n2(xb_m2) T_n3(xb_m3) c[n1][n2][n3]
 // of their interpolant (Eq. 5), in FP64 as three 1-D passes (6 l^4 flops).
-constexpr int kMaxLd = kMaxOrder * kMaxOrder * kMaxOrder;
-__global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__ jobs,
-                                                      const StepTab* __restrict__ tab) {
-  __shared__ double va[kMaxLd], vb[kMaxLd];
-  __shared__ double A[kMaxOrder * kMaxOrder];
+// One wavefront per row.
+template <int L>
+__device__ void loc_sum_modal(const JobDev& J, int64_t r, double* lds) {
+  constexpr int L2 = L * L, L3 = L2 * L;
+  const int lane = threadIdx.x;
+  double* const A = lds;  // A[m][n] = T_n(xb_m)
+  double* const X = lds + L2;
+  const int64_t n = J.locx_rows * J.ld;
+  double* loc = J.Loc + (J.locx_first + r) * J.ld;
+  const double* x = J.LocX + r * J.ld;
+  const int parts = wuni(J.m2l_parts);
+  for (int e = lane; e < L2; e += 64) A[e] = J.tcheb[e];
+  for (int e = lane; e < L3; e += 64) {
+    double v = gld(loc + e);
+    for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
+    X[e] = v;
+  }
+  __syncthreads();
+  auto to_x = [&](int i, double v) { X[i] = v; };
+  // (the barriers between the passes also keep the compiler from holding
+  // all of A in registers across them)
+  rot_contract<L>(X, A, lane, to_x);  // along z: (n1, n2, n3) -> (m3, n1, n2)
+  __syncthreads();
+  rot_contract<L>(X, A, lane, to_x);  // along y: -> (m2, m3, n1)
+  __syncthreads();
+  rot_contract<L>(X, A, lane, [&](int i, double v) { gst(loc + i, v); });  // along x
+  for (int e = L3 + lane; e < J.ld; e += 64) gst(loc + e, 0.0);
+  __syncthreads();
+}
+
+size_t loc_sum_lds_bytes(int L) { return sizeof(double) * size_t(L * L * L + L * L); }
+
+// Item = row r of a plan of order L.
+template <int L>
+__global__ __launch_bounds__(64) void loc_sum_kernel(const JobDev* __restrict__ jobs,
+                                                     const StepTab* __restrict__ tab) {
+  extern __shared__ double dyn_lds[];
   const int t = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int64_t r = it_ - tab->start[k];
+    if (wuni(J.modal)) {
+      loc_sum_modal<L>(J, r, dyn_lds);
+      continue;
+    }
     const int64_t n = J.locx_rows * J.ld;
     double* loc = J.Loc + (J.locx_first + r) * J.ld;
     const double* x = J.LocX + r * J.ld;
     const int parts = wuni(J.m2l_parts);
-    if (!wuni(J.modal)) {
-      for (int e = t; e < J.ld; e += 256) {
-        double v = gld(loc + e);
-        for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
-        gst(loc + e, v);
-      }
-      continue;
-    }
-    const int L = wuni(J.order), L2 = L * L, l3 = L2 * L;
-    for (int e = t; e < L2; e += 256) A[e] = J.tcheb[e];
-    for (int e = t; e < l3; e += 256) {
+    for (int e = t; e < J.ld; e += 64) {
       double v = gld(loc + e);
       for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
-      va[e] = v;
-    }
-    __syncthreads();
-    for (int e = t; e < l3; e += 256) {  // along z: (n1, n2, n3) -> (n1, n2, m3)
-      const int m3 = e % L;
-      const double* src = va + (e - m3);
-      double v = 0.0;
-      for (int j = 0; j < L; ++j) v += A[m3 * L + j] * src[j];
-      vb[e] = v;
-    }
-    __syncthreads();
-    for (int e = t; e < l3; e += 256) {  // along y: (n1, n2, m3) -> (n1, m2, m3)
-      const int m3 = e % L, m2 = (e / L) % L, n1 = e / L2;
-      const double* src = vb + n1 * L2 + m3;
-      double v = 0.0;
-      for (int j = 0; j < L; ++j) v += A[m2 * L + j] * src[j * L];
-      va[e] = v;
-    }
-    __syncthreads();
-    for (int e = t; e < J.ld; e += 256) {  // along x: (n1, m2, m3) -> (m1, m2, m3)
-      double v = 0.0;
-      if (e < l3) {
-        const int m1 = e / L2;
-        const double* src = va + (e - m1 * L2);
-        for (int j = 0; j < L; ++j) v += A[m1 * L + j] * src[j * L2];
-      }
       gst(loc + e, v);
     }
-    __syncthreads();
   }
 }
 
@@ -838,13 +925,17 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       break;
     }
     case kStepM2M:
-      m2m_kernel<<<g, kTransThreads, lds_up_to(L, m2m_lds_bytes), s>>>(jobs, tab);
+#define M2M_CALL(LL) m2m_kernel<LL><<<g, kTransThreads, m2m_lds_bytes(LL), s>>>(jobs, tab)
+      FMM_ORDER_SWITCH(L, M2M_CALL)
+#undef M2M_CALL
       break;
     case kStepCast:
       cast_kernel<<<g, 256, 0, s>>>(jobs, tab);
       break;
     case kStepLocSum:
-      loc_sum_kernel<<<g, 256, 0, s>>>(jobs, tab);
+#define LOC_SUM_CALL(LL) loc_sum_kernel<LL><<<g, 64, loc_sum_lds_bytes(LL), s>>>(jobs, tab)
+      FMM_ORDER_SWITCH(L, LOC_SUM_CALL)
+#undef LOC_SUM_CALL
       break;
     case kStepM2L:
       launch_m2l_step(L, fp32, jobs, tab, grid, s);
@@ -853,10 +944,17 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       launch_m2l_svd_step(L, fp32, jobs, tab, grid, xs, s);
       break;
     case kStepL2L:
-      l2l_kernel<<<g, kTransThreads, lds_up_to(L, l2l_lds_bytes), s>>>(jobs, tab);
+#define L2L_CALL(LL) l2l_kernel<LL><<<g, kTransThreads, l2l_lds_bytes(LL), s>>>(jobs, tab)
+      FMM_ORDER_SWITCH(L, L2L_CALL)
+#undef L2L_CALL
       break;
     case kStepL2P:
 #define L2P_CALL(LL) l2p_kernel<LL><<<g, 64, 0, s>>>(jobs, tab)
+      FMM_ORDER_SWITCH(L, L2P_CALL)
+#undef L2P_CALL
+      break;
+    case kStepL2PSparse:
+#define L2P_CALL(LL) l2p_sparse_kernel<LL><<<g, 64, 0, s>>>(jobs, tab)
       FMM_ORDER_SWITCH(L, L2P_CALL)
 #undef L2P_CALL
       break;
@@ -930,9 +1028,11 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
                   p->job_h.xs);
   };
   auto loc_sum = [&]() {
-    if (p->tab_h[kTabLocSum].start[1] > 0)
+    if (p->tab_h[kTabLocSum].start[1] > 0) {
+      Timed t(FMM_TIME_LOC_SUM, s);
       launch_step(kStepLocSum, L, false, J, p->tab_d + kTabLocSum, nullptr,
                   p->tab_h[kTabLocSum].start[1], s);
+    }
   };
   if (h >= 3) {
     {
@@ -951,9 +1051,12 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
       }
       FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
     }
-    for (int st = 0; st + 4 <= h; ++st)
-      launch_step(kStepM2M, L, false, J, p->tab_d + kTabM2M + st, nullptr,
-                  p->tab_h[kTabM2M + st].start[1], s);
+    {
+      Timed t(FMM_TIME_M2M, s);
+      for (int st = 0; st + 4 <= h; ++st)
+        launch_step(kStepM2M, L, false, J, p->tab_d + kTabM2M + st, nullptr,
+                    p->tab_h[kTabM2M + st].start[1], s);
+    }
     if (mixed && p->tab_h[kTabCast].start[1] > 0)
       launch_step(kStepCast, L, true, J, p->tab_d + kTabCast, nullptr,
                   p->tab_h[kTabCast].start[1], s);
@@ -964,23 +1067,27 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
         FMM_HIP_CHECK(hipStreamWaitEvent(s, p->ev_join, 0));
         loc_sum();
       }
-    } else {
-      Timed t(FMM_TIME_M2L, s);
-      if (p->ntiles > 0) {
+    } else if (p->ntiles > 0) {
+      {
+        Timed t(FMM_TIME_M2L, s);
         m2l_launch(kTabM2L, s);
-        loc_sum();
       }
+      loc_sum();
     }
     if (forked && FMM_FORK_AFTER_M2L == 1) fork_near();
-    for (int st = 0; st + 4 <= h; ++st) {
-      if (forked && FMM_FORK_AFTER_M2L == 3 && st + 4 == h) fork_near();
-      launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,
-                  p->tab_h[kTabL2L + st].start[1], s);
+    {
+      Timed t(FMM_TIME_L2L, s);
+      for (int st = 0; st + 4 <= h; ++st) {
+        if (forked && FMM_FORK_AFTER_M2L == 3 && st + 4 == h) fork_near();
+        launch_step(kStepL2L, L, false, J, p->tab_d + kTabL2L + st, nullptr,
+                    p->tab_h[kTabL2L + st].start[1], s);
+      }
     }
     if (forked && (FMM_FORK_AFTER_M2L == 2 || (FMM_FORK_AFTER_M2L == 3 && h < 4))) fork_near();
     {
       Timed t(FMM_TIME_L2P, s);
-      launch_step(kStepL2P, L, false, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+      launch_step(p->job_h.l2p_sparse ? kStepL2PSparse : kStepL2P, L, false, J,
+                  p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
     }
   }
   if (forked) {
@@ -996,7 +1103,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
 
 
 bool timing_hooks_set() {
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kTimedSteps; ++i)
     if (g_time_ev[i][0] || g_time_ev[i][1]) return true;
   return false;
 }

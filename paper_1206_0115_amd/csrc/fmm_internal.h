@@ -29,6 +29,13 @@ namespace fmm {
 
 constexpr int kMaxHeight = 21;
 constexpr int kMaxOrder = 12;
+// Plans with at most this many particles per leaf on average evaluate their
+// local expansions with one wavefront per leaf spread over the l^3 terms
+// (l2p_sparse_kernel); denser ones with lanes over particles (l2p_kernel).
+// Per leaf of np particles the first costs about 20 np instructions per lane
+// per 64 terms, the second one pass of about 3 l^2 + 2 l^3 per 32 particles:
+// even near np = 7 at orders 7 to 10.
+constexpr int kL2PSparseMax = 6;
 constexpr int kTileN = 64;     // target cells per M2L tile
 constexpr int kSlots = 189;    // far offsets per child parity
 constexpr int kOffsets = 316;  // distinct far offsets
@@ -274,5 +281,6 @@ void release_graph(fmm_plan_s* p);
 void upload_job(fmm_plan_s* p, hipStream_t stream);
 // Step timing hooks (enum fmm_timed_step): the step's launch in later
 // evaluations on this thread is bracketed by these events when they are set.
-extern thread_local hipEvent_t g_time_ev[4][2];
+constexpr int kTimedSteps = FMM_TIME_LOC_SUM + 1;
+extern thread_local hipEvent_t g_time_ev[kTimedSteps][2];
 }  // namespace fmm

@@ -44,6 +44,9 @@ struct JobDev {
   // FP32 M2L (mixed modes): the local expansions of levels >= 2 leave M2L
   // as Chebyshev coefficients and become node values in the loc-sum pass
   int modal;
+  // leaves hold few particles on average: L2P spreads each particle's l^3
+  // terms over a wavefront's lanes (l2p_sparse_kernel)
+  int l2p_sparse;
   // compressed M2L split: each tile's far offsets in m2l_parts consecutive
   // ranges, one work item each; part 0 writes Loc, part p > 0 the rows
   // (p - 1) * locx_rows + (target row - locx_first) of LocX
@@ -125,7 +128,7 @@ __device__ inline int step_find(const StepTab& t, int item) {
 // kStepM2LSvd is the compressed M2L; `xs` is then the LDS row stride (the
 // largest padded rank of the launch's jobs + 4).
 enum StepKind { kStepGather, kStepP2M, kStepM2M, kStepCast, kStepM2L, kStepL2L, kStepL2P,
-                kStepP2P, kStepCombine, kStepM2LSvd, kStepLocSum };
+                kStepP2P, kStepCombine, kStepM2LSvd, kStepLocSum, kStepL2PSparse };
 void launch_step(StepKind kind, int order, bool fp32, const JobDev* jobs, const StepTab* tab,
                  const CallDev* calls, int grid, hipStream_t s, int xs = 0);
 

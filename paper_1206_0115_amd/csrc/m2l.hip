@@ -50,7 +50,7 @@
 
 namespace fmm {
 
-thread_local hipEvent_t g_time_ev[4][2] = {{nullptr, nullptr}};
+thread_local hipEvent_t g_time_ev[kTimedSteps][2] = {{nullptr, nullptr}};
 
 // ------------------------------------------------------------ tables
 namespace {
@@ -1230,19 +1230,35 @@ __device__ inline bool svd_item(const JobDev* __restrict__ jobs, const StepTab* 
   return I.col0 < I.tl.count;
 }
 
-template <typename T, int NT, int D>
+// The 32-column items of 8 consumers (FP32 at orders 10 to 12, where whole
+// tiles would spill) have registers to spare at 3 wavefronts per SIMD: their
+// producers take 3 rank tiles per pass, so that the offsets padded to rank
+// 48 gather their multipoles once, and keep two chunks in flight (30M-
+// particle order-10 cube, M2L 5126 -> 4771 ms; 167 VGPRs, no spills).  The
+// other shapes spill with either.
+#ifndef FMM_M2L_SVD_RPASS_WIDE_F32
+#define FMM_M2L_SVD_RPASS_WIDE_F32 3
+#endif
+#ifndef FMM_M2L_SVD_WS_LOOK_WIDE_F32
+#define FMM_M2L_SVD_WS_LOOK_WIDE_F32 2
+#endif
+
+template <typename T, int NT, int D, int NCW>
 __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
                                       const StepTab* __restrict__ tab, T* const lds,
                                       SvdMeta* const meta, int kg) {
   typedef typename Vec4<T>::type T4;
   constexpr bool F32 = sizeof(T) == 4;
   constexpr int NC = 16 * NT;
-  constexpr int kRP = F32 ? FMM_M2L_SVD_RPASS_F32 : FMM_M2L_SVD_RPASS_F64;
+  constexpr bool kWide = F32 && NT == 2 && NCW == 8;
+  constexpr int kRP = kWide ? FMM_M2L_SVD_RPASS_WIDE_F32
+                            : F32 ? FMM_M2L_SVD_RPASS_F32 : FMM_M2L_SVD_RPASS_F64;
   // staged path: the next rank tile's factor fragments load while this one
   // computes (1) or after it (0)
   constexpr bool kAPre = F32 ? FMM_M2L_SVD_WS_APRE_F32 : FMM_M2L_SVD_WS_APRE_F64;
   constexpr bool kXPre = F32 ? FMM_M2L_SVD_WS_XPRE_F32 : FMM_M2L_SVD_WS_XPRE_F64;
-  constexpr int kLook = F32 ? FMM_M2L_SVD_WS_LOOK_F32 : FMM_M2L_SVD_WS_LOOK_F64;
+  constexpr int kLook = kWide ? FMM_M2L_SVD_WS_LOOK_WIDE_F32
+                              : F32 ? FMM_M2L_SVD_WS_LOOK_F32 : FMM_M2L_SVD_WS_LOOK_F64;
   const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
   const int total = step_total(*tab);
   int buf = 0;
@@ -1606,7 +1622,7 @@ __global__ __launch_bounds__(64 * (4 + NCW), svd_ws_waves(NCW, NT * int(sizeof(T
   // the role is uniform per wavefront: a scalar branch, no lane masking
   const int wave = wuni(int(threadIdx.x >> 6));
   if (wave < 4)
-    svd_ws_produce<T, NT, D>(jobs, tab, lds, meta, wave);
+    svd_ws_produce<T, NT, D, NCW>(jobs, tab, lds, meta, wave);
   else
     svd_ws_consume<T, MTW, NT, NCW>(jobs, tab, lds, meta, wave - 4);
 }

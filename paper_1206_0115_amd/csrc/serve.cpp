@@ -32,7 +32,10 @@
 namespace fmm {
 namespace {
 
-constexpr int kMaxSteps = 160;
+// Launches per batch: up to 48 per order present (two per tree level for
+// M2M and L2L, eight M2L forms, P2M, two L2P forms, the coefficient rows)
+// and five more.
+constexpr int kMaxSteps = 640;
 constexpr int kBuffers = 2;
 // Batching window: admitted requests wait for the planner to finish the
 // requests that arrived with them, but no longer than this, so that a burst
@@ -368,13 +371,13 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
   for (int L : orders)
     add(kStepP2M, L, false, [&](Request* r) { return far(r) && r->order == L; },
         [](Request* r) { return int(r->plan->nleaf); }, lvl0);
-  // M2M and L2L take every order in one launch; their LDS is sized for the
-  // batch's highest order
-  const int maxo = orders.empty() ? 0 : orders.back();
+  // M2M, L2L and the coefficient rows are compiled per order: one launch per
+  // order present at each level
   for (int s = 0; s < steps; ++s)
-    add(kStepM2M, maxo, false, [&](Request* r) { return r->h - 4 >= s; },
-        [&](Request* r) { return int(r->plan->lev[r->h - 2 - s].ncell); },
-        [&](Request* r) { return r->h - 2 - s; });
+    for (int L : orders)
+      add(kStepM2M, L, false, [&](Request* r) { return r->h - 4 >= s && r->order == L; },
+          [&](Request* r) { return int(r->plan->lev[r->h - 2 - s].ncell); },
+          [&](Request* r) { return r->h - 2 - s; });
   add(kStepCast, 0, true, [&](Request* r) { return far(r) && mixed(r); },
       [](Request* r) { return int(r->plan->tab_h[kTabCast].start[1]); }, lvl0);
   // dense, then compressed by the kernel's N-tiles per item (1, 2, 4): one
@@ -394,18 +397,25 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
             lvl0);
   // partial sums of plans that split their compressed M2L back into Loc, and
   // the FP32 M2L's Chebyshev-coefficient rows back to node values
-  add(kStepLocSum, 0, false,
-      [&](Request* r) {
-        return far(r) && (r->plan->job_h.m2l_parts > 1 || r->plan->job_h.modal);
-      },
-      [](Request* r) { return int(r->plan->job_h.locx_rows); }, lvl0);
-  for (int s = 0; s < steps; ++s)
-    add(kStepL2L, maxo, false, [&](Request* r) { return r->h - 4 >= s; },
-        [&](Request* r) { return int(r->plan->lev[2 + s].ncell); },
-        [&](Request*) { return 3 + s; });
   for (int L : orders)
-    add(kStepL2P, L, false, [&](Request* r) { return far(r) && r->order == L; },
-        [](Request* r) { return int(r->plan->nleaf); }, lvl0);
+    add(kStepLocSum, L, false,
+        [&](Request* r) {
+          return far(r) && r->order == L &&
+                 (r->plan->job_h.m2l_parts > 1 || r->plan->job_h.modal);
+        },
+        [](Request* r) { return int(r->plan->job_h.locx_rows); }, lvl0);
+  for (int s = 0; s < steps; ++s)
+    for (int L : orders)
+      add(kStepL2L, L, false, [&](Request* r) { return r->h - 4 >= s && r->order == L; },
+          [&](Request* r) { return int(r->plan->lev[2 + s].ncell); },
+          [&](Request*) { return 3 + s; });
+  for (int L : orders)
+    for (int sp = 0; sp < 2; ++sp)
+      add(sp ? kStepL2PSparse : kStepL2P, L, false,
+          [&](Request* r) {
+            return far(r) && r->order == L && (r->plan->job_h.l2p_sparse != 0) == (sp != 0);
+          },
+          [](Request* r) { return int(r->plan->nleaf); }, lvl0);
   for (int f32 = 0; f32 < 2; ++f32)
     add(kStepP2P, 0, f32 != 0, [&](Request* r) { return mixed(r) == (f32 != 0); },
         [](Request* r) { return int(r->plan->nleaf); }, lvl0);

@@ -303,14 +303,16 @@ class Plan:
 
 
 FMM_TIME_M2L, FMM_TIME_P2P, FMM_TIME_P2M, FMM_TIME_L2P = 0, 1, 2, 3
+FMM_TIME_M2M, FMM_TIME_L2L, FMM_TIME_LOC_SUM = 4, 5, 6
 TIMED_STEPS = {"m2l": FMM_TIME_M2L, "p2p": FMM_TIME_P2P, "p2m": FMM_TIME_P2M,
-               "l2p": FMM_TIME_L2P}
+               "l2p": FMM_TIME_L2P, "m2m": FMM_TIME_M2M, "l2l": FMM_TIME_L2L,
+               "loc_sum": FMM_TIME_LOC_SUM}
 
 
 def set_step_timing_events(step, ev0, ev1):
-    """Bracket one operator's kernel ("m2l", "p2p", "p2m" or "l2p") in later
-    evaluations on this thread with two ``torch.cuda.Event`` objects (or None
-    to stop)."""
+    """Bracket one operator's kernel ("m2l", "p2p", "p2m", "l2p", "loc_sum",
+    or all levels of "m2m" or "l2l") in later evaluations on this thread with
+    two ``torch.cuda.Event`` objects (or None to stop)."""
     code = TIMED_STEPS[step] if isinstance(step, str) else int(step)
     if ev0 is None:
         _check(lib().fmm_set_step_timing_events(code, None, None))

@@ -56,6 +56,10 @@ def test_calls_reject_null_plan():
     assert lib.fmm_plan_set_m2l_split(None, 2) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_m2l_split(None, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_set_step_timing_events(9, None, None) == fmm.FMM_ERR_ARG
+    assert lib.fmm_set_step_timing_events(fmm.FMM_TIME_LOC_SUM + 1, None, None) == fmm.FMM_ERR_ARG
+    assert lib.fmm_set_step_timing_events(-1, None, None) == fmm.FMM_ERR_ARG
+    for step in fmm.TIMED_STEPS.values():
+        assert lib.fmm_set_step_timing_events(step, None, None) == fmm.FMM_OK
     assert lib.fmm_set_step_timing_events(fmm.FMM_TIME_P2P, fake, None) == fmm.FMM_ERR_ARG
     assert lib.fmm_set_step_timing_events(fmm.FMM_TIME_P2P, None, None) == fmm.FMM_OK
     assert lib.fmm_plan_info(None, None) == fmm.FMM_ERR_ARG

@@ -103,6 +103,28 @@ def test_fp64_parity(kind, n, h, l, seed):
         assert not host(pf).any() and not host(ff).any()
 
 
+# Orders whose l^2 lines take two or three rounds of a wavefront in the
+# transfer passes (l >= 9), over two and three levels of M2M and L2L, with
+# dense leaves (lanes over particles in L2P) and sparse ones (lanes over the
+# l^3 terms), against the oracle at sampled targets.
+HIGH = [(h, l, n) for l in (9, 10, 11, 12) for h, n in ((4, 30000), (5, 60000))] + [
+    (5, 9, 5000), (4, 11, 2000)]
+
+
+@pytest.mark.parametrize("h,l,n", HIGH)
+def test_high_order_transfer_levels(h, l, n):
+    say(f"high-order transfer levels h={h} l={l} n={n}")
+    pos, q = inputs.make("cube", n, 91)
+    tree = oracle.Tree(pos, h)
+    idx = np.sort(np.random.default_rng(3).choice(n, 32, replace=False))
+    p_o, f_o = tree.fmm(l, q, targets=idx)
+    plan = fmm.Plan(dev(pos), h, l, "fp64")
+    phi, f = plan.evaluate(dev(q))
+    torch.cuda.synchronize()
+    assert rel(host(phi)[idx], p_o) <= FP64_TOL
+    assert rel(host(f)[idx], f_o) <= FP64_TOL
+
+
 def test_one_level_matches_direct():
     pos, q = inputs.uniform_cube(2000, 21)
     plan = fmm.Plan(dev(pos), 1, 5)
