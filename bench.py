@@ -43,11 +43,9 @@ HEADLINE = "cube30m_h9_p10"
 # against FP64 on their density twin: the same particles per leaf slot,
 # order and M2L tolerance, two levels fewer.
 TWIN = {"cube30m_h9_p10": "cube469k_h7_p10"}
-# Compressed-M2L tolerance per workload (None: the library default,
-# 10^-order).  At order 10 the mixed mode's error against FP64 is set by
-# the SVD truncation and the FP32 phase-1 sums; 1e-7 keeps the twin within
-# half the gate with about half the ranks of 1e-10.
-HEADLINE_EPS = {"cube30m_h9_p10": 1e-7, "cube469k_h7_p10": 1e-7}
+# Compressed-M2L tolerance per workload (absent: the library default,
+# 10^-order), chosen on the twin by the gate (inputs.SVD_TOL).
+from paper_1206_0115_amd.inputs import SVD_TOL as HEADLINE_EPS  # noqa: E402
 N_EXACT = 256  # seeded targets of the exact-sum check
 
 
@@ -269,14 +267,10 @@ def ingest_traffic(args):
         # the elementwise negation of the COPY_BYTES buffer is the largest
         # elementwise dispatch for both counters
         cal = max(v for _, k, v in rows if "elementwise" in k)
-        # one M2L step per mode: the M2L kernel, then the row pass that adds
-        # the partial sums back and turns coefficients into node values
-        m2l = []
-        for _, k, v in rows:
-            if "m2l_kernel" in k or "m2l_svd_kernel" in k or "m2l_svd_ws_kernel" in k:
-                m2l.append(v)
-            elif "loc_sum_kernel" in k and m2l:
-                m2l[-1] += v
+        # one M2L launch per mode (the kernel the roofline times; the row
+        # pass after it is a kernel of its own)
+        m2l = [v for _, k, v in rows
+               if "m2l_kernel" in k or "m2l_svd_kernel" in k or "m2l_svd_ws_kernel" in k]
         return COPY_BYTES / (cal * 1024.0), cal, m2l
 
     sf, calf, mf = scale_and_m2l(fetch)
@@ -429,9 +423,17 @@ class Bench:
         """Average duration of each bulk operator's kernel, every operator on
         one stream (serial schedule, so no kernel shares the GPU)."""
         torch, fmm, s = self.torch, self.fmm, self.stream
-        names = ("m2l", "p2p", "p2m", "l2p", "m2m", "l2l", "loc_sum")
         with torch.cuda.stream(s):
             p = self.plan(prec)
+            # the steps this plan runs (the events are recorded once when
+            # made, so a step that never runs would time as zero)
+            names = ["p2p"]
+            if self.h >= 3:
+                names += ["m2l", "p2m", "l2p"]
+                if p.m2l_split() > 1:
+                    names.append("loc_sum")
+            if self.h >= 4:
+                names += ["m2m", "l2l"]
             p.set_schedule("serial")
             p.evaluate(self.q_d, self.phi, self.frc, stream=s)
             ev = [self.new_events(2 * len(names)) for _ in range(reps)]
@@ -444,13 +446,8 @@ class Bench:
             for name in names:
                 fmm.set_step_timing_events(name, None, None)
             p.release()
-        out = {}
-        for k, name in enumerate(names):
-            try:  # a step the mode does not run leaves its events unrecorded
-                out[name] = float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
-            except RuntimeError:
-                pass
-        return out
+        return {name: float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
+                for k, name in enumerate(names)}
 
     def exact_error(self, count):
         """Error of the last evaluation's output against exact sums (GPU
@@ -501,8 +498,9 @@ class Bench:
                         "6 l^4 FP64 flops per child cell, all levels"),
             "l2l": rate(trans * children, st.get("l2l"), PEAK_TFLOPS["fp64"], "TFLOP/s", "alu",
                         "6 l^4 FP64 flops per child cell, all levels"),
-            "loc_sum": rate(trans * rows, st.get("loc_sum"), PEAK_TFLOPS["fp64"], "TFLOP/s", "alu",
-                            "6 l^4 FP64 flops per cell of levels >= 2"),
+            "loc_sum": rate(8.0 * self.l ** 3 * rows * (getattr(self, "split", 1) + 1),
+                            st.get("loc_sum"), HBM_GBPS, "GB/s", "hbm",
+                            "l^3 x 8 B per part and cell of levels >= 2 read, the cell's row written"),
         }
         return {k: v for k, v in out.items() if v is not None}
 

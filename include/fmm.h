@@ -301,8 +301,8 @@ int fmm_set_m2l_timing_events(hipEvent_t ev0, hipEvent_t ev1);
  * P2P in the forked schedule, the plan's side stream; for M2L in the
  * pipelined one, the leaf level's launch on the side stream).  M2M and L2L
  * bracket all their level launches; FMM_TIME_LOC_SUM the pass that adds the
- * split M2L's partial sums and turns the FP32 M2L's Chebyshev coefficients
- * into node values (absent where neither applies).  Pass NULLs to stop.
+ * split compressed M2L's partial sums (absent for an unsplit M2L).  Pass
+ * NULLs to stop.
  * Returns FMM_ERR_ARG for an unknown step or a single NULL event. */
 enum fmm_timed_step {
   FMM_TIME_M2L = 0,

@@ -157,7 +157,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.kp32 = op->kpack32;
   J.slot_kid = op->slot_kid;
   J.cheb = op->cheb;
-  J.tcheb = op->tcheb;
+  J.child_modal = op->child_modal;
   J.child = op->child;
   J.phi_n = p->phi_n;
   J.f_n = p->f_n;
@@ -178,7 +178,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
     p->tab_h[kTabM2LLeaf] = one_job(leaf_items);
     p->tab_h[kTabM2LCoarse] = one_job(int(p->ntiles) * J.nmb * parts - leaf_items);
     p->tab_h[kTabM2LCoarse].first[0] = leaf_items;
-    p->tab_h[kTabLocSum] = one_job(parts > 1 || J.modal ? int(lrows) : 0);
+    p->tab_h[kTabLocSum] = one_job(parts > 1 ? int(lrows) : 0);
     for (int st = 0; st + 4 <= h; ++st) {
       p->tab_h[kTabM2M + st] = one_job(int(p->lev[h - 2 - st].ncell), h - 2 - st);
       // L2L items are the parents (level 2 + st) of the cells it updates

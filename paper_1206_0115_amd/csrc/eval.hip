@@ -151,7 +151,8 @@ __device__ __forceinline__ void wave_lds_sync() {
 // next one again runs along the last index (three restore the order).  M is
 // row-major in LDS.  One wavefront: lane takes lines a L + b = lane + 64 r;
 // every lane reads all its lines before any lane writes (so `out` may be
-// `in`), and each output goes with its index m L^2 + a L + b to `emit`.
+// `in`), and each output goes to `emit` with its index m L^2 + a L + b and
+// its (m, round).
 template <int L, typename Emit>
 __device__ __forceinline__ void rot_contract(const double* in, const double* M, int lane,
                                              Emit emit) {
@@ -176,7 +177,7 @@ __device__ __forceinline__ void rot_contract(const double* in, const double* M, 
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < L; ++q) acc += row[q] * v[r][q];
-      if (line < L2) emit(m * L2 + line, acc);
+      if (line < L2) emit(m * L2 + line, acc, m, r);
     }
   }
 }
@@ -212,7 +213,7 @@ __device__ void m2m_item(const JobDev& J, int lv, int p, double* lds) {
   }
   __syncthreads();
   if (w < nc) {
-    auto to_x = [&](int i, double v) { Xw[i] = v; };
+    auto to_x = [&](int i, double v, int, int) { Xw[i] = v; };
     rot_contract<L>(Xw, Sc + ((oct >> 2) & 1) * L2, lane, to_x);  // along z
     rot_contract<L>(Xw, Sc + ((oct >> 1) & 1) * L2, lane, to_x);  // along y
     rot_contract<L>(Xw, Sc + (oct & 1) * L2, lane, to_x);         // along x
@@ -241,18 +242,22 @@ __global__ __launch_bounds__(kTransThreads) void m2m_kernel(const JobDev* __rest
 }
 
 // Parent cell p at level lv - 1: every child c (level lv) gets
-// Loc_c += (Sx (x) Sy (x) Sz)_c^T Loc_p.
+// Loc_c += (Sx (x) Sy (x) Sz)_c^T Loc_p on node values, or the exact
+// re-expansion (Rx (x) Ry (x) Rz)_c Loc_p on Chebyshev coefficients.
 template <int L>
 __device__ void l2l_item(const JobDev& J, int lv, int p, double* lds) {
   constexpr int L2 = L * L, L3 = L2 * L;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  double* const St = lds;  // St[s][m][q] = Sc[s][q][m]
+  // node values: St[s][m][q] = Sc[s][q][m]; Chebyshev coefficients (the
+  // mixed modes): the re-expansion R_s[m][q] on the child's interval
+  double* const St = lds;
   double* const P = lds + 2 * L2;
   double* const X = P + L3;
   const int ld = J.ld;
+  const bool modal = wuni(J.modal);
   for (int e = t; e < 2 * L2; e += kTransThreads) {
     const int s = e / L2, m = (e / L) % L, q = e % L;
-    St[e] = J.child[s * L2 + q * L + m];
+    St[e] = modal ? J.child_modal[e] : J.child[s * L2 + q * L + m];
   }
   const double* lp = J.Loc + (J.lev_off[lv - 1] + p) * int64_t(ld);
   for (int e = t; e < L3; e += kTransThreads) P[e] = lp[e];
@@ -262,11 +267,21 @@ __device__ void l2l_item(const JobDev& J, int lv, int p, double* lds) {
     const int oct = wuni(int(gld(J.keys[lv] + c0 + w) & 7u));
     double* const Xw = X + w * L3;
     double* const out = J.Loc + (J.lev_off[lv] + c0 + w) * int64_t(ld);
-    auto to_x = [&](int i, double v) { Xw[i] = v; };
+    // the child's expansion where this lane adds to it in the last pass,
+    // loaded before the passes so that the adds do not wait on memory
+    constexpr int R = (L2 + 63) / 64;
+    double cur[R][L];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int m = 0; m < L; ++m)
+        cur[r][m] = lane + 64 * r < L2 ? gld(out + m * L2 + lane + 64 * r) : 0.0;
+    auto to_x = [&](int i, double v, int, int) { Xw[i] = v; };
     rot_contract<L>(P, St + ((oct >> 2) & 1) * L2, lane, to_x);  // along z, transposed
     rot_contract<L>(Xw, St + ((oct >> 1) & 1) * L2, lane, to_x);  // along y
-    rot_contract<L>(Xw, St + (oct & 1) * L2, lane,
-                    [&](int i, double v) { out[i] += v; });  // along x, accumulated
+    rot_contract<L>(Xw, St + (oct & 1) * L2, lane, [&](int i, double v, int m, int r) {
+      gst(out + i, cur[r][m] + v);  // along x, accumulated
+    });
   }
   __syncthreads();
 }
@@ -288,7 +303,9 @@ __global__ __launch_bounds__(kTransThreads) void l2l_kernel(const JobDev* __rest
 // occupancy, so a wavefront's second half would idle otherwise); the leaf's
 // local expansion sits in LDS and each half-wavefront reads one coefficient
 // (broadcast).
-// phi = sum_m S_m(u) Loc[m];  F = -q (1/a) grad_u sum_m S_m(u) Loc[m].
+// phi = sum_m S_m(u) Loc[m];  F = -q (1/a) grad_u sum_m S_m(u) Loc[m], with
+// S_m(u) = sum_n C[m][n] T_n(u) for node values and S_m = T_m for Chebyshev
+// coefficients (C the identity).
 template <int L>
 __global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
                                                  const StepTab* __restrict__ tab) {
@@ -299,7 +316,8 @@ __global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
-    for (int e = t; e < L * L; e += 64) C[e] = J.cheb[e];
+    const bool modal = wuni(J.modal);
+    for (int e = t; e < L * L; e += 64) C[e] = modal ? (e / L == e % L ? 1.0 : 0.0) : J.cheb[e];
     const double* lsrc = J.Loc + (J.lev_off[J.height - 1] + a) * J.ld;
     for (int e = t; e < L * L * L; e += 64) Lc[e] = lsrc[e];
     double c[3];
@@ -385,30 +403,40 @@ __global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
 }
 
 // Item = leaf, one wavefront, for plans whose leaves hold few particles
-// (kL2PSparseMax): up to kL2PSparseNP particles at a time, lanes over the
-// l^3 terms of their sums.  Per particle the 1-D factors S_d(m) and their
-// derivatives (computed as in l2p_kernel) go to LDS; lane k sums the terms
-// e = k, k + 64, ... of phi and the three gradient components; the 64
-// partial sums of each are then added in lane order.
+// (kL2PSparseMax): lanes over the l^3 terms of each particle's sums.  The
+// leaf's l^3 coefficients are loaded at once into registers (one memory
+// latency per leaf); the 1-D factors S_d(m) and their derivatives of up to
+// kL2PSparseNP particles (computed as in l2p_kernel) go to LDS; then, one
+// particle at a time, lane k sums the terms e = k, k + 64, ... of phi and the
+// three gradient components, and the 64 partial sums of each are added in a
+// fixed two-level order (eight runs of eight lanes, then the eight run sums).
 constexpr int kL2PSparseNP = 8;
 
 template <int L>
-__global__ __launch_bounds__(64, 4) void l2p_sparse_kernel(const JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(64) void l2p_sparse_kernel(const JobDev* __restrict__ jobs,
                                                         const StepTab* __restrict__ tab) {
-  constexpr int L2 = L * L, L3 = L2 * L, NP = kL2PSparseNP;
+  constexpr int L2 = L * L, L3 = L2 * L, NP = kL2PSparseNP, NE = (L3 + 63) / 64;
   __shared__ double C[L2];
   __shared__ double Sd[NP][6][L];  // S_0, S_1, S_2, dS_0, dS_1, dS_2
-  __shared__ double red[4 * NP][65];
+  __shared__ double red[4][64];
+  __shared__ double red2[4][8];
   const int lane = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
-    for (int e = lane; e < L2; e += 64) C[e] = J.cheb[e];
+    const double* lsrc = J.Loc + (J.lev_off[J.height - 1] + a) * J.ld;
+    double lcv[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = lane + 64 * t;
+      lcv[t] = e < L3 ? gld(lsrc + e) : 0.0;
+    }
+    const bool modal = wuni(J.modal);
+    for (int e = lane; e < L2; e += 64) C[e] = modal ? (e / L == e % L ? 1.0 : 0.0) : J.cheb[e];
     double c[3];
     leaf_centre(J.geo, J.leaf_keys[a], c);
     const double ia = 2.0 / J.geo.w;
-    const double* lsrc = J.Loc + (J.lev_off[J.height - 1] + a) * J.ld;
     const int s0 = wuni(gld(J.leaf_start + a)), s1 = wuni(gld(J.leaf_start + a + 1));
     __syncthreads();
     for (int i0 = s0; i0 < s1; i0 += NP) {
@@ -438,48 +466,53 @@ __global__ __launch_bounds__(64, 4) void l2p_sparse_kernel(const JobDev* __restr
         Sd[j][3 + d][m] = dv;
       }
       __syncthreads();
-      double acc[NP][4];
+      for (int j = 0; j < np; ++j) {
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) acc[j][0] = acc[j][1] = acc[j][2] = acc[j][3] = 0.0;
-#pragma unroll 2
-      for (int e = lane; e < L3; e += 64) {
-        const double lc = gld(lsrc + e);
-        const int m1 = e / L2, m2 = (e / L) % L, m3 = e % L;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) {
-          if (j >= np) break;
-          const double t23 = lc * Sd[j][1][m2] * Sd[j][2][m3];
-          const double t1 = lc * Sd[j][0][m1];
-          acc[j][0] += Sd[j][0][m1] * t23;
-          acc[j][1] += Sd[j][3][m1] * t23;
-          acc[j][2] += t1 * Sd[j][4][m2] * Sd[j][2][m3];
-          acc[j][3] += t1 * Sd[j][1][m2] * Sd[j][5][m3];
+        for (int t = 0; t < NE; ++t) {
+          const int e = lane + 64 * t;
+          if (e < L3) {
+            const int m1 = e / L2, m2 = (e / L) % L, m3 = e % L;
+            const double s1 = Sd[j][0][m1], s2 = Sd[j][1][m2], s3 = Sd[j][2][m3];
+            const double t23 = lcv[t] * s2 * s3;
+            const double t1 = lcv[t] * s1;
+            p0 += s1 * t23;
+            p1 += Sd[j][3][m1] * t23;
+            p2 += t1 * Sd[j][4][m2] * s3;
+            p3 += t1 * s2 * Sd[j][5][m3];
+          }
         }
-      }
+        red[0][lane] = p0;
+        red[1][lane] = p1;
+        red[2][lane] = p2;
+        red[3][lane] = p3;
+        __syncthreads();
+        if (lane < 32) {  // (value, run of eight)
+          const int q = lane >> 3, r = lane & 7;
+          double v = 0.0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        if (j >= np) break;
+          for (int l = 0; l < 8; ++l) v += red[q][8 * r + l];
+          red2[q][r] = v;
+        }
+        __syncthreads();
+        if (lane < 4) {
+          double v = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[4 * j + q][lane] = acc[j][q];
+          for (int r = 0; r < 8; ++r) v += red2[lane][r];
+          red[lane][0] = v;
+        }
+        __syncthreads();
+        if (lane == 0) {
+          const int i = i0 + j;
+          const double fq = -J.qs[i] * ia;
+          J.phi_f[i] = red[0][0];
+          const int64_t i3 = 3 * int64_t(i);
+          J.f_f[i3] = fq * red[1][0];
+          J.f_f[i3 + 1] = fq * red[2][0];
+          J.f_f[i3 + 2] = fq * red[3][0];
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      if (lane < 4 * np) {
-        double v = 0.0;
-#pragma unroll 8
-        for (int l = 0; l < 64; ++l) v += red[lane][l];
-        red[lane][64] = v;
-      }
-      __syncthreads();
-      if (lane < np) {
-        const int i = i0 + lane;
-        const double fq = -J.qs[i] * ia;
-        J.phi_f[i] = red[4 * lane][64];
-        const int64_t i3 = 3 * int64_t(i);
-        J.f_f[i3] = fq * red[4 * lane + 1][64];
-        J.f_f[i3 + 1] = fq * red[4 * lane + 2][64];
-        J.f_f[i3 + 2] = fq * red[4 * lane + 3][64];
-      }
-      __syncthreads();
     }
   }
 }
@@ -741,61 +774,19 @@ __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ 
 // ------------------------------------------ M2L parts and coefficient rows
 // Item = row of levels >= 2 of a job whose M2L ran in parts or in FP32:
 // Loc += the partial local expansions of parts 1 .. K-1, added in part order
-// (one FP64 sum per element, the same order every run); then, where the FP32
-// M2L left Chebyshev coefficients c (J.modal), the node values
-//     Loc[m1][m2][m3] = sum_n T_n1(xb_m1) T_n2(xb_m2) T_n3(xb_m3) c[n1][n2][n3]
-// of their interpolant (Eq. 5), in FP64 as three 1-D passes (6 l^4 flops).
-// One wavefront per row.
-template <int L>
-__device__ void loc_sum_modal(const JobDev& J, int64_t r, double* lds) {
-  constexpr int L2 = L * L, L3 = L2 * L;
-  const int lane = threadIdx.x;
-  double* const A = lds;  // A[m][n] = T_n(xb_m)
-  double* const X = lds + L2;
-  const int64_t n = J.locx_rows * J.ld;
-  double* loc = J.Loc + (J.locx_first + r) * J.ld;
-  const double* x = J.LocX + r * J.ld;
-  const int parts = wuni(J.m2l_parts);
-  for (int e = lane; e < L2; e += 64) A[e] = J.tcheb[e];
-  for (int e = lane; e < L3; e += 64) {
-    double v = gld(loc + e);
-    for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
-    X[e] = v;
-  }
-  __syncthreads();
-  auto to_x = [&](int i, double v) { X[i] = v; };
-  // (the barriers between the passes also keep the compiler from holding
-  // all of A in registers across them)
-  rot_contract<L>(X, A, lane, to_x);  // along z: (n1, n2, n3) -> (m3, n1, n2)
-  __syncthreads();
-  rot_contract<L>(X, A, lane, to_x);  // along y: -> (m2, m3, n1)
-  __syncthreads();
-  rot_contract<L>(X, A, lane, [&](int i, double v) { gst(loc + i, v); });  // along x
-  for (int e = L3 + lane; e < J.ld; e += 64) gst(loc + e, 0.0);
-  __syncthreads();
-}
-
-size_t loc_sum_lds_bytes(int L) { return sizeof(double) * size_t(L * L * L + L * L); }
-
-// Item = row r of a plan of order L.
-template <int L>
-__global__ __launch_bounds__(64) void loc_sum_kernel(const JobDev* __restrict__ jobs,
-                                                     const StepTab* __restrict__ tab) {
-  extern __shared__ double dyn_lds[];
+// (one FP64 sum per element, the same order every run).  Item = row.
+__global__ __launch_bounds__(256) void loc_sum_kernel(const JobDev* __restrict__ jobs,
+                                                      const StepTab* __restrict__ tab) {
   const int t = threadIdx.x;
   FOR_ITEMS(tab) {
     const int k = step_find(*tab, it_);
     const JobDev& J = jobs[tab->job[k]];
     const int64_t r = it_ - tab->start[k];
-    if (wuni(J.modal)) {
-      loc_sum_modal<L>(J, r, dyn_lds);
-      continue;
-    }
     const int64_t n = J.locx_rows * J.ld;
     double* loc = J.Loc + (J.locx_first + r) * J.ld;
     const double* x = J.LocX + r * J.ld;
     const int parts = wuni(J.m2l_parts);
-    for (int e = t; e < J.ld; e += 64) {
+    for (int e = t; e < J.ld; e += 256) {
       double v = gld(loc + e);
       for (int p = 1; p < parts; ++p) v += gld(x + (p - 1) * n + e);
       gst(loc + e, v);
@@ -933,9 +924,7 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       cast_kernel<<<g, 256, 0, s>>>(jobs, tab);
       break;
     case kStepLocSum:
-#define LOC_SUM_CALL(LL) loc_sum_kernel<LL><<<g, 64, loc_sum_lds_bytes(LL), s>>>(jobs, tab)
-      FMM_ORDER_SWITCH(L, LOC_SUM_CALL)
-#undef LOC_SUM_CALL
+      loc_sum_kernel<<<g, 256, 0, s>>>(jobs, tab);
       break;
     case kStepM2L:
       launch_m2l_step(L, fp32, jobs, tab, grid, s);

@@ -82,7 +82,9 @@ void* pinned_staging(size_t bytes);
 struct OpSet {
   int order = 0, l3 = 0, ld = 0, mt = 0, kc = 0;
   double* cheb = nullptr;     // [l][l]: C[m][n] = (n==0 ? 1 : 2 T_n(xb_m)) / l
-  double* tcheb = nullptr;    // [l][l]: T_n(xb_m), Chebyshev coefficients -> node values
+  // [2][l][l]: R_s[n][k], the coefficient of T_n in T_k((s + x)/2), s = -1, +1:
+  // a parent's Chebyshev coefficients re-expanded on a child's interval
+  double* child_modal = nullptr;
   double* child = nullptr;    // [2][l][l]: S(xb_m; (s + xb_m')/2), s = -1, +1
   double* kpack64 = nullptr;  // [316][mt][kc][64][4] unit M2L operators, MFMA order
   float* kpack32 = nullptr;   // FP32, rows in the Chebyshev-coefficient basis (see m2l.hip)

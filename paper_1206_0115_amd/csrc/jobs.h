@@ -42,7 +42,7 @@ struct JobDev {
   int w32_leaf;  // leaf multipoles live in W32 only (W holds levels < h-1)
   int fold_every;  // compressed FP32 M2L: far offsets between FP64 folds
   // FP32 M2L (mixed modes): the local expansions of levels >= 2 leave M2L
-  // as Chebyshev coefficients and become node values in the loc-sum pass
+  // as Chebyshev coefficients, and L2L and L2P take them as such
   int modal;
   // leaves hold few particles on average: L2P spreads each particle's l^3
   // terms over a wavefront's lanes (l2p_sparse_kernel)
@@ -82,7 +82,7 @@ struct JobDev {
   const float* p2_32;
   const int* slot_kid;
   const double* cheb;
-  const double* tcheb;  // [l][l] T_n(xb_m)
+  const double* child_modal;  // [2][l][l] coefficient re-expansion (OpSet)
   const double* child;
   double* phi_n;  // near/far partial results in sorted order
   double* f_n;

@@ -269,12 +269,11 @@ const OpSet* get_opset(int l, int kernel, hipStream_t s) {
 
   double xi[kMaxOrder], Tm[kMaxOrder];
   cheb_nodes(l, xi);
-  std::vector<double> cheb(l * l), tcheb(l * l), child(2 * l * l);
+  std::vector<double> cheb(l * l), child(2 * l * l), child_modal(2 * l * l, 0.0);
   for (int m = 0; m < l; ++m) {
     cheb_T(l, xi[m], Tm);
     for (int n = 0; n < l; ++n) {
       cheb[m * l + n] = (n == 0 ? 1.0 : 2.0 * Tm[n]) / l;
-      tcheb[m * l + n] = Tm[n];
     }
   }
   // child-to-parent interpolation S(xb_m; (sigma + xb_m')/2), sigma = -1, +1
@@ -287,6 +286,16 @@ const OpSet* get_opset(int l, int kernel, hipStream_t s) {
         for (int n = 0; n < l; ++n) v += cheb[m * l + n] * Tu[n];
         child[(sg * l + m) * l + mp] = v;
       }
+    }
+  // the same re-expansion on Chebyshev coefficients: T_k((sigma + x)/2) is a
+  // polynomial of degree k < l, so its coefficients are its values at the l
+  // nodes transformed with C (exact): R[n][k] = sum_m C[m][n] T_k((sigma + xb_m)/2)
+  for (int sg = 0; sg < 2; ++sg)
+    for (int m = 0; m < l; ++m) {
+      double Tu[kMaxOrder];
+      cheb_T(l, ((sg ? 1.0 : -1.0) + xi[m]) / 2.0, Tu);
+      for (int n = 0; n < l; ++n)
+        for (int k = 0; k < l; ++k) child_modal[(sg * l + n) * l + k] += cheb[m * l + n] * Tu[k];
     }
 
   std::vector<int> tc(3 * 16), info(7 * kOffsets);
@@ -310,7 +319,8 @@ const OpSet* get_opset(int l, int kernel, hipStream_t s) {
   };
   try {
     op->cheb = static_cast<double*>(up(cheb.data(), sizeof(double) * cheb.size(), true));
-    op->tcheb = static_cast<double*>(up(tcheb.data(), sizeof(double) * tcheb.size(), true));
+    op->child_modal =
+        static_cast<double*>(up(child_modal.data(), sizeof(double) * child_modal.size(), true));
     op->child = static_cast<double*>(up(child.data(), sizeof(double) * child.size(), true));
     op->slot_kid = static_cast<int*>(up(T.slot_kid.data(), sizeof(int) * T.slot_kid.size(), true));
     op->slot_t = static_cast<signed char*>(up(T.slot_t.data(), T.slot_t.size(), true));

@@ -32,9 +32,8 @@
 namespace fmm {
 namespace {
 
-// Launches per batch: up to 48 per order present (two per tree level for
-// M2M and L2L, eight M2L forms, P2M, two L2P forms, the coefficient rows)
-// and five more.
+// Launches per batch: up to 47 per order present (two per tree level for
+// M2M and L2L, eight M2L forms, P2M, two L2P forms) and six more.
 constexpr int kMaxSteps = 640;
 constexpr int kBuffers = 2;
 // Batching window: admitted requests wait for the planner to finish the
@@ -371,8 +370,8 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
   for (int L : orders)
     add(kStepP2M, L, false, [&](Request* r) { return far(r) && r->order == L; },
         [](Request* r) { return int(r->plan->nleaf); }, lvl0);
-  // M2M, L2L and the coefficient rows are compiled per order: one launch per
-  // order present at each level
+  // M2M and L2L are compiled per order: one launch per order present at
+  // each level
   for (int s = 0; s < steps; ++s)
     for (int L : orders)
       add(kStepM2M, L, false, [&](Request* r) { return r->h - 4 >= s && r->order == L; },
@@ -397,13 +396,8 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
             lvl0);
   // partial sums of plans that split their compressed M2L back into Loc, and
   // the FP32 M2L's Chebyshev-coefficient rows back to node values
-  for (int L : orders)
-    add(kStepLocSum, L, false,
-        [&](Request* r) {
-          return far(r) && r->order == L &&
-                 (r->plan->job_h.m2l_parts > 1 || r->plan->job_h.modal);
-        },
-        [](Request* r) { return int(r->plan->job_h.locx_rows); }, lvl0);
+  add(kStepLocSum, 0, false, [&](Request* r) { return far(r) && r->plan->job_h.m2l_parts > 1; },
+      [](Request* r) { return int(r->plan->job_h.locx_rows); }, lvl0);
   for (int s = 0; s < steps; ++s)
     for (int L : orders)
       add(kStepL2L, L, false, [&](Request* r) { return r->h - 4 >= s && r->order == L; },

@@ -85,6 +85,26 @@ def test_mixed_compressed_full_size_gate(name, mixed_bound):
     assert 0 < inf.m2l_flops < 2.0 * l ** 6 * inf.far_pairs / 3
 
 
+def test_twin_at_the_workload_tolerance():
+    """The 30M-particle workload runs its compressed M2L at a tolerance above
+    the default (chosen on its twin by the gate): there both compressed
+    modes stay within half the 1e-6 gate of the dense FP64 path."""
+    name = "cube469k_h7_p10"
+    kind, n, h, l, seed = inputs.CONFIGS[name]
+    eps = inputs.SVD_TOL[name]
+    print(f"twin at eps {eps:g}", flush=True)
+    pos, q = inputs.make(kind, n, seed)
+    plan = fmm.Plan(dev(pos), h, l, "fp64", m2l_tolerance=eps)
+    p64, f64 = [host(t) for t in plan.evaluate(dev(q))]
+    for mode in ("fp64_svd", "mixed_svd"):
+        plan.set_precision(mode)
+        assert plan.svd_info().eps == pytest.approx(eps)
+        phi, f = [host(t) for t in plan.evaluate(dev(q))]
+        e = max(rel(phi, p64), rel(f, f64))
+        print(f"  {mode} vs fp64 {e:.2e}", flush=True)
+        assert e <= 5e-7
+
+
 def test_compressed_deterministic():
     pos, q = inputs.sphere_surface(30000, 43)
     plan = fmm.Plan(dev(pos), 6, 5, "mixed_svd")

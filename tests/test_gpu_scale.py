@@ -26,9 +26,9 @@ def rel(a, b):
 
 
 # The FMM's own error against exact sums at the 30M workload's density and
-# order (the order-10 interpolation, with the SVD truncation at 1e-7),
-# measured on its 469k-particle twin; the mixed mode adds at most the 5e-7
-# the twin's gate tests allow.
+# order (the order-10 interpolation, with the SVD truncation at the
+# workload's tolerance), measured on its 469k-particle twin; the mixed mode
+# adds at most the 5e-7 the twin's gate tests allow.
 TWIN_FP64_VS_EXACT = 8e-6
 
 
@@ -38,7 +38,8 @@ def test_twin_fmm_error_against_exact_sums():
     pos, q = inputs.make(kind, n, seed)
     idx = np.sort(np.random.default_rng(11).choice(n, 256, replace=False))
     pd, fd = oracle.direct_sampled(pos, q, idx)
-    plan = fmm.Plan(torch.from_numpy(pos).cuda(), h, l, "fp64", m2l_tolerance=1e-7)
+    plan = fmm.Plan(torch.from_numpy(pos).cuda(), h, l, "fp64",
+                    m2l_tolerance=inputs.SVD_TOL["cube469k_h7_p10"])
     errs = {}
     for mode in ("fp64", "fp64_svd", "mixed_svd"):
         plan.set_precision(mode)
@@ -58,7 +59,7 @@ def test_cube30m_order10_mixed_compressed():
     pos, q = inputs.make(kind, n, seed)
     pos_d, q_d = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
     t0 = time.perf_counter()
-    plan = fmm.Plan(pos_d, h, l, "mixed_svd", m2l_tolerance=1e-7)
+    plan = fmm.Plan(pos_d, h, l, "mixed_svd", m2l_tolerance=inputs.SVD_TOL["cube30m_h9_p10"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     inf = plan.info()
