@@ -204,12 +204,22 @@ __device__ void m2m_item(const JobDev& J, int lv, int p, double* lds) {
   if (w < nc) {
     oct = wuni(int(gld(J.keys[lv + 1] + c0 + w) & 7u));
     const int64_t crow = (J.lev_off[lv + 1] + c0 + w) * int64_t(ld);
-    // leaf children of the mixed modes are stored in FP32; the contraction
-    // is FP64
-    if (J.w32_leaf && lv + 1 == J.height - 1)
-      for (int e = lane; e < L3; e += 64) Xw[e] = double(gld(J.W32 + crow + e));
-    else
-      for (int e = lane; e < L3; e += 64) Xw[e] = gld(J.W + crow + e);
+    // all of the child's loads in flight at once (a loop bounded at run time
+    // waits for each before issuing the next); leaf children of the mixed
+    // modes are stored in FP32, the contraction is FP64
+    constexpr int NE = (L3 + 63) / 64;
+    double v[NE];
+    if (J.w32_leaf && lv + 1 == J.height - 1) {
+#pragma unroll
+      for (int k = 0; k < NE; ++k)
+        v[k] = lane + 64 * k < L3 ? double(gld(J.W32 + crow + lane + 64 * k)) : 0.0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < NE; ++k) v[k] = lane + 64 * k < L3 ? gld(J.W + crow + lane + 64 * k) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (lane + 64 * k < L3) Xw[lane + 64 * k] = v[k];
   }
   __syncthreads();
   if (w < nc) {
@@ -260,7 +270,15 @@ __device__ void l2l_item(const JobDev& J, int lv, int p, double* lds) {
     St[e] = modal ? J.child_modal[e] : J.child[s * L2 + q * L + m];
   }
   const double* lp = J.Loc + (J.lev_off[lv - 1] + p) * int64_t(ld);
-  for (int e = t; e < L3; e += kTransThreads) P[e] = lp[e];
+  {
+    constexpr int NE = (L3 + kTransThreads - 1) / kTransThreads;
+    double v[NE];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) v[k] = t + kTransThreads * k < L3 ? gld(lp + t + kTransThreads * k) : 0.0;
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (t + kTransThreads * k < L3) P[t + kTransThreads * k] = v[k];
+  }
   const int c0 = J.child_start[lv - 1][p], nc = J.child_start[lv - 1][p + 1] - c0;
   __syncthreads();
   if (w < nc) {
@@ -319,7 +337,15 @@ __global__ FMM_L2P_BOUNDS void l2p_kernel(const JobDev* __restrict__ jobs,
     const bool modal = wuni(J.modal);
     for (int e = t; e < L * L; e += 64) C[e] = modal ? (e / L == e % L ? 1.0 : 0.0) : J.cheb[e];
     const double* lsrc = J.Loc + (J.lev_off[J.height - 1] + a) * J.ld;
-    for (int e = t; e < L * L * L; e += 64) Lc[e] = lsrc[e];
+    {  // all loads in flight at once
+      constexpr int NE = (L * L * L + 63) / 64;
+      double v[NE];
+#pragma unroll
+      for (int k = 0; k < NE; ++k) v[k] = t + 64 * k < L * L * L ? gld(lsrc + t + 64 * k) : 0.0;
+#pragma unroll
+      for (int k = 0; k < NE; ++k)
+        if (t + 64 * k < L * L * L) Lc[t + 64 * k] = v[k];
+    }
     double c[3];
     leaf_centre(J.geo, J.leaf_keys[a], c);
     const double ia = 2.0 / J.geo.w;
