@@ -449,6 +449,34 @@ class Bench:
         return {name: float(np.mean([e[2 * k].elapsed_time(e[2 * k + 1]) for e in ev]))
                 for k, name in enumerate(names)}
 
+    def near_forms(self, prec, reps):
+        """The near field's two forms (one-sided; mutual, Sec. 5's reduction
+        form) on this workload and mode: the average time of the near-field
+        launches (serial schedule, HIP events around them), and the mutual
+        form's output against the one-sided one's."""
+        torch, fmm, s = self.torch, self.fmm, self.stream
+        out, res = {}, {}
+        with torch.cuda.stream(s):
+            p = self.plan(prec)
+            p.set_schedule("serial")
+            for near in ("one_sided", "mutual"):
+                p.set_near(near)
+                p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+                ev = [self.new_events(2) for _ in range(reps)]
+                s.synchronize()
+                for e in ev:
+                    fmm.set_step_timing_events("p2p", e[0], e[1])
+                    p.evaluate(self.q_d, self.phi, self.frc, stream=s)
+                s.synchronize()
+                fmm.set_step_timing_events("p2p", None, None)
+                res[near] = (self.phi.cpu().numpy(), self.frc.cpu().numpy())
+                out[near + "_ms"] = round(float(np.mean([e[0].elapsed_time(e[1]) for e in ev])), 4)
+            p.release()
+        out["mutual_speedup"] = round(out["one_sided_ms"] / out["mutual_ms"], 3)
+        out["mutual_vs_one_sided_rel_l2"] = max(rel(res["mutual"][0], res["one_sided"][0]),
+                                                rel(res["mutual"][1], res["one_sided"][1]))
+        return out
+
     def exact_error(self, count):
         """Error of the last evaluation's output against exact sums (GPU
         direct summation over all sources) at `count` seeded targets."""
@@ -555,7 +583,8 @@ def side_config(name, stream, steps):
            "rel_l2_vs_fp64": modes[prec]["rel_l2_vs_fp64"],
            "rel_l2_vs_exact": b.exact_error(N_EXACT), "modes": modes,
            "kernels": b.kernels(prec, 5),
-           "eval_only_ms_by_schedule": b.schedule_times(prec, max(5, steps))}
+           "eval_only_ms_by_schedule": b.schedule_times(prec, max(5, steps)),
+           "near_field_forms": b.near_forms(prec, 5)}
     if name == "cube1m_h6_p7":
         out["second_kernel"] = b.second_kernel(prec, max(5, steps // 2))
     b.release()

@@ -51,12 +51,13 @@ enum fmm_status {
 enum fmm_precision {
   /* every operator in FP64 (FP64 MFMA for M2L) */
   FMM_FP64 = 0,
-  /* P2P in FP32 (pair differences rounded once from FP64) with
-   * per-source-leaf FP64 folding; M2L as FP32 MFMA contractions whose
-   * operators produce Chebyshev coefficients of the local expansions,
-   * accumulated in FP32 and folded into FP64 per far offset, then turned
-   * into node values in FP64; P2M, M2M, L2L, L2P and the output sums stay
-   * FP64 */
+  /* P2P in FP32 (pair differences rounded once from FP64) with FP64
+   * folding per source chunk (at most 64 particles); M2L as FP32 MFMA
+   * contractions whose operators produce Chebyshev coefficients of the
+   * local expansions, accumulated in FP32 and folded into FP64 after every
+   * far offset; L2L and L2P take the coefficients in FP64.  P2M, M2M, L2L,
+   * L2P and the output sums compute in FP64 (M2L reads FP32 copies of the
+   * multipoles) */
   FMM_MIXED_FP32 = 1,
   /* Reserved for M2L as BF16 MFMA products with FP32 accumulation.  Not
    * built: BF16 keeps 8 significant bits, so even a two-term (hi + lo)
@@ -233,6 +234,29 @@ int fmm_plan_set_graph(fmm_plan_t plan, int on);
 enum fmm_kernel { FMM_KERNEL_INV_R = 1, FMM_KERNEL_INV_R2 = 2 };
 int fmm_plan_set_kernel(fmm_plan_t plan, int kernel);
 
+/* Near-field form of later evaluations (P2P, Sec. 5).
+ *   FMM_NEAR_ONE_SIDED  (default) each target leaf sums over the particles of
+ *                       its up to 27 neighbour leaves (itself included), so
+ *                       every pair of particles in distinct leaves is
+ *                       computed twice, once from each side
+ *   FMM_NEAR_MUTUAL     the reduction form of Sec. 5 (P2Preduce): each pair of
+ *                       distinct neighbour leaves is computed once and its
+ *                       terms are added to both leaves' sums; pairs within a
+ *                       leaf stay one-sided.  The pairs go in 26 launches
+ *                       (13 forward offsets, each in two colours), each of
+ *                       which touches every leaf at most once, so the sums
+ *                       are taken in a fixed order without atomics: results
+ *                       are deterministic, and equal to the one-sided form's
+ *                       up to the order of summation.
+ * The first switch to FMM_NEAR_MUTUAL builds the plan's pair lists (at most
+ * 13 ints per leaf, owned by the plan; the build synchronises the plan's
+ * stream and waits for its in-flight evaluation).  The near-field timing hook
+ * brackets all of the form's launches.  Returns FMM_ERR_ARG for a null plan
+ * or an unknown mode, FMM_ERR_OOM if the lists do not fit.  The serving calls
+ * use the one-sided form. */
+enum fmm_near { FMM_NEAR_ONE_SIDED = 0, FMM_NEAR_MUTUAL = 1 };
+int fmm_plan_set_near(fmm_plan_t plan, int mode);
+
 /* Plan facts (host struct). */
 struct fmm_info {
   int64_t n;
@@ -264,6 +288,16 @@ int fmm_plan_info(fmm_plan_t plan, struct fmm_info* out);
  *   FMM_EXPORT_FAR_OFF     int64  [ncell[level]+1] far lists (level >= 2) as
  *   FMM_EXPORT_FAR_IDX     int64  [far_off[ncell]]  CSR of level-local indices,
  *                                                   ascending
+ *   FMM_EXPORT_MUTUAL_OFF  int64  [27]      bounds of the mutual near field's
+ *                                           26 pair lists: list 2k + c holds
+ *                                           the leaves a whose neighbour at
+ *                                           near slot 14 + k exists and whose
+ *                                           colour is c (fmm_plan_set_near)
+ *   FMM_EXPORT_MUTUAL_IDX  int64  [mutual_off[26]]  the lists' leaves
+ *                                           (ascending within a list); both
+ *                                           need the lists built (FMM_ERR_ARG
+ *                                           before the first switch to
+ *                                           FMM_NEAR_MUTUAL)
  * `bytes` must be at least the size of the array; returns FMM_ERR_ARG
  * otherwise.  Synchronous.
  */
@@ -275,7 +309,9 @@ enum fmm_export {
   FMM_EXPORT_NEAR_OFF = 4,
   FMM_EXPORT_NEAR_IDX = 5,
   FMM_EXPORT_FAR_OFF = 6,
-  FMM_EXPORT_FAR_IDX = 7
+  FMM_EXPORT_FAR_IDX = 7,
+  FMM_EXPORT_MUTUAL_OFF = 8,
+  FMM_EXPORT_MUTUAL_IDX = 9
 };
 int fmm_plan_export(fmm_plan_t plan, int what, int level, void* host_dst,
                     size_t bytes);

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libfmm.so")
 
-SOURCES = ["api.cpp", "alloc.cpp", "plan.hip", "m2l.hip", "eval.hip", "serve.cpp", "direct.hip",
+SOURCES = ["api.cpp", "alloc.cpp", "plan.hip", "m2l.hip", "eval.hip", "p2p_mutual.hip", "serve.cpp", "direct.hip",
            "direct_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

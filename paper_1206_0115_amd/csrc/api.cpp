@@ -449,6 +449,20 @@ int fmm_plan_set_schedule(fmm_plan_t p, int schedule) {
   });
 }
 
+int fmm_plan_set_near(fmm_plan_t p, int mode) {
+  if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
+  if (mode != FMM_NEAR_ONE_SIDED && mode != FMM_NEAR_MUTUAL)
+    return fail(FMM_ERR_ARG, "unknown near-field mode " + std::to_string(mode));
+  return guarded([&]() -> int {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->in_flight) FMM_HIP_CHECK(hipEventSynchronize(p->done));
+    if (mode == FMM_NEAR_MUTUAL && !p->mutual_list) fmm::build_mutual_lists(p, p->last_stream);
+    if (mode != p->near_mode) fmm::release_graph(p);
+    p->near_mode = mode;
+    return FMM_OK;
+  });
+}
+
 int fmm_plan_set_kernel(fmm_plan_t p, int kernel) {
   if (!p) return fail(FMM_ERR_ARG, "plan is NULL");
   if (kernel != FMM_KERNEL_INV_R && kernel != FMM_KERNEL_INV_R2)
@@ -706,6 +720,25 @@ int fmm_plan_export(fmm_plan_t p, int what, int level, void* dst, size_t bytes) 
         const std::vector<int64_t>& v = what == FMM_EXPORT_FAR_OFF ? off : idx;
         if (!need(sizeof(int64_t) * v.size())) return fail(FMM_ERR_ARG, "buffer too small");
         std::memcpy(dst, v.data(), sizeof(int64_t) * v.size());
+        return FMM_OK;
+      }
+      case FMM_EXPORT_MUTUAL_OFF:
+      case FMM_EXPORT_MUTUAL_IDX: {
+        if (!p->mutual_list) return fail(FMM_ERR_ARG, "the mutual pair lists are not built");
+        constexpr int kLists = 2 * fmm::kMutualSlots;
+        const int64_t total = p->mutual_off[kLists];
+        if (what == FMM_EXPORT_MUTUAL_OFF) {
+          if (!need(sizeof(int64_t) * (kLists + 1))) return fail(FMM_ERR_ARG, "buffer too small");
+          std::memcpy(dst, p->mutual_off, sizeof(int64_t) * (kLists + 1));
+          return FMM_OK;
+        }
+        if (!need(sizeof(int64_t) * total)) return fail(FMM_ERR_ARG, "buffer too small");
+        std::vector<int> v(total);
+        if (total > 0)
+          FMM_HIP_CHECK(hipMemcpy(v.data(), p->mutual_list, sizeof(int) * total,
+                                  hipMemcpyDeviceToHost));
+        int64_t* o = static_cast<int64_t*>(dst);
+        for (int64_t i = 0; i < total; ++i) o[i] = v[i];
         return FMM_OK;
       }
       default:

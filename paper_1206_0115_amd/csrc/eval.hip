@@ -621,8 +621,9 @@ __device__ __forceinline__ bool near_next(int nj0, int nj1, int& sl, int& jb, in
 // the pair difference is taken in FP64 and rounded once (a relative error of
 // 2^-24 of the distance itself, however close the pair), r^2, the reciprocal
 // (square) root and the products are FP32, and the partial sums over one
-// source leaf are kept in FP32 and folded into FP64 accumulators.  Pairs are
-// taken in the same order as one leaf, one chunk at a time.
+// source chunk (at most 64 particles, so their rounding does not grow with
+// the leaves' occupancy) are kept in FP32 and folded into FP64 accumulators.
+// Pairs are taken in the same order as one leaf, one chunk at a time.
 typedef double src4 __attribute__((ext_vector_type(4)));  // x, y, z, q of one source
 
 // FP32 charges travel in the q slot as their own bits (low word), so the
@@ -671,7 +672,9 @@ __device__ __forceinline__ void p2p_passes_f64(const src4* src, int split, int S
   }
 }
 
-template <int KP, bool F32>
+// SELF: only the leaf's own particles (the within-leaf part of the mutual
+// near field, whose pairs of distinct leaves go through p2p_mutual.hip).
+template <int KP, bool F32, bool SELF>
 __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
   const int lane = threadIdx.x;
   const double *px = J.px, *py = J.py, *pz = J.pz;
@@ -680,7 +683,7 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
   const int S = 64 / P;
   const int split = lane / P;
   int nj0 = 0, nj1 = 0;
-  if (lane < 27) {
+  if (SELF ? lane == kSelfSlot : lane < 27) {
     const int b = gld(J.near + 27 * a + lane);
     if (b >= 0) {
       nj0 = gld(J.leaf_start + b);
@@ -730,13 +733,11 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
           p2p_passes_f32<KP, true>(src, split, S, npass, xi, yi, zi, p32, x32, y32, z32);
         else
           p2p_passes_f32<KP, false>(src, split, S, npass, xi, yi, zi, p32, x32, y32, z32);
-        if (!have || sl != csl) {  // the source leaf ends here
-          ph += double(p32);
-          fx += double(x32);
-          fy += double(y32);
-          fz += double(z32);
-          p32 = x32 = y32 = z32 = 0.f;
-        }
+        ph += double(p32);
+        fx += double(x32);
+        fy += double(y32);
+        fz += double(z32);
+        p32 = x32 = y32 = z32 = 0.f;
       } else if (csl == kSelfSlot) {
         p2p_passes_f64<KP, true>(src, split, S, npass, xi, yi, zi, ph, fx, fy, fz);
       } else {
@@ -761,6 +762,7 @@ __device__ __forceinline__ void p2p_leaf(const JobDev& J, int a, src4* src) {
   }
 }
 
+template <bool SELF>
 __global__ __launch_bounds__(64) void p2p_f64_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
   __shared__ src4 src[kSrcSlots];
@@ -772,13 +774,14 @@ __global__ __launch_bounds__(64) void p2p_f64_kernel(const JobDev* __restrict__ 
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
     if (J.kernel == 2)
-      p2p_leaf<2, false>(J, a, src);
+      p2p_leaf<2, false, SELF>(J, a, src);
     else
-      p2p_leaf<1, false>(J, a, src);
+      p2p_leaf<1, false, SELF>(J, a, src);
     __syncthreads();
   }
 }
 
+template <bool SELF>
 __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ jobs,
                                                      const StepTab* __restrict__ tab) {
   __shared__ src4 src[kSrcSlots];
@@ -790,9 +793,9 @@ __global__ __launch_bounds__(64) void p2p_f32_kernel(const JobDev* __restrict__ 
     const JobDev& J = jobs[tab->job[k]];
     const int a = it_ - tab->start[k];
     if (J.kernel == 2)
-      p2p_leaf<2, true>(J, a, src);
+      p2p_leaf<2, true, SELF>(J, a, src);
     else
-      p2p_leaf<1, true>(J, a, src);
+      p2p_leaf<1, true, SELF>(J, a, src);
     __syncthreads();
   }
 }
@@ -974,8 +977,12 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
 #undef L2P_CALL
       break;
     case kStepP2P:
-      if (fp32) p2p_f32_kernel<<<g, 64, 0, s>>>(jobs, tab);
-      else p2p_f64_kernel<<<g, 64, 0, s>>>(jobs, tab);
+      if (fp32) p2p_f32_kernel<false><<<g, 64, 0, s>>>(jobs, tab);
+      else p2p_f64_kernel<false><<<g, 64, 0, s>>>(jobs, tab);
+      break;
+    case kStepP2PSelf:
+      if (fp32) p2p_f32_kernel<true><<<g, 64, 0, s>>>(jobs, tab);
+      else p2p_f64_kernel<true><<<g, 64, 0, s>>>(jobs, tab);
       break;
     case kStepCombine:
       combine_kernel<<<g, kChunk, 0, s>>>(jobs, tab, calls);
@@ -1026,13 +1033,21 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   // the pipelined schedule forks the near field like the forked one
   const bool pipelined = p->schedule == FMM_SCHEDULE_PIPELINED;
   const bool forked = p->schedule == FMM_SCHEDULE_FORKED || pipelined;
+  // the near field: one-sided, or the leaves' own pairs and then the mutual
+  // pair lists of distinct neighbour leaves (Sec. 5)
+  auto near_field = [&](hipStream_t st) {
+    Timed t(FMM_TIME_P2P, st);
+    if (p->near_mode == FMM_NEAR_MUTUAL) {
+      launch_step(kStepP2PSelf, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), st);
+      launch_p2p_mutual(p, mixed, st);
+    } else {
+      launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), st);
+    }
+  };
   auto fork_near = [&]() {
     FMM_HIP_CHECK(hipEventRecord(p->ev_fork, s));
     FMM_HIP_CHECK(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    {
-      Timed t(FMM_TIME_P2P, p->side);
-      launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), p->side);
-    }
+    near_field(p->side);
     FMM_HIP_CHECK(hipEventRecord(p->ev_join, p->side));
   };
   if (forked && h < 3) fork_near();
@@ -1108,8 +1123,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   if (forked) {
     FMM_HIP_CHECK(hipStreamWaitEvent(s, p->ev_join, 0));
   } else {
-    Timed t(FMM_TIME_P2P, s);
-    launch_step(kStepP2P, L, mixed, J, p->tab_d + kTabLeaf, nullptr, int(p->nleaf), s);
+    near_field(s);
   }
   CallDev c{q, phi, f, phi_n, f_n, phi_f, f_f};
   combine1_kernel<<<chunks, kChunk, 0, s>>>(J, c);

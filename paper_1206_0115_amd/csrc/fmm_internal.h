@@ -177,6 +177,12 @@ int m2l_svd_xs(int rmax_pad, bool fp32);  // the slab stride for a padded rank
 
 }  // namespace fmm
 
+namespace fmm {
+// mutual near field: the forward near-list slots 14..26 (plan.hip)
+constexpr int kMutualSlots = 13;
+constexpr int kMutualFirstSlot = 14;
+}  // namespace fmm
+
 struct fmm_plan_s {
   int device = 0;
   int64_t n = 0;
@@ -234,6 +240,9 @@ struct fmm_plan_s {
   bool w32_leaf = false;           // mixed modes: leaf multipoles only in W32
   int m2l_fold = 0;                // compressed FP32 fold interval (0: by order)
   int m2l_split = 0;               // compressed M2L offset ranges per tile (0: auto)
+  int near_mode = FMM_NEAR_ONE_SIDED;  // fmm_plan_set_near
+  int* mutual_list = nullptr;      // leaves of the mutual pair lists (built on first use)
+  int64_t mutual_off[2 * fmm::kMutualSlots + 1] = {0};  // list (slot 14 + k, colour c) at 2k + c
   int m2l_parts = 1;               // the split in use
   double* LocX = nullptr;          // partial local expansions of parts 1..
   size_t locx_bytes = 0;
@@ -276,6 +285,10 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f,
 // first use, and again after the job or the schedule changed).
 void evaluate_graph(fmm_plan_s* p, const double* q, double* phi, double* f,
                     hipStream_t stream);
+// the mutual near field's pair lists of the plan (plan.hip); synchronises s
+void build_mutual_lists(fmm_plan_s* p, hipStream_t s);
+// the 26 pair-list launches of the mutual near field (p2p_mutual.hip)
+void launch_p2p_mutual(const fmm_plan_s* p, bool fp32, hipStream_t s);
 // whether any step timing hook is set on the calling thread
 bool timing_hooks_set();
 void release_graph(fmm_plan_s* p);

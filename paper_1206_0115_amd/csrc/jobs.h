@@ -128,7 +128,8 @@ __device__ inline int step_find(const StepTab& t, int item) {
 // kStepM2LSvd is the compressed M2L; `xs` is then the LDS row stride (the
 // largest padded rank of the launch's jobs + 4).
 enum StepKind { kStepGather, kStepP2M, kStepM2M, kStepCast, kStepM2L, kStepL2L, kStepL2P,
-                kStepP2P, kStepCombine, kStepM2LSvd, kStepLocSum, kStepL2PSparse };
+                kStepP2P, kStepCombine, kStepM2LSvd, kStepLocSum, kStepL2PSparse,
+                kStepP2PSelf };
 void launch_step(StepKind kind, int order, bool fp32, const JobDev* jobs, const StepTab* tab,
                  const CallDev* calls, int grid, hipStream_t s, int xs = 0);
 

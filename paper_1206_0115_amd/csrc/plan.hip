@@ -852,6 +852,94 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   p->stats_stage = hc;
 }
 
+// ------------------------------------------------------ mutual pair lists
+// The mutual near field (Sec. 5, P2Preduce) visits every pair of distinct
+// neighbour leaves once, as (a, near[a][s]) for the forward slots
+// s = 14..26 (the offsets after the leaf itself in slot order; slot 26 - s
+// is the opposite offset).  Launch (s, c) takes the leaves a of colour c:
+// the parity of a's grid coordinate along the first non-zero axis of the
+// offset.  Along that axis a and its neighbour differ by one, so their
+// parities differ, and no leaf is a's side of one pair and the neighbour's
+// side of another in the same launch: the launch's pairs touch disjoint
+// leaves.  Flag (2k + c) * nl + a marks leaf a in list (14 + k, c).
+__global__ void mutual_flags_kernel(const uint64_t* __restrict__ leaf_keys, int bits,
+                                    const int* __restrict__ near, int64_t nl,
+                                    int* __restrict__ flags) {
+  const int64_t a = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (a >= nl) return;
+  int c[3];
+  demorton3(leaf_keys[a], bits, c);
+  for (int k = 0; k < kMutualSlots; ++k) {
+    const int s = kMutualFirstSlot + k;
+    const int dx = s / 9 - 1, dy = (s / 3) % 3 - 1;
+    const int colour = c[dx != 0 ? 0 : dy != 0 ? 1 : 2] & 1;
+    const bool has = near[27 * a + s] >= 0;
+    flags[(2 * k) * nl + a] = has && colour == 0;
+    flags[(2 * k + 1) * nl + a] = has && colour == 1;
+  }
+}
+
+// list[scan[i]] = leaf of flag i, for the set flags; then the list bounds
+__global__ void mutual_emit_kernel(const int* __restrict__ flags, const int64_t* __restrict__ scan,
+                                   int64_t nl, int* __restrict__ list) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= 2 * kMutualSlots * nl) return;
+  if (flags[i]) list[scan[i]] = int(i % nl);
+}
+
+__global__ void mutual_bounds_kernel(const int* __restrict__ flags,
+                                     const int64_t* __restrict__ scan, int64_t nl,
+                                     int64_t* __restrict__ off) {
+  const int k = threadIdx.x;
+  const int64_t m = 2 * kMutualSlots * nl;
+  if (k < 2 * kMutualSlots) off[k] = scan[k * nl];
+  if (k == 2 * kMutualSlots) off[k] = scan[m - 1] + flags[m - 1];
+}
+
+__global__ void int_to_i64_kernel(const int* __restrict__ in, int64_t* __restrict__ out,
+                                  int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+void build_mutual_lists(fmm_plan_s* p, hipStream_t s) {
+  const int64_t nl = p->nleaf, m = 2 * kMutualSlots * nl;
+  std::vector<void*> tmp;
+  struct TmpGuard {
+    std::vector<void*>& v;
+    hipStream_t s;
+    ~TmpGuard() {
+      (void)hipStreamSynchronize(s);
+      for (void* q : v) dev_free(q);
+    }
+  } guard{tmp, s};
+  auto talloc = [&](size_t b) {
+    void* q = dev_alloc(b);
+    tmp.push_back(q);
+    return q;
+  };
+  int* flags = static_cast<int*>(talloc(sizeof(int) * m));
+  int64_t* scan = static_cast<int64_t*>(talloc(sizeof(int64_t) * m));
+  int64_t* off_d = static_cast<int64_t*>(talloc(sizeof(int64_t) * (2 * kMutualSlots + 1)));
+  mutual_flags_kernel<<<grid_for(nl, 256), 256, 0, s>>>(p->lev[p->height - 1].keys,
+                                                        p->height - 1, p->near, nl, flags);
+  FMM_HIP_CHECK(hipGetLastError());
+  int_to_i64_kernel<<<grid_for(m, 256), 256, 0, s>>>(flags, scan, m);
+  FMM_HIP_CHECK(hipGetLastError());
+  exclusive_scan<int64_t>(scan, scan, m, s, tmp);
+  mutual_bounds_kernel<<<1, 64, 0, s>>>(flags, scan, nl, off_d);
+  FMM_HIP_CHECK(hipGetLastError());
+  int64_t off[2 * kMutualSlots + 1];
+  FMM_HIP_CHECK(hipMemcpyAsync(off, off_d, sizeof(off), hipMemcpyDeviceToHost, s));
+  FMM_HIP_CHECK(hipStreamSynchronize(s));
+  const int64_t total = off[2 * kMutualSlots];
+  int* list = static_cast<int*>(p->alloc(sizeof(int) * std::max<int64_t>(total, 1)));
+  mutual_emit_kernel<<<grid_for(m, 256), 256, 0, s>>>(flags, scan, nl, list);
+  FMM_HIP_CHECK(hipGetLastError());
+  p->mutual_list = list;
+  for (int k = 0; k <= 2 * kMutualSlots; ++k) p->mutual_off[k] = off[k];
+}
+
 void plan_stats(fmm_plan_s* p) {
   const unsigned long long* hc = p->stats_stage;
   if (!hc) return;

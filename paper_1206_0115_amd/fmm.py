@@ -25,9 +25,12 @@ SCHEDULES = {"serial": FMM_SCHEDULE_SERIAL, "forked": FMM_SCHEDULE_FORKED,
              "pipelined": FMM_SCHEDULE_PIPELINED}
 FMM_KERNEL_INV_R, FMM_KERNEL_INV_R2 = 1, 2
 KERNELS = {"inv_r": FMM_KERNEL_INV_R, "inv_r2": FMM_KERNEL_INV_R2}
+FMM_NEAR_ONE_SIDED, FMM_NEAR_MUTUAL = 0, 1
+NEAR_MODES = {"one_sided": FMM_NEAR_ONE_SIDED, "mutual": FMM_NEAR_MUTUAL}
 
 EXPORT_KEYS, EXPORT_PERM, EXPORT_LEAF_START, EXPORT_CELL_KEYS = 0, 1, 2, 3
 EXPORT_NEAR_OFF, EXPORT_NEAR_IDX, EXPORT_FAR_OFF, EXPORT_FAR_IDX = 4, 5, 6, 7
+EXPORT_MUTUAL_OFF, EXPORT_MUTUAL_IDX = 8, 9
 
 
 class FMMError(RuntimeError):
@@ -104,6 +107,7 @@ def lib():
     L.fmm_plan_set_schedule.argtypes = [vp, i32]
     L.fmm_plan_set_graph.argtypes = [vp, i32]
     L.fmm_plan_set_kernel.argtypes = [vp, i32]
+    L.fmm_plan_set_near.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_tolerance.argtypes = [vp, ctypes.c_double]
     L.fmm_plan_set_m2l_fold_interval.argtypes = [vp, i32]
     L.fmm_plan_set_m2l_split.argtypes = [vp, i32]
@@ -204,6 +208,12 @@ class Plan:
         """Replay evaluations from a captured hipGraph (``fmm_plan_set_graph``)."""
         _check(lib().fmm_plan_set_graph(self._h, 1 if on else 0))
 
+    def set_near(self, mode):
+        """"one_sided" (the default) or "mutual" (each pair of distinct
+        neighbour leaves computed once, ``fmm_plan_set_near``)."""
+        code = NEAR_MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(lib().fmm_plan_set_near(self._h, code))
+
     def set_kernel(self, kernel):
         """"inv_r" (1/r, the default) or "inv_r2" (1/r^2)."""
         code = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
@@ -283,6 +293,11 @@ class Plan:
         elif what == EXPORT_FAR_IDX:
             off = self.export(EXPORT_FAR_OFF, level)
             out = np.empty(int(off[-1]), dtype=np.int64)
+        elif what == EXPORT_MUTUAL_OFF:
+            out = np.empty(27, dtype=np.int64)
+        elif what == EXPORT_MUTUAL_IDX:
+            off = self.export(EXPORT_MUTUAL_OFF)
+            out = np.empty(max(int(off[-1]), 1), dtype=np.int64)[:int(off[-1])]
         else:
             raise ValueError("unknown export item")
         _check(lib().fmm_plan_export(self._h, what, level,

@@ -52,6 +52,9 @@ def test_calls_reject_null_plan():
     assert lib.fmm_plan_set_precision(None, 0) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_schedule(None, fmm.FMM_SCHEDULE_SERIAL) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_kernel(None, fmm.FMM_KERNEL_INV_R2) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_set_near(None, fmm.FMM_NEAR_MUTUAL) == fmm.FMM_ERR_ARG
+    assert lib.fmm_plan_set_near(fake, 2) == fmm.FMM_ERR_ARG  # mode checked before the plan is touched
+    assert "near-field mode" in fmm.last_error()
     assert lib.fmm_plan_set_m2l_fold_interval(None, 4) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_set_m2l_split(None, 2) == fmm.FMM_ERR_ARG
     assert lib.fmm_plan_m2l_split(None, None) == fmm.FMM_ERR_ARG
