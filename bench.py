@@ -625,11 +625,13 @@ def summarize_counters(paths):
     print("\n".join(lines))
 
 
-def summarize_trace(path, top):
+def summarize_trace(path, top, only=None):
     """Per-(kernel, grid) dispatch count and mean / total duration from a
     rocprofv3 --kernel-trace CSV, as a markdown table of the `top` kernels by
     total time.  The grid separates launches of one kernel over different
-    workloads (a headline workload and its twin)."""
+    workloads (a headline workload and its twin).  `only`: a regular
+    expression; the overlap of queues then counts only the kernels whose
+    names match it (e.g. the evaluation kernels of serving batches)."""
     import csv
     import re
     acc = {}
@@ -648,6 +650,8 @@ def summarize_trace(path, top):
     # time during which kernels of two or more hardware queues ran at once
     spans = {}
     for r in csv.DictReader(open(path)):
+        if only and not re.search(only, r.get("Kernel_Name", "")):
+            continue
         qid = r.get("Queue_Id") or r.get("Stream_Id") or "?"
         spans.setdefault(qid, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
     ev = []
@@ -665,7 +669,8 @@ def summarize_trace(path, top):
                 both += t - last
         active[qid] = active.get(qid, 0) + d
         last = t
-    print(f"\nqueues with kernels: {len(spans)}; time with a kernel running "
+    print(f"\n{'kernels matching ' + only + ': ' if only else ''}"
+          f"queues with kernels: {len(spans)}; time with a kernel running "
           f"{busy * 1e-6:.2f} ms, with kernels of two or more queues at once "
           f"{both * 1e-6:.2f} ms")
 
@@ -689,6 +694,8 @@ def main():
                     help="write profiles/m2l_traffic.json from the two counter CSVs")
     ap.add_argument("--summarize-counters", nargs="+", metavar="CSV",
                     help="print per-kernel counter means from rocprofv3 --pmc CSVs")
+    ap.add_argument("--trace-only", metavar="REGEX",
+                    help="with --summarize-trace: count queue overlap over matching kernels only")
     ap.add_argument("--summarize-trace", metavar="CSV",
                     help="print per-kernel durations from a rocprofv3 --kernel-trace CSV")
     ap.add_argument("--requests", type=int, default=500)
@@ -704,7 +711,7 @@ def main():
         sys.exit(2)
 
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, 25)
+        summarize_trace(args.summarize_trace, 25, args.trace_only)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
