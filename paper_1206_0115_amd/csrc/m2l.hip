@@ -104,12 +104,21 @@ const StaticTables& tables() {
           S.offs.push_back(o);
         }
     // per child parity p (bit d = parity of the cell coordinate along d):
-    // offsets with t_d in [-2-p_d, 3-p_d], lexicographic in (tx, ty, tz)
+    // offsets with t_d in [-2-p_d, 3-p_d], in the order the M2L kernels take
+    // them: z outermost, x innermost, each axis in steps of two cells (-3,
+    // -1, 1, 3, 2, 0, -2) and rows in alternate directions.  The targets of
+    // a work item are same-parity cells two apart (4 x 4 x 2 of them), so an
+    // offset two cells from the last one reads mostly the same source
+    // multipoles, which are then still in L2 (30M-particle order-10 cube:
+    // M2L 4327 -> 4222 ms against the lexicographic order)
+    static const int zig[7] = {-3, -1, 1, 3, 2, 0, -2};
     for (int p = 0; p < 8; ++p) {
       int cnt = 0;
-      for (int tx = -3; tx <= 3; ++tx)
-        for (int ty = -3; ty <= 3; ++ty)
-          for (int tz = -3; tz <= 3; ++tz) {
+      for (int i0 = 0; i0 < 7; ++i0)
+        for (int i1 = 0; i1 < 7; ++i1)
+          for (int i2 = 0; i2 < 7; ++i2) {
+            const int tz = zig[i0], ty = zig[i0 % 2 ? 6 - i1 : i1];
+            const int tx = zig[(i0 * 7 + i1) % 2 ? 6 - i2 : i2];
             const int t[3] = {tx, ty, tz};
             bool ok = std::max({std::abs(tx), std::abs(ty), std::abs(tz)}) >= 2;
             for (int d = 0; d < 3; ++d) {
