@@ -274,6 +274,12 @@ struct fmm_info {
   double m2l_flops;           /* algorithmic M2L flops of one evaluation in the
                                  current mode: 2 l^6 per pair (dense) or
                                  4 l^3 r_t per pair (compressed, unpadded rank) */
+  int64_t m2l_groups;         /* 16-target groups of the tiles at their active
+                                 offsets */
+  int64_t m2l_groups_empty;   /* ... of them with no source at that offset */
+  int32_t m2l_group_skip;     /* 1 when the compressed M2L skips those groups
+                                 (at least a tenth of them, as for points on a
+                                 surface); the results are the same either way */
 };
 int fmm_plan_info(fmm_plan_t plan, struct fmm_info* out);
 

@@ -152,6 +152,7 @@ void upload_job(fmm_plan_s* p, hipStream_t s) {
   J.tgt = p->tgt;
   J.tile_src = p->tile_src;
   J.tile_act = p->tile_act;
+  J.tile_gmask = p->tile_gmask;
   J.tile_nact = p->tile_nact;
   J.kp64 = op->kpack64;
   J.kp32 = op->kpack32;
@@ -617,6 +618,9 @@ int fmm_plan_info(fmm_plan_t p, struct fmm_info* out) {
   for (int l = 0; l < fmm::kMaxHeight; ++l) out->far_pairs_level[l] = p->far_pairs_level[l];
   out->m2l_tiles = p->ntiles;
   out->m2l_active_slots = p->active_slots;
+  out->m2l_groups = p->m2l_groups;
+  out->m2l_groups_empty = p->m2l_groups_empty;
+  out->m2l_group_skip = p->m2l_gskip ? 1 : 0;
   out->device_bytes = int64_t(p->bytes);
   // algorithmic M2L flops of one evaluation in the current mode
   const double l3 = double(p->order) * p->order * p->order;

@@ -928,10 +928,10 @@ __global__ __launch_bounds__(256) void cast_kernel(const JobDev* __restrict__ jo
 void launch_m2l_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
                      hipStream_t s);
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
-                         int xs, hipStream_t s);
+                         int xs, hipStream_t s, bool gskip);
 
 void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const StepTab* tab,
-                 const CallDev* calls, int grid, hipStream_t s, int xs) {
+                 const CallDev* calls, int grid, hipStream_t s, int xs, bool gskip) {
   const unsigned g = unsigned(grid);
   switch (kind) {
     case kStepGather:
@@ -959,7 +959,7 @@ void launch_step(StepKind kind, int L, bool fp32, const JobDev* jobs, const Step
       launch_m2l_step(L, fp32, jobs, tab, grid, s);
       break;
     case kStepM2LSvd:
-      launch_m2l_svd_step(L, fp32, jobs, tab, grid, xs, s);
+      launch_m2l_svd_step(L, fp32, jobs, tab, grid, xs, s, gskip);
       break;
     case kStepL2L:
 #define L2L_CALL(LL) l2l_kernel<LL><<<g, kTransThreads, l2l_lds_bytes(LL), s>>>(jobs, tab)
@@ -1055,7 +1055,7 @@ void evaluate(fmm_plan_s* p, const double* q, double* phi, double* f, double* ph
   auto m2l_launch = [&](int tab, hipStream_t st) {
     if (p->tab_h[tab].start[1] > 0)
       launch_step(m2l_kind, L, mixed, J, p->tab_d + tab, nullptr, p->tab_h[tab].start[1], st,
-                  p->job_h.xs);
+                  p->job_h.xs, p->m2l_gskip);
   };
   auto loc_sum = [&]() {
     if (p->tab_h[kTabLocSum].start[1] > 0) {

@@ -211,6 +211,7 @@ struct fmm_plan_s {
   int* tgt = nullptr;              // global ids of targets, grouped by (level, parity)
   int* tile_src = nullptr;         // [ntiles][189][64]
   unsigned char* tile_act = nullptr;  // [ntiles][189]
+  unsigned char* tile_gmask = nullptr;  // [ntiles][189] 16-target groups with a source
   int* tile_nact = nullptr;        // [ntiles]
   std::vector<fmm::M2LTile> tiles_host;
 
@@ -219,6 +220,9 @@ struct fmm_plan_s {
   int64_t far_pairs = 0;           // M2L (target, source) cell pairs
   int64_t far_pairs_level[fmm::kMaxHeight] = {0};
   int64_t active_slots = 0;        // sum over tiles of slots with a source
+  int64_t m2l_groups = 0;          // 16-target groups at active slots
+  int64_t m2l_groups_empty = 0;    // ... of them without a source
+  bool m2l_gskip = false;          // the compressed M2L skips the empty groups
   const unsigned long long* stats_stage = nullptr;  // unread statistics (plan_stats)
   int64_t pairs_by_kid[fmm::kOffsets] = {0};  // far pairs per packed operator
 

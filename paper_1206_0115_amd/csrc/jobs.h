@@ -66,6 +66,7 @@ struct JobDev {
   const int* tgt;
   const int* tile_src;
   const unsigned char* tile_act;
+  const unsigned char* tile_gmask;  // per active slot: 16-target groups with a source
   const int* tile_nact;
   double scale[kMaxHeightJ];  // a_l^-p, the M2L level factor
   const double* kp64;
@@ -130,7 +131,9 @@ __device__ inline int step_find(const StepTab& t, int item) {
 enum StepKind { kStepGather, kStepP2M, kStepM2M, kStepCast, kStepM2L, kStepL2L, kStepL2P,
                 kStepP2P, kStepCombine, kStepM2LSvd, kStepLocSum, kStepL2PSparse,
                 kStepP2PSelf };
+// gskip: the compressed M2L skips the 16-target groups without a source at
+// an offset (plans whose tiles have many, fmm_info.m2l_group_skip).
 void launch_step(StepKind kind, int order, bool fp32, const JobDev* jobs, const StepTab* tab,
-                 const CallDev* calls, int grid, hipStream_t s, int xs = 0);
+                 const CallDev* calls, int grid, hipStream_t s, int xs = 0, bool gskip = false);
 
 }  // namespace fmm

@@ -1194,10 +1194,11 @@ __device__ inline void svd_part_range(const SvdItem& I, int nact, int& ia0, int&
 struct SvdMeta {
   int64_t off;
   int s;
-  int nr_nst;  // nr | nst << 16
+  int nr_nst;  // nr | nst << 16 | gmask << 24 (the slot's 16-target groups with a source)
 };
 constexpr size_t kSvdMetaBytes = sizeof(SvdMeta) * kSlots;
 
+template <bool GS = false>
 __device__ inline void svd_meta_fill(const SvdItem& I, int nact, SvdMeta* meta) {
   const JobDev& J = *I.J;
   int ia0, ia1;
@@ -1209,7 +1210,8 @@ __device__ inline void svd_meta_fill(const SvdItem& I, int nact, SvdMeta* meta) 
     const int kid = gld(kidp + sl);
     const int nr = gld(J.svd_rpad + kid) >> 4;
     const int nst = (gld(J.svd_rank + kid) - 16 * (nr - 1) + 3) >> 2;
-    meta[t] = SvdMeta{gld(J.svd_off + kid), sl, nr | (nst << 16)};
+    const int gm = GS ? gld(J.tile_gmask + int64_t(I.tile) * kSlots + ia0 + t) : 0xf;
+    meta[t] = SvdMeta{gld(J.svd_off + kid), sl, nr | (nst << 16) | (gm << 24)};
   }
   __syncthreads();
 }
@@ -1262,7 +1264,11 @@ __device__ inline bool svd_item(const JobDev* __restrict__ jobs, const StepTab* 
 #define FMM_M2L_SVD_WS_LOOK_WIDE_F32 2
 #endif
 
-template <typename T, int NT, int D, int NCW>
+// GS: the N-tiles whose 16 target columns have no source at an offset
+// (their multipole columns are the zero row, so their products are zero)
+// are skipped, by both roles; a wavefront-uniform test per N-tile, which
+// costs the dense cubes 9-11%, so only plans with many empty groups take it
+template <typename T, int NT, int D, int NCW, bool GS>
 __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
                                       const StepTab* __restrict__ tab, T* const lds,
                                       SvdMeta* const meta, int kg) {
@@ -1297,7 +1303,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
     const int* kidp = J.slot_kid + I.tl.parity * kSlots;
     int ia0, ia1;
     svd_part_range(I, nact, ia0, ia1);
-    svd_meta_fill(I, nact, meta);
+    svd_meta_fill<GS>(I, nact, meta);
     // each lane's source cells, one offset ahead
     int src_next[NT];
     if (ia0 < ia1) {
@@ -1312,7 +1318,11 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
       if (ia < ia1) {
         // phase 1 of offset ia: this K-group's partial X into its slab
         const SvdMeta md = meta[ia - ia0];
-        const int nr = wuni(md.nr_nst) & 0xffff;
+        const int nrs = wuni(md.nr_nst);
+        const int nr = nrs & 0xffff;
+        bool on[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) on[j] = !GS || ((nrs >> (24 + I.col0 / 16 + j)) & 1);
         const int64_t off = wuni(md.off);
         int src[NT];
 #pragma unroll
@@ -1363,7 +1373,8 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
 #pragma unroll
               for (int st = 0; st < 4; ++st)
 #pragma unroll
-                for (int j = 0; j < NT; ++j) x[j] = mfma16x16x4(av[u][st], wv[u][j][st], x[j]);
+                for (int j = 0; j < NT; ++j)
+                  if (on[j]) x[j] = mfma16x16x4(av[u][st], wv[u][j][st], x[j]);
             }
             if (!kAPre && i + 1 < nr) {
               const T* an0 = a0 + int64_t(i + 1) * KC * 256;
@@ -1438,7 +1449,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
               for (int i = 0; i < kRP; ++i)
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
-                  if (i < np) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
+                  if (i < np && on[j]) x[i][j] = mfma16x16x4(av[i][st], bv[j][st], x[i][j]);
             if (kLook > 1) {
 #pragma unroll
               for (int j = 0; j < NT; ++j) {
@@ -1495,7 +1506,7 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
   }
 }
 
-template <typename T, int MTW, int NT, int NCW>
+template <typename T, int MTW, int NT, int NCW, bool GS>
 __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
                                       const StepTab* __restrict__ tab, const T* const lds,
                                       SvdMeta* const meta, int wg) {
@@ -1526,7 +1537,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
     const int* kidp = J.slot_kid + tl.parity * kSlots;
     int ia0, ia1;
     svd_part_range(I, nact, ia0, ia1);
-    svd_meta_fill(I, nact, meta);
+    svd_meta_fill<GS>(I, nact, meta);
     // the first U fragments (rank chunk 0) of the offset consumed next,
     // loaded before the barrier that precedes it
     constexpr int kCP = F32 ? FMM_M2L_SVD_WS_CPRE_F32 : FMM_M2L_SVD_WS_CPRE_F64;
@@ -1537,7 +1548,10 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
         const int ic = ia - 1;
         const SvdMeta md = meta[ic - ia0];
         const int nrs = wuni(md.nr_nst);
-        const int nr = nrs & 0xffff, nst = nrs >> 16;  // rank chunks; K-steps of the last
+        const int nr = nrs & 0xffff, nst = (nrs >> 16) & 0xff;  // rank chunks; K-steps of the last
+        bool on[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) on[j] = !GS || ((nrs >> (24 + I.col0 / 16 + j)) & 1);
         const int64_t off = wuni(md.off);
         const T* const P = lds + (buf ^ 1) * 4 * NC * XS;
         const T* a2 = P2 + off + int64_t(mt0) * nr * 256 + lane * 4;
@@ -1545,6 +1559,8 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
           T4 bv[NT];
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
+            bv[j] = T4{0, 0, 0, 0};
+            if (!on[j]) continue;
             const int o = (16 * j + c16) * XS + 16 * c + 4 * g;
             T4 v = *reinterpret_cast<const T4*>(P + o);
 #pragma unroll
@@ -1566,7 +1582,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
               if (st >= ns) continue;
 #pragma unroll
               for (int j = 0; j < NT; ++j)
-                acc[i][j] = mfma16x16x4(av[st], bv[j][st], acc[i][j]);
+                if (on[j]) acc[i][j] = mfma16x16x4(av[st], bv[j][st], acc[i][j]);
             }
           }
         }
@@ -1629,7 +1645,7 @@ __device__ inline void svd_ws_consume(const JobDev* __restrict__ jobs,
   }
 }
 
-template <typename T, int MTW, int NT, int D, int NCW>
+template <typename T, int MTW, int NT, int D, int NCW, bool GS = false>
 __global__ __launch_bounds__(64 * (4 + NCW), svd_ws_waves(NCW, NT * int(sizeof(T) / 4))) void m2l_svd_ws_kernel(
     const JobDev* __restrict__ jobs, const StepTab* __restrict__ tab) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1641,9 +1657,9 @@ __global__ __launch_bounds__(64 * (4 + NCW), svd_ws_waves(NCW, NT * int(sizeof(T
   // the role is uniform per wavefront: a scalar branch, no lane masking
   const int wave = wuni(int(threadIdx.x >> 6));
   if (wave < 4)
-    svd_ws_produce<T, NT, D, NCW>(jobs, tab, lds, meta, wave);
+    svd_ws_produce<T, NT, D, NCW, GS>(jobs, tab, lds, meta, wave);
   else
-    svd_ws_consume<T, MTW, NT, NCW>(jobs, tab, lds, meta, wave - 4);
+    svd_ws_consume<T, MTW, NT, NCW, GS>(jobs, tab, lds, meta, wave - 4);
 }
 
 // M-tiles per wavefront for the compressed kernel: the whole output in one
@@ -1729,14 +1745,16 @@ size_t m2l_svd_lds_need(int order, bool fp32, int xs) {
 // workgroup has 4 more).
 
 template <typename T, int MTW, int NT, int NCW>
-static const void* svd_ws_ptr() {
-  return reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, MTW, NT, 0, NCW>);
+static const void* svd_ws_ptr(bool gs = false) {
+  return gs ? reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, MTW, NT, 0, NCW, true>)
+            : reinterpret_cast<const void*>(&m2l_svd_ws_kernel<T, MTW, NT, 0, NCW>);
 }
 
 // The warp-specialised kernel of a shape; staged selects the stage depth
-// FMM_M2L_SVD_WS_STAGE_* of the NWV-consumer shape.
+// FMM_M2L_SVD_WS_STAGE_* of the NWV-consumer shape, gs the form that skips
+// empty 16-target groups (whole-tile and 8-consumer shapes).
 template <typename T>
-static const void* svd_ws_fn(SvdShape sh, bool staged) {
+static const void* svd_ws_fn(SvdShape sh, bool staged, bool gs) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4);
   constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
   const int mtw = sh.mtw;
@@ -1745,22 +1763,22 @@ static const void* svd_ws_fn(SvdShape sh, bool staged) {
   if constexpr (FULL && NT < FNT) {
     if (sh.nt == FNT) {
       switch (mtw) {
-        case 1: return svd_ws_ptr<T, 1, FNT, 8>();
-        case 2: return svd_ws_ptr<T, 2, FNT, 8>();
-        case 3: return svd_ws_ptr<T, 3, FNT, 8>();
-        case 4: return svd_ws_ptr<T, 4, FNT, 8>();
-        case 5: return svd_ws_ptr<T, 5, FNT, 8>();
-        default: return svd_ws_ptr<T, kSvdFullMtw, FNT, 8>();
+        case 1: return svd_ws_ptr<T, 1, FNT, 8>(gs);
+        case 2: return svd_ws_ptr<T, 2, FNT, 8>(gs);
+        case 3: return svd_ws_ptr<T, 3, FNT, 8>(gs);
+        case 4: return svd_ws_ptr<T, 4, FNT, 8>(gs);
+        case 5: return svd_ws_ptr<T, 5, FNT, 8>(gs);
+        default: return svd_ws_ptr<T, kSvdFullMtw, FNT, 8>(gs);
       }
     }
   }
   if (sh.ncw == 8 && NW != 8) {
     switch (mtw) {
-      case 4: return svd_ws_ptr<T, 4, NT, 8>();
-      case 5: return svd_ws_ptr<T, 5, NT, 8>();
-      case 6: return svd_ws_ptr<T, 6, NT, 8>();
-      case 7: return svd_ws_ptr<T, 7, NT, 8>();
-      default: return svd_ws_ptr<T, kSvdWideMtw, NT, 8>();
+      case 4: return svd_ws_ptr<T, 4, NT, 8>(gs);
+      case 5: return svd_ws_ptr<T, 5, NT, 8>(gs);
+      case 6: return svd_ws_ptr<T, 6, NT, 8>(gs);
+      case 7: return svd_ws_ptr<T, 7, NT, 8>(gs);
+      default: return svd_ws_ptr<T, kSvdWideMtw, NT, 8>(gs);
     }
   }
 #define FMM_WS_FN(M)                                                                     \
@@ -1779,13 +1797,13 @@ static const void* svd_ws_fn(SvdShape sh, bool staged) {
 
 template <typename T, int FOLD>
 static void launch_svd_mtw(SvdShape sh, int kc, const JobDev* jobs, const StepTab* tab, int grid,
-                           size_t lds, hipStream_t s) {
+                           size_t lds, hipStream_t s, bool gs) {
   constexpr int NT = svd_nt(sizeof(T) == 4), NW = svd_nwv(sizeof(T) == 4), B = 64 * NW;
   constexpr bool WS = sizeof(T) == 4 ? FMM_M2L_SVD_WS_F32 : FMM_M2L_SVD_WS_F64;
   if (WS) {
     constexpr int D = sizeof(T) == 4 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
     const bool staged = D > 0 && (kc + 3) / 4 <= D && sh.ncw == NW && sh.nt == NT;
-    const void* f = svd_ws_fn<T>(sh, staged);
+    const void* f = svd_ws_fn<T>(sh, staged, gs);
     void* args[] = {&jobs, &tab};
     FMM_HIP_CHECK(hipLaunchKernel(f, dim3(grid), dim3(64 * (4 + sh.ncw)), args, lds, s));
     return;
@@ -1808,7 +1826,7 @@ int m2l_svd_slots(int order, bool fp32, int xs) {
   const int D = fp32 ? FMM_M2L_SVD_WS_STAGE_F32 : FMM_M2L_SVD_WS_STAGE_F64;
   const bool staged =
       D > 0 && (kc + 3) / 4 <= D && sh.ncw == svd_nwv(fp32) && sh.nt == svd_nt(fp32);
-  const void* f = fp32 ? svd_ws_fn<float>(sh, staged) : svd_ws_fn<double>(sh, staged);
+  const void* f = fp32 ? svd_ws_fn<float>(sh, staged, false) : svd_ws_fn<double>(sh, staged, false);
   int per_cu = 0, dev = 0, cus = 0;
   FMM_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, f, 64 * (4 + sh.ncw), m2l_svd_lds_bytes(xs, fp32, sh.nt)));
@@ -1818,14 +1836,14 @@ int m2l_svd_slots(int order, bool fp32, int xs) {
 }
 
 void launch_m2l_svd_step(int order, bool fp32, const JobDev* jobs, const StepTab* tab, int grid,
-                         int xs, hipStream_t s) {
+                         int xs, hipStream_t s, bool gskip) {
   const int kc = svd_kc(order);
   const SvdShape sh = m2l_svd_shape(kc, fp32, xs);
   const size_t lds = m2l_svd_lds_bytes(xs, fp32, sh.nt);
   if (fp32)
-    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(sh, kc, jobs, tab, grid, lds, s);
+    launch_svd_mtw<float, FMM_M2L_SVD_F32_FOLD_MODE>(sh, kc, jobs, tab, grid, lds, s, gskip);
   else
-    launch_svd_mtw<double, 0>(sh, kc, jobs, tab, grid, lds, s);
+    launch_svd_mtw<double, 0>(sh, kc, jobs, tab, grid, lds, s, gskip);
   FMM_HIP_CHECK(hipGetLastError());
 }
 

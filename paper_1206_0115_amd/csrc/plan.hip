@@ -488,7 +488,10 @@ __global__ __launch_bounds__(256) void parity_keys_kernel(CellLevels c, int h,
 // One workgroup of eight wavefronts per tile.  Lane j of every wavefront owns
 // target j; wavefront w looks up the source cells of the slots w, w+8, ...
 // (zero row if absent) and marks the slots with at least one source; then
-// the first thread lists the marked slots in slot order.
+// the marked slots are listed in slot order, each with the mask of its
+// 16-target groups that have a source (bit g: targets 16g .. 16g+15), and
+// the tile's groups of targets without a source at an active slot are
+// counted.
 constexpr int kTileThreads = 512;
 
 __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
@@ -496,10 +499,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
     const LevelDev* __restrict__ levels, const int64_t* __restrict__ lev_off,
     const signed char* __restrict__ slot_t,  // [8][189][3]
     int zero_row, int* __restrict__ tile_src, unsigned char* __restrict__ act,
-    int* __restrict__ nact, unsigned long long* __restrict__ pairs_level,
+    unsigned char* __restrict__ gmask, int* __restrict__ nact, unsigned long long* __restrict__ pairs_level,
     const int* __restrict__ slot_kid, unsigned long long* __restrict__ pairs_kid,
-    unsigned long long* __restrict__ active_total) {
+    unsigned long long* __restrict__ active_total,
+    unsigned long long* __restrict__ groups) {  // [0] groups at active slots, [1] empty ones
   __shared__ int npair[kSlots];
+  __shared__ unsigned char smask[kSlots];
   const int tile = blockIdx.x, j = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const M2LTile T = tiles[tile];
   const LevelDev L = levels[T.level];
@@ -530,7 +535,12 @@ __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
       if (s >= kSlots) continue;  // the same for the whole wavefront
       out[s * kTileN + j] = bs[u] >= 0 ? bs[u] + int(lev_off[T.level]) : zero_row;
       const uint64_t m = __ballot(bs[u] >= 0);
-      if (j == 0) npair[s] = __popcll(m);
+      if (j == 0) {
+        npair[s] = __popcll(m);
+        int g = 0;
+        for (int q = 0; q < 4; ++q) g |= ((m >> (16 * q)) & 0xffffu) != 0 ? 1 << q : 0;
+        smask[s] = (unsigned char)g;
+      }
     }
   }
   __syncthreads();
@@ -550,12 +560,28 @@ __global__ __launch_bounds__(kTileThreads) void tile_src_kernel(
     if (k > 0) {
       const int pos = base + __popcll(m & ((uint64_t(1) << j) - 1));
       act[int64_t(tile) * kSlots + pos] = (unsigned char)s;
+      gmask[int64_t(tile) * kSlots + pos] = smask[s];
       atomicAdd(&pairs_kid[slot_kid[T.parity * kSlots + s]], (unsigned long long)k);
     }
     // pairs of this wavefront's slots, summed across its lanes
     unsigned long long np = (unsigned long long)k;
     for (int o = 32; o > 0; o >>= 1) np += __shfl_xor(np, o, 64);
     if (j == 0 && np) atomicAdd(&pairs_level[T.level], np);
+    // groups of targets at the active slots, and those without a source
+    const int ngr = (T.count + 15) / 16;
+    unsigned long long gt = 0, ge = 0;
+    if (k > 0) {
+      gt = (unsigned long long)ngr;
+      for (int q = 0; q < ngr; ++q) ge += (smask[s] >> q) & 1 ? 0 : 1;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      gt += __shfl_xor(gt, o, 64);
+      ge += __shfl_xor(ge, o, 64);
+    }
+    if (j == 0 && gt) {
+      atomicAdd(&groups[0], gt);
+      if (ge) atomicAdd(&groups[1], ge);
+    }
     if (threadIdx.x == 0) {
       int na = 0;
       for (int w = 0; w < kSlotWaves; ++w) na += wave_active[w];
@@ -740,7 +766,7 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   // --- near lists ---
   // counters: far pairs per level, near pairs, active M2L slots, then far
   // pairs per operator
-  const size_t ncount = kMaxHeight + 2 + kOffsets;
+  const size_t ncount = kMaxHeight + 2 + kOffsets + 2;
   unsigned long long* counters =
       static_cast<unsigned long long*>(talloc(sizeof(unsigned long long) * ncount));
   FMM_HIP_CHECK(hipMemsetAsync(counters, 0, sizeof(unsigned long long) * ncount, s));
@@ -821,6 +847,7 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
       FMM_HIP_CHECK(hipMemcpyAsync(p->tiles, htiles, tbytes, hipMemcpyHostToDevice, s));
       p->tile_src = static_cast<int*>(p->alloc(sizeof(int) * size_t(p->ntiles) * kSlots * kTileN));
       p->tile_act = static_cast<unsigned char*>(p->alloc(size_t(p->ntiles) * kSlots));
+      p->tile_gmask = static_cast<unsigned char*>(p->alloc(size_t(p->ntiles) * kSlots));
       p->tile_nact = static_cast<int*>(p->alloc(sizeof(int) * p->ntiles));
       LevelDev* ld_d = static_cast<LevelDev*>(talloc(sizeof(LevelDev) * kMaxHeight));
       int64_t* off_d = static_cast<int64_t*>(talloc(sizeof(int64_t) * kMaxHeight));
@@ -834,8 +861,9 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
                                    hipMemcpyHostToDevice, s));
       tile_src_kernel<<<unsigned(p->ntiles), kTileThreads, 0, s>>>(
           p->tiles, p->tgt, ld_d, off_d, p->ops->slot_t,
-          int(p->ncell_total), p->tile_src, p->tile_act, p->tile_nact, counters,
-          p->ops->slot_kid, counters + kMaxHeight + 2, counters + kMaxHeight + 1);
+          int(p->ncell_total), p->tile_src, p->tile_act, p->tile_gmask, p->tile_nact, counters,
+          p->ops->slot_kid, counters + kMaxHeight + 2, counters + kMaxHeight + 1,
+          counters + kMaxHeight + 2 + kOffsets);
       FMM_HIP_CHECK(hipGetLastError());
     }
   }
@@ -843,9 +871,9 @@ void build_plan(fmm_plan_s* p, const double* pos, hipStream_t s) {
   // --- statistics ---
   // statistics in the staging buffer's first 4 KiB (the box and counts
   // there are no longer needed)
-  static_assert(sizeof(unsigned long long) * (kMaxHeight + 2 + kOffsets) <= 4096, "staging");
+  static_assert(sizeof(unsigned long long) * (kMaxHeight + 4 + kOffsets) <= 4096, "staging");
   unsigned long long* hc = reinterpret_cast<unsigned long long*>(stage);
-  FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(unsigned long long) * (kMaxHeight + 2 + kOffsets),
+  FMM_HIP_CHECK(hipMemcpyAsync(hc, counters, sizeof(unsigned long long) * (kMaxHeight + 4 + kOffsets),
                                hipMemcpyDeviceToHost, s));
   // read by plan_stats after the caller's next synchronisation of s (no
   // wait here: nothing the plan builds next needs them)
@@ -951,6 +979,11 @@ void plan_stats(fmm_plan_s* p) {
     p->far_pairs += int64_t(hc[l]);
   }
   p->active_slots = int64_t(hc[kMaxHeight + 1]);
+  p->m2l_groups = int64_t(hc[kMaxHeight + 2 + kOffsets]);
+  p->m2l_groups_empty = int64_t(hc[kMaxHeight + 3 + kOffsets]);
+  // plans whose tiles leave many 16-target groups without a source at an
+  // offset (points on surfaces) take the compressed M2L that skips them
+  p->m2l_gskip = p->m2l_groups > 0 && 10 * p->m2l_groups_empty >= p->m2l_groups;
   p->stats_stage = nullptr;
 }
 

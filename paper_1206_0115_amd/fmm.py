@@ -54,6 +54,9 @@ class FmmInfo(ctypes.Structure):
         ("m2l_active_slots", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
         ("m2l_flops", ctypes.c_double),
+        ("m2l_groups", ctypes.c_int64),
+        ("m2l_groups_empty", ctypes.c_int64),
+        ("m2l_group_skip", ctypes.c_int32),
     ]
 
 

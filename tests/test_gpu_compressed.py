@@ -198,3 +198,30 @@ def test_m2l_split_agrees_with_unsplit_and_is_checked():
     assert plan.m2l_split() == 1
     again = [host(t) for t in plan.evaluate(dev(q))]
     assert np.array_equal(again[0], p64) and np.array_equal(again[1], f64)
+
+
+@pytest.mark.parametrize("kind,n,h,l,skip", [("sphere", 40000, 5, 6, 1), ("sphere", 6000, 5, 4, None),
+                                             ("cube", 20000, 4, 5, 0), ("sphere", 3000, 4, 9, None)])
+def test_empty_group_skip_on_surfaces(kind, n, h, l, skip):
+    """Points on a surface leave many 16-target groups of a tile without a
+    source at an offset; such plans take the compressed M2L that skips those
+    groups (both precisions, whole-tile and 8-consumer shapes), and agree
+    with the oracle's compressed M2L as every plan does."""
+    print(f"group skip {kind} n={n} h={h} l={l}", flush=True)
+    pos, q = inputs.make(kind, n, 33)
+    plan = fmm.Plan(dev(pos), h, l, "fp64_svd", m2l_tolerance=1e-8)
+    inf = plan.info()
+    frac = inf.m2l_groups_empty / max(inf.m2l_groups, 1)
+    print(f"  empty groups {frac:.3f}", flush=True)
+    assert inf.m2l_group_skip == int(frac >= 0.1)
+    if skip is not None:
+        assert inf.m2l_group_skip == skip
+    ops, _ = oracle.compressed_unit_ops(l, 1e-8)
+    p_o, f_o = oracle.Tree(pos, h).fmm(l, q, unit_ops=ops)
+    phi, f = plan.evaluate(dev(q))
+    torch.cuda.synchronize()
+    assert max(rel(host(phi), p_o), rel(host(f), f_o)) <= SVD_TOL
+    plan.set_precision("mixed_svd")
+    pm, fm = plan.evaluate(dev(q))
+    torch.cuda.synchronize()
+    assert max(rel(host(pm), host(phi)), rel(host(fm), host(f))) <= 1e-6
