@@ -1284,6 +1284,8 @@ __device__ inline void svd_ws_produce(const JobDev* __restrict__ jobs,
   constexpr bool kXPre = F32 ? FMM_M2L_SVD_WS_XPRE_F32 : FMM_M2L_SVD_WS_XPRE_F64;
   constexpr int kLook = kWide ? FMM_M2L_SVD_WS_LOOK_WIDE_F32
                               : F32 ? FMM_M2L_SVD_WS_LOOK_F32 : FMM_M2L_SVD_WS_LOOK_F64;
+  // the chunk pipeline below holds the current chunk and at most two more
+  static_assert(kLook == 1 || kLook == 2, "one or two chunks in flight");
   const int lane = threadIdx.x & 63, g = lane >> 4, c16 = lane & 15;
   const int total = step_total(*tab);
   int buf = 0;

@@ -32,9 +32,9 @@
 namespace fmm {
 namespace {
 
-// Launches per batch: up to 47 per order present (two per tree level for
-// M2M and L2L, eight M2L forms, P2M, two L2P forms) and six more.
-constexpr int kMaxSteps = 640;
+// Launches per batch: up to 53 per order present (two per tree level for
+// M2M and L2L, fourteen M2L forms, P2M, two L2P forms) and six more.
+constexpr int kMaxSteps = 704;
 constexpr int kBuffers = 2;
 // Batching window: admitted requests wait for the planner to finish the
 // requests that arrived with them, but no longer than this, so that a burst
@@ -95,6 +95,7 @@ struct Launch {
   int order;
   bool fp32;
   int xs;  // LDS row stride of the compressed M2L
+  bool gskip;  // compressed M2L: skip the 16-target groups without a source
 };
 
 struct TableBuf {
@@ -326,7 +327,8 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
 
   std::vector<Launch> seq;
   std::string key;
-  auto add = [&](StepKind kind, int order, bool fp32, auto want, auto items, auto level) {
+  auto add = [&](StepKind kind, int order, bool fp32, auto want, auto items, auto level,
+                 bool gskip = false) {
     StepTab& t = tabs[seq.size()];
     std::memset(&t, 0, sizeof(t));
     int tot = 0, xs = 0;
@@ -345,9 +347,9 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
     if (t.njobs == 0) return;
     if (seq.size() + 1 >= size_t(kMaxSteps)) throw FmmError{FMM_ERR_HIP, "batch step table full"};
     if (kind != kStepM2LSvd) xs = 0;
-    seq.push_back({kind, order, fp32, xs});
+    seq.push_back({kind, order, fp32, xs, gskip});
     key += std::to_string(int(kind)) + ":" + std::to_string(order) + (fp32 ? "f" : "d") + ":" +
-           std::to_string(xs) + ";";
+           std::to_string(xs) + (gskip ? "g" : "") + ";";
   };
   auto all_ = [](Request*) { return true; };
   auto lvl0 = [](Request*) { return 0; };
@@ -380,20 +382,24 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
   add(kStepCast, 0, true, [&](Request* r) { return far(r) && mixed(r); },
       [](Request* r) { return int(r->plan->tab_h[kTabCast].start[1]); }, lvl0);
   // dense, then compressed by the kernel's N-tiles per item (1, 2, 4): one
-  // launch decodes every plan's items alike
+  // launch decodes every plan's items alike; the compressed plans that skip
+  // empty 16-target groups (points on surfaces) in launches of their own
   auto svd_nt = [&](Request* r) { return m2l_svd_nt(r->order, mixed(r), r->plan->job_h.xs); };
   for (int L : orders)
     for (int f32 = 0; f32 < 2; ++f32)
       for (int cmp = 0; cmp < 4; ++cmp)
-        add(cmp ? kStepM2LSvd : kStepM2L, L, f32 != 0,
-            [&](Request* r) {
-              return far(r) && r->order == L && mixed(r) == (f32 != 0) && svd(r) == (cmp != 0) &&
-                     (cmp == 0 || svd_nt(r) == 1 << (cmp - 1));
-            },
-            [](Request* r) {
-              return int(r->plan->ntiles) * r->plan->job_h.nmb * r->plan->job_h.m2l_parts;
-            },
-            lvl0);
+        for (int gs = 0; gs < (cmp ? 2 : 1); ++gs)
+          add(cmp ? kStepM2LSvd : kStepM2L, L, f32 != 0,
+              [&](Request* r) {
+                return far(r) && r->order == L && mixed(r) == (f32 != 0) &&
+                       svd(r) == (cmp != 0) &&
+                       (cmp == 0 || (svd_nt(r) == 1 << (cmp - 1) &&
+                                     r->plan->m2l_gskip == (gs != 0)));
+              },
+              [](Request* r) {
+                return int(r->plan->ntiles) * r->plan->job_h.nmb * r->plan->job_h.m2l_parts;
+              },
+              lvl0, gs != 0);
   // partial sums of plans that split their compressed M2L back into Loc, and
   // the FP32 M2L's Chebyshev-coefficient rows back to node values
   add(kStepLocSum, 0, false, [&](Request* r) { return far(r) && r->plan->job_h.m2l_parts > 1; },
@@ -427,7 +433,7 @@ void fmm_server_s::launch_on(int bi, const std::vector<Request*>& reqs) {
     FMM_HIP_CHECK(hipMemcpyAsync(B.dev, B.pinned, kTableBytes, hipMemcpyHostToDevice, exec_stream));
     for (size_t i = 0; i < seq.size(); ++i)
       launch_step(seq[i].kind, seq[i].order, seq[i].fp32, jobs_d, tabs_d + i, calls_d,
-                  persistent_grid(seq[i].kind), exec_stream, seq[i].xs);
+                  persistent_grid(seq[i].kind), exec_stream, seq[i].xs, seq[i].gskip);
     FMM_HIP_CHECK(hipStreamEndCapture(exec_stream, &g));
     hipGraphExec_t ge = nullptr;
     FMM_HIP_CHECK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
