@@ -223,6 +223,28 @@ def probe_modes(workload):
     return ["mixed_svd"] if workload in TWIN else MODES
 
 
+def run_near_probe(args):
+    """Two evaluations of the workload with each near-field form (one-sided,
+    then mutual), serial schedule, compressed mixed mode: the program that
+    rocprofv3 runs to compare the two forms' kernels."""
+    import torch
+
+    from paper_1206_0115_amd import fmm, inputs
+
+    kind, n, h, l, seed = inputs.CONFIGS[args.workload]
+    pos, q = inputs.make(kind, n, seed)
+    pos_d, q_d = torch.from_numpy(pos).cuda(), torch.from_numpy(q).cuda()
+    p = fmm.Plan(pos_d, h, l, "mixed_svd", m2l_tolerance=HEADLINE_EPS.get(args.workload))
+    p.set_schedule("serial")
+    for near in ("one_sided", "mutual"):
+        p.set_near(near)
+        for _ in range(2):
+            p.evaluate(q_d)
+        torch.cuda.synchronize()
+        print("probe", near, flush=True)
+    p.release()
+
+
 def run_traffic_probe(args):
     """One copy of COPY_BYTES (device to device) and then, for every
     precision mode of the workload, one plan + evaluation: the program that
@@ -692,6 +714,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--serve", action="store_true",
                     help="benchmark the serving loop instead (Poisson request stream)")
+    ap.add_argument("--near-probe", action="store_true",
+                    help="evaluate --workload with each near-field form (for rocprofv3)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="the program to run under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -722,6 +746,9 @@ def main():
         return
     if args.ingest_traffic:
         ingest_traffic(args)
+        return
+    if args.near_probe:
+        run_near_probe(args)
         return
     if args.traffic_probe:
         run_traffic_probe(args)
